@@ -1,0 +1,359 @@
+"""FP64 CPU oracle for gradient-descent mixed-state multislice ptychography.
+
+TEST INFRASTRUCTURE. This module is the slow, plain reference that the GPU path
+is checked against. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or run it; the product path
+(the HIP library and its Python binding) never does, and it shares no code,
+tables or constants with that path.
+
+Everything is complex128 / float64 and follows the paper (arXiv 2505.14372):
+
+* Forward model: Sec. 3 ("Algorithm description"), the unnumbered multislice
+  recursion  Psi_0,k = P_k(r - X_j),  Psi_i,k = (Psi_{i-1,k} O_{i-1}) * p(dz_{i-1}),
+  followed by the far-field intensity I(k) = sum_k |F(Psi_n,k)|^2.
+* Noise models and detector-plane gradients: Sec. 3.1 ("Noise models").
+* Gradient convention and stochastic descent over groups: Sec. 3.2
+  ("Gradient descent solver"); Adam per Kingma & Ba as cited there.
+
+Readings fixed where the paper is silent:
+
+* F is the unitary 2D DFT (numpy ``norm="ortho"``); detector in FFT order.
+* Propagator H(u) = B(u) exp(-i pi lambda dz |q|^2), q = fftfreq(N)/dx in 1/A;
+  B is a circular band limit k_y^2 + k_x^2 <= (f N / 2)^2 on signed integer
+  bins (inclusive), f = 2/3 by default, f <= 0 disables it.
+* S slices have S-1 gaps, hence S-1 propagations and none after the last slice.
+* Positions X_j = (row, col) of the window's top-left corner in object pixels;
+  n_j = floor(X_j + 0.5) is the integer window offset and d_j = X_j - n_j in
+  [-0.5, 0.5) is applied to the probe as a Fourier shift
+  R_j(u) = exp(-2 pi i (u_y d_y + u_x d_x)).
+* Poisson loss l = I - Ie - Ie (ln(I + eps) - ln(Ie + eps)) (l = I where Ie = 0),
+  whose exact derivative is the paper's Poisson detector gradient.
+* Complex gradients are dL/dRe + i dL/dIm (= 2 dL/dconj(z)), the PyTorch
+  convention; the paper's conj(dL/dz) differs by the positive factor 2.
+* Losses are sums over pixels and over the positions of the group.
+
+Parity status: every function below is pinned by tests under ``tests/``
+(brute-force DFT, unitarity, closed-form Gaussian beam, strong-phase-object
+reduction, zero loss at the truth, central finite differences, dot-product
+tests, invariants, torch.optim.Adam).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+
+LOSS_KINDS = ("amplitude", "anscombe", "poisson", "gaussian")
+
+
+@dataclass
+class Geometry:
+    """Physical parameters of one reconstruction (Sec. 3)."""
+    N: int
+    dx: float = 0.2                 # pixel size, Angstrom
+    wavelength: float = 0.019688    # Angstrom (300 keV electrons)
+    dz: Sequence[float] = field(default_factory=tuple)  # S-1 slice gaps, Angstrom
+    bandlimit: float = 2.0 / 3.0    # fraction of Nyquist; <= 0 disables
+    loss: str = "poisson"
+    eps: float = 0.0
+    sigma: float = 1.0
+
+
+# --------------------------------------------------------------------------
+# Transforms and grids
+# --------------------------------------------------------------------------
+
+def fft2u(a):
+    """Unitary 2D DFT over the last two axes, F[x](u) = N^-1 sum_r x(r) e^{-2 pi i u.r/N}."""
+    return np.fft.fft2(a, norm="ortho")
+
+
+def ifft2u(a):
+    """Inverse of fft2u (its adjoint, since F is unitary)."""
+    return np.fft.ifft2(a, norm="ortho")
+
+
+def freq(N):
+    """Spatial frequencies in cycles per pixel, FFT order (Nyquist is -0.5 for even N)."""
+    return np.fft.fftfreq(N)
+
+
+def signed_bins(N):
+    """Signed integer frequency bins k in FFT order (k = freq * N)."""
+    k = np.arange(N)
+    return np.where(k < (N + 1) // 2, k, k - N)
+
+
+def bandlimit_mask(N, frac):
+    """Circular anti-aliasing band limit applied at each propagation (Sec. 3).
+
+    B(u) = 1 iff k_y^2 + k_x^2 <= (frac * N / 2)^2 on signed integer bins,
+    inclusive; the radius is compared with a relative slack of 1e-9 so that
+    a bin lying exactly on the boundary is kept whatever the rounding of frac.
+    frac <= 0 turns the limit off.
+    """
+    if frac <= 0:
+        return np.ones((N, N), dtype=bool)
+    k = signed_bins(N).astype(np.float64)
+    k2 = k[:, None] ** 2 + k[None, :] ** 2
+    r = frac * N / 2.0
+    return k2 <= r * r * (1.0 + 1e-9)
+
+
+def propagator(N, dx, wavelength, dz, frac):
+    """Fresnel free-space propagator in Fourier space (Sec. 3, p(dz)).
+
+    H(u) = B(u) exp(-i pi lambda dz (q_y^2 + q_x^2)), q = u / dx in 1/Angstrom.
+    Convolution with p(dz) in real space is multiplication by H after the
+    forward DFT.
+    """
+    q = freq(N) / dx
+    q2 = q[:, None] ** 2 + q[None, :] ** 2
+    H = np.exp(-1j * np.pi * wavelength * dz * q2)
+    return H * bandlimit_mask(N, frac)
+
+
+def split_positions(X):
+    """Integer window offsets n = floor(X + 0.5) and subpixel remainders d = X - n."""
+    X = np.asarray(X, dtype=np.float64)
+    n = np.floor(X + 0.5)
+    return n.astype(np.int64), X - n
+
+
+def shift_ramp(N, d):
+    """Fourier ramp R(u) = exp(-2 pi i (u_y d_y + u_x d_x)): F^-1(F(P) R) is P(r - d)."""
+    u = freq(N)
+    return np.exp(-2j * np.pi * (u[:, None] * d[0] + u[None, :] * d[1]))
+
+
+# --------------------------------------------------------------------------
+# Forward model (Sec. 3)
+# --------------------------------------------------------------------------
+
+def check_window(n, N, H, W):
+    if n[0] < 0 or n[1] < 0 or n[0] + N > H or n[1] + N > W:
+        raise IndexError(f"window at {tuple(n)} of size {N} leaves the {H}x{W} object")
+
+
+def forward_position(probe, obj, X, geom: Geometry, props=None):
+    """Multislice forward model for one probe position, every mode.
+
+    Returns (psi, far, I): psi[i] is the entry wave of slice i for all modes
+    (shape [S][M][N][N]), far the detector-plane waves F(phi_{S-1}) per mode,
+    I = sum_m |far_m|^2.
+    """
+    N = geom.N
+    S = obj.shape[0]
+    n, d = split_positions(X)
+    check_window(n, N, obj.shape[1], obj.shape[2])
+    if props is None:
+        props = [propagator(N, geom.dx, geom.wavelength, geom.dz[i], geom.bandlimit)
+                 for i in range(S - 1)]
+    R = shift_ramp(N, d)
+    psi = [ifft2u(fft2u(probe) * R)]                      # Psi_0 = P(r - X_j)
+    for i in range(S):
+        patch = obj[i, n[0]:n[0] + N, n[1]:n[1] + N]
+        phi = psi[i] * patch                               # transmission
+        if i < S - 1:
+            psi.append(ifft2u(props[i] * fft2u(phi)))      # Fresnel step
+    far = fft2u(phi)                                       # far field
+    I = np.sum(np.abs(far) ** 2, axis=0)                   # incoherent mode sum
+    return np.stack(psi), far, I
+
+
+def forward(probe, obj, positions, batch_idx, geom: Geometry):
+    """Intensities [B][N][N] for the positions positions[batch_idx]."""
+    probe = np.asarray(probe, dtype=np.complex128)
+    obj = np.asarray(obj, dtype=np.complex128)
+    S = obj.shape[0]
+    props = [propagator(geom.N, geom.dx, geom.wavelength, geom.dz[i], geom.bandlimit)
+             for i in range(S - 1)]
+    return np.stack([forward_position(probe, obj, positions[j], geom, props)[2]
+                     for j in batch_idx])
+
+
+# --------------------------------------------------------------------------
+# Noise models (Sec. 3.1)
+# --------------------------------------------------------------------------
+
+def loss_and_weight(I, Ie, kind, eps=0.0, sigma=1.0):
+    """Per-pixel loss l(I, Ie) and detector weight w = 2 dl/dI.
+
+    amplitude / anscombe (c = 0 / 3/8): l = 1/2 (sqrt(I+c) - sqrt(Ie+c))^2 and the
+        regularised weight w = 1 - sqrt(Ie+c) / (eps + sqrt(I+c)) (w := 0 where
+        eps + sqrt(I+c) = 0, a pixel where every mode's far field vanishes);
+    poisson: l = I - Ie - Ie (ln(I+eps) - ln(Ie+eps)), l := I where Ie = 0,
+        w = 2 (1 - Ie / (I + eps));
+    gaussian: l = (I - Ie)^2 / (2 sigma^2), w = 2 (I - Ie) / sigma^2.
+
+    The gradient of the loss with respect to a detector-plane wave Psi_m is
+    then w * Psi_m (PyTorch convention), the paper's detector gradients up to
+    a positive factor.
+    """
+    I = np.asarray(I, dtype=np.float64)
+    Ie = np.asarray(Ie, dtype=np.float64)
+    if kind in ("amplitude", "anscombe"):
+        c = 0.0 if kind == "amplitude" else 3.0 / 8.0
+        a = np.sqrt(I + c)
+        ae = np.sqrt(Ie + c)
+        ell = 0.5 * (a - ae) ** 2
+        den = eps + a
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w = np.where(den > 0, 1.0 - ae / np.where(den > 0, den, 1.0), 0.0)
+        return ell, w
+    if kind == "poisson":
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ell = np.where(Ie > 0,
+                           I - Ie - Ie * (np.log(I + eps) - np.log(Ie + eps)),
+                           I)
+            w = 2.0 * (1.0 - np.where(Ie > 0, Ie / (I + eps), 0.0))
+        return ell, w
+    if kind == "gaussian":
+        return (I - Ie) ** 2 / (2.0 * sigma ** 2), 2.0 * (I - Ie) / sigma ** 2
+    raise ValueError(kind)
+
+
+# --------------------------------------------------------------------------
+# Exact adjoint (vector-Jacobian product, Sec. 3.2)
+# --------------------------------------------------------------------------
+
+def loss_and_grad(probe, obj, positions, patterns, batch_idx, geom: Geometry):
+    """Loss of one group and its exact gradients.
+
+    Returns a dict with
+      loss       total loss (sum over positions and pixels),
+      loss_pos   per-position losses [B],
+      I          modelled intensities [B][N][N],
+      g_object   dL/dRe O + i dL/dIm O, shape of obj,
+      g_probe    same for the probe modes,
+      g_pos      dL/dX per batch entry [B][2].
+    """
+    probe = np.asarray(probe, dtype=np.complex128)
+    obj = np.asarray(obj, dtype=np.complex128)
+    N = geom.N
+    M = probe.shape[0]
+    S = obj.shape[0]
+    props = [propagator(N, geom.dx, geom.wavelength, geom.dz[i], geom.bandlimit)
+             for i in range(S - 1)]
+    probe_hat = fft2u(probe)
+    u = freq(N)
+    g_obj = np.zeros_like(obj)
+    g_probe_hat = np.zeros_like(probe)
+    g_pos = np.zeros((len(batch_idx), 2))
+    loss_pos = np.zeros(len(batch_idx))
+    Is = np.zeros((len(batch_idx), N, N))
+    for b, j in enumerate(batch_idx):
+        n, d = split_positions(positions[j])
+        psi, far, I = forward_position(probe, obj, positions[j], geom, props)
+        Is[b] = I
+        ell, w = loss_and_weight(I, patterns[j], geom.loss, geom.eps, geom.sigma)
+        loss_pos[b] = ell.sum()
+        # gradient with respect to the last exit wave phi_{S-1}, every mode
+        g = ifft2u(w * far)
+        for i in range(S - 1, -1, -1):
+            patch = obj[i, n[0]:n[0] + N, n[1]:n[1] + N]
+            # phi_i = psi_i * O_i: both factors receive conj(other) * g
+            g_obj[i, n[0]:n[0] + N, n[1]:n[1] + N] += np.sum(np.conj(psi[i]) * g, axis=0)
+            h = np.conj(patch) * g                          # gradient wrt psi_i
+            if i > 0:
+                # psi_i = F^-1 H F phi_{i-1}  ->  adjoint F^-1 conj(H) F
+                g = ifft2u(np.conj(props[i - 1]) * fft2u(h))
+        # psi_0 = F^-1 (P_hat R): gradient wrt the shifted spectrum A = P_hat R
+        h_hat = fft2u(h)
+        R = shift_ramp(N, d)
+        g_probe_hat += h_hat * np.conj(R)
+        # dA/dd_a = A * (-2 pi i u_a); dL/dd_a = Re sum conj(grad_A) dA/dd_a
+        A = probe_hat * R
+        dAy = A * (-2j * np.pi * u[:, None])
+        dAx = A * (-2j * np.pi * u[None, :])
+        g_pos[b, 0] = np.real(np.sum(np.conj(h_hat) * dAy))
+        g_pos[b, 1] = np.real(np.sum(np.conj(h_hat) * dAx))
+    g_probe = ifft2u(g_probe_hat)                           # P_hat = F P
+    return dict(loss=float(loss_pos.sum()), loss_pos=loss_pos, I=Is,
+                g_object=g_obj, g_probe=g_probe, g_pos=g_pos)
+
+
+def total_loss(probe, obj, positions, patterns, batch_idx, geom: Geometry):
+    """Loss only (used by finite-difference pins)."""
+    I = forward(probe, obj, positions, batch_idx, geom)
+    ell, _ = loss_and_weight(I, np.asarray(patterns)[list(batch_idx)], geom.loss,
+                             geom.eps, geom.sigma)
+    return float(ell.sum())
+
+
+# --------------------------------------------------------------------------
+# Optimiser step (Sec. 3.2: SGD and Adam on each variable)
+# --------------------------------------------------------------------------
+
+def _as_real(a):
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        return np.stack([a.real, a.imag], axis=-1)
+    return np.asarray(a, dtype=np.float64)
+
+
+def _from_real(r, like):
+    if np.iscomplexobj(like):
+        return r[..., 0] + 1j * r[..., 1]
+    return r
+
+
+def sgd_update(theta, grad, lr):
+    """theta <- theta - lr * grad."""
+    return theta - lr * grad
+
+
+def adam_update(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba) on the real components of theta, step t >= 1.
+
+    m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+    theta <- theta - (lr / (1-b1^t)) m / (sqrt(v) / sqrt(1-b2^t) + eps)
+    (the bias-corrected form with eps added after the v correction).
+    m and v are real arrays shaped like the real view of theta.
+    Returns (theta, m, v).
+    """
+    g = _as_real(grad)
+    th = _as_real(theta)
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    bc1 = 1.0 - beta1 ** t
+    bc2 = 1.0 - beta2 ** t
+    th = th - (lr / bc1) * m / (np.sqrt(v) / np.sqrt(bc2) + eps)
+    return _from_real(th, theta), m, v
+
+
+def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
+    """One gradient step on one group (Sec. 2.2 engine loop, Sec. 3.2 solver).
+
+    state: dict with probe, object, positions and, for Adam, m_/v_ moments
+    per variable and the step counter t (number of steps already taken).
+    opt: dict(kind='sgd'|'adam', lr_object, lr_probe, lr_pos, beta1, beta2, eps).
+    Gradients of positions outside the group are zero; the update is applied
+    to every element, as a dense optimiser on the whole variable does.
+    Returns (new_state, loss).
+    """
+    r = loss_and_grad(state["probe"], state["object"], state["positions"],
+                      patterns, batch_idx, geom)
+    g_pos = np.zeros_like(np.asarray(state["positions"], dtype=np.float64))
+    for b, j in enumerate(batch_idx):
+        g_pos[j] += r["g_pos"][b]
+    grads = dict(object=r["g_object"], probe=r["g_probe"], positions=g_pos)
+    lrs = dict(object=opt["lr_object"], probe=opt["lr_probe"], positions=opt["lr_pos"])
+    new = dict(state)
+    if opt["kind"] == "sgd":
+        for k in grads:
+            new[k] = sgd_update(np.asarray(state[k]), grads[k], lrs[k])
+        return new, r["loss"]
+    t = state.get("t", 0) + 1
+    for k in grads:
+        m = state.get("m_" + k)
+        v = state.get("v_" + k)
+        if m is None:
+            m = np.zeros_like(_as_real(state[k]))
+            v = np.zeros_like(m)
+        new[k], new["m_" + k], new["v_" + k] = adam_update(
+            np.asarray(state[k]), grads[k], m, v, t, lrs[k],
+            opt.get("beta1", 0.9), opt.get("beta2", 0.999), opt.get("eps", 1e-8))
+    new["t"] = t
+    return new, r["loss"]
