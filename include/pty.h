@@ -1,0 +1,221 @@
+/*
+ * pty.h -- C ABI of the MI355X (gfx950) hot path of gradient-descent
+ * mixed-state multislice ptychography (arXiv 2505.14372).
+ *
+ * What the library computes, per group ("batch") of probe positions:
+ *   - the multislice forward model of Sec. 3: each probe mode is shifted to
+ *     the position (Fourier subpixel shift, integer window offset), multiplied
+ *     by each object slice's transmission function and Fresnel-propagated
+ *     between slices (band-limited), then taken to the far field; intensities
+ *     of the incoherent modes are summed;
+ *   - the loss of one of the noise models of Sec. 3.1 against measured
+ *     patterns (sum over pixels and positions);
+ *   - the exact vector-Jacobian product of Sec. 3.2 back to the object, the
+ *     probe modes and the positions, with overlapping object gradients
+ *     scatter-added;
+ *   - one optimiser step (SGD or Adam, Sec. 3.2) on all three variables.
+ *
+ * Conventions (fixed readings of the paper):
+ *   - complex numbers are interleaved float32 pairs (pty_c64);
+ *   - the 2D DFT is unitary; detector patterns are in FFT order (DC at [0,0]);
+ *   - the propagator for gap dz is H(u) = B(u) exp(-i pi lambda dz |q|^2),
+ *     q = fftfreq(N) / dx, B the circular band limit
+ *     k_y^2 + k_x^2 <= (bandlimit * N / 2)^2 on signed integer bins
+ *     (inclusive; bandlimit <= 0 disables it);
+ *   - S slices have S-1 gaps: S-1 propagations, none after the last slice;
+ *   - position X_j = (row, col) of the window's top-left corner in object
+ *     pixels; the window starts at n_j = floor(X_j + 0.5) and the probe is
+ *     shifted by d_j = X_j - n_j in [-0.5, 0.5) with the ramp
+ *     exp(-2 pi i (u_y d_y + u_x d_x)), u = fftfreq(N);
+ *   - complex gradients are dL/dRe + i dL/dIm;
+ *   - Poisson loss l = I - Ie - Ie (ln(I+eps) - ln(Ie+eps)) (l = I if Ie = 0),
+ *     amplitude/Anscombe l = (sqrt(I+c) - sqrt(Ie+c))^2 / 2 with the
+ *     eps-regularised weight 1 - sqrt(Ie+c)/(eps + sqrt(I+c)),
+ *     Gaussian l = (I - Ie)^2 / (2 sigma^2).
+ *
+ * Memory and ownership:
+ *   - every array argument is a DEVICE pointer to C-contiguous memory owned
+ *     by the caller, except pty_geometry.dz (host, copied at create);
+ *   - the library allocates device memory only in pty_create /
+ *     pty_group_create (workspace sized for max_batch), never in a call;
+ *   - calls are asynchronous and stream-ordered on the given hipStream_t
+ *     (passed as void*; NULL = the null stream); scalar results (loss) are
+ *     written to device doubles;
+ *   - gradient outputs are overwritten unless PTY_ACCUMULATE is set; a NULL
+ *     gradient pointer skips that output.
+ *
+ * Errors: every entry point returns a pty_status; nothing throws across the
+ * ABI. Host-side validation (shapes, sizes, NULL) happens at call time and
+ * leaves device state untouched. Conditions only the device can see (a
+ * window leaving the object, a non-finite loss or weight) set sticky flags
+ * that pty_check() reads (it synchronises the stream) and clears; windows
+ * that leave the object are skipped (they contribute nothing).
+ * pty_last_error() describes the last failure of a context.
+ */
+#ifndef PTY_H
+#define PTY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } pty_c64;
+
+typedef enum {
+  PTY_OK = 0,
+  PTY_EINVAL = 1,        /* bad argument (NULL, size, shape) */
+  PTY_EBOUNDS = 2,       /* a probe window left the object (device flag) */
+  PTY_EUNSUPPORTED = 3,  /* N not in {64, 128, 192, 256}, or a limit exceeded */
+  PTY_ENOMEM = 4,        /* device allocation failed at create */
+  PTY_EHIP = 5,          /* a HIP runtime call failed */
+  PTY_ENONFINITE = 6,    /* non-finite loss or detector weight (device flag) */
+  PTY_ESTATE = 7         /* pty_backward without a preceding pty_forward_save */
+} pty_status;
+
+/* Noise models of Sec. 3.1. */
+typedef enum {
+  PTY_LOSS_AMPLITUDE = 0,   /* c = 0 */
+  PTY_LOSS_ANSCOMBE = 1,    /* c = 3/8 */
+  PTY_LOSS_POISSON = 2,
+  PTY_LOSS_GAUSSIAN = 3
+} pty_loss_kind;
+
+#define PTY_ACCUMULATE 1u   /* add into gradient outputs instead of overwriting */
+
+/* One reconstruction's geometry (the unknowns of Sec. 3: probe modes, sliced
+ * object with gaps dz, positions). */
+typedef struct {
+  int32_t N;            /* window / probe / pattern side: 64, 128, 192 or 256 */
+  int32_t n_modes;      /* M >= 1 incoherent probe modes */
+  int32_t n_slices;     /* S >= 1 object slices */
+  int32_t obj_h, obj_w; /* object slice size, >= N */
+  int32_t n_positions;  /* J, rows of the positions / patterns arrays */
+  double dx;            /* pixel size (Angstrom) */
+  double wavelength;    /* Angstrom */
+  const double* dz;     /* host array [n_slices-1] of gaps (Angstrom); copied */
+  double bandlimit;     /* band-limit radius as a fraction of Nyquist; <= 0: none */
+  int32_t loss;         /* pty_loss_kind */
+  double eps;           /* noise-model epsilon (Sec. 3.1) */
+  double sigma;         /* Gaussian noise standard deviation */
+} pty_geometry;
+
+typedef struct pty_ctx pty_ctx;
+
+/* Create a context for one geometry with workspace for groups of up to
+ * max_batch positions. checkpoint_every = 1 stores every slice's entry wave
+ * during the forward pass; k > 1 stores every k-th and recomputes the others
+ * segment by segment in the backward pass; 0 picks 1 if the workspace fits
+ * in hbm_budget bytes (0 = no limit), else the smallest k that fits.
+ * Builds the propagator tables on the device. */
+pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every,
+                      size_t hbm_budget, pty_ctx** out);
+
+/* Device bytes pty_create would allocate for these arguments. */
+pty_status pty_workspace_bytes(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every,
+                               size_t* bytes);
+
+/* Checkpoint interval chosen at create (1 = store all). */
+int32_t pty_checkpoint_every(const pty_ctx* ctx);
+
+/* Forward model (Sec. 3) for the positions batch_idx[0..batch) (device int32,
+ * values in [0, J)). probe [M][N][N], object [S][H][W], positions [J][2]
+ * float32 (row, col). Writes intensities [batch][N][N] (FFT order) if not
+ * NULL and, if patterns [J][N][N] and loss are both given, the group loss
+ * (one device double). */
+pty_status pty_forward(pty_ctx* ctx, void* stream, const pty_c64* probe, const pty_c64* object,
+                       const float* positions, const int32_t* batch_idx, int32_t batch,
+                       const float* patterns, float* intensities, double* loss);
+
+/* Loss of the group and its gradients (Sec. 3.1-3.2): g_object [S][H][W],
+ * g_probe [M][N][N], g_pos [batch][2] (per batch entry, dL/dX). loss may be
+ * NULL. flags: PTY_ACCUMULATE. */
+pty_status pty_loss_and_grad(pty_ctx* ctx, void* stream, const pty_c64* probe,
+                             const pty_c64* object, const float* positions, const float* patterns,
+                             const int32_t* batch_idx, int32_t batch, double* loss,
+                             pty_c64* g_object, pty_c64* g_probe, float* g_pos, uint32_t flags);
+
+/* Split form of pty_loss_and_grad for automatic differentiation: the forward
+ * pass stores the per-slice entry waves (checkpoints) and the detector-plane
+ * gradient seed in the context ("tape"); pty_backward runs the adjoint from
+ * that tape and scales every gradient by grad_scale. The probe, object,
+ * positions and batch_idx buffers must stay unchanged until pty_backward;
+ * any other call on the context invalidates the tape (PTY_ESTATE). */
+pty_status pty_forward_save(pty_ctx* ctx, void* stream, const pty_c64* probe,
+                            const pty_c64* object, const float* positions, const float* patterns,
+                            const int32_t* batch_idx, int32_t batch, float* intensities,
+                            double* loss);
+pty_status pty_backward(pty_ctx* ctx, void* stream, double grad_scale, pty_c64* g_object,
+                        pty_c64* g_probe, float* g_pos, uint32_t flags);
+
+/* Resident reconstruction state (device pointers). Moments (m_*, v_*) are
+ * float32 arrays with the real-component shape of their variable; they are
+ * only used by Adam. step counts completed Adam steps (host-side). */
+typedef struct {
+  pty_c64* probe;      /* [M][N][N] */
+  pty_c64* object;     /* [S][H][W] */
+  float* positions;    /* [J][2] */
+  float* m_probe; float* v_probe;     /* [M][N][N][2] */
+  float* m_object; float* v_object;   /* [S][H][W][2] */
+  float* m_pos; float* v_pos;         /* [J][2] */
+  int64_t step;
+} pty_state;
+
+typedef enum { PTY_OPT_SGD = 0, PTY_OPT_ADAM = 1 } pty_opt_kind;
+
+typedef struct {
+  int32_t kind;          /* pty_opt_kind */
+  double lr_object, lr_probe, lr_pos;   /* 0 freezes a variable */
+  double beta1, beta2, eps;             /* Adam */
+} pty_optim;
+
+/* One gradient step on one group (Sec. 2.2 engine loop, Sec. 3.2 solver):
+ * loss and gradients of the group, then SGD (theta -= lr g) or Adam (per real
+ * component, bias-corrected, eps added to sqrt(v)/sqrt(1-beta2^t)) applied
+ * densely to object, probe and positions (positions outside the group get a
+ * zero gradient). Increments st->step for Adam. loss may be NULL. */
+pty_status pty_reconstruct_step(pty_ctx* ctx, void* stream, pty_state* st, const float* patterns,
+                                const int32_t* batch_idx, int32_t batch, const pty_optim* opt,
+                                double* loss);
+
+/* Synchronise the stream, return PTY_EBOUNDS / PTY_ENONFINITE if a device
+ * flag was raised since the last check (then clear it), else PTY_OK. */
+pty_status pty_check(pty_ctx* ctx, void* stream);
+
+const char* pty_last_error(const pty_ctx* ctx);
+void pty_destroy(pty_ctx* ctx);
+
+/* ---- grouped launches (continuous-batching server) ---------------------
+ * A pty_group owns a workspace for one window size N and runs one step over
+ * position chunks of several reconstructions (contexts with that N, any M,
+ * S, object size, loss) in shared kernel launches. Entry waves are stored for
+ * every slice (no recompute) in the group's workspace. */
+typedef struct pty_group pty_group;
+
+typedef struct {
+  pty_ctx* ctx;               /* geometry of this reconstruction (same N) */
+  pty_state* state;           /* its resident state */
+  const float* patterns;      /* [J][N][N] device */
+  const int32_t* batch_idx;   /* device [batch] */
+  int32_t batch;
+  const pty_optim* opt;       /* host */
+  double* loss;               /* device double or NULL */
+} pty_group_item;
+
+/* max_tiles bounds sum(batch * M) over the items of one call; max_ckpt_tiles
+ * bounds sum(batch * M * S). */
+pty_status pty_group_create(int32_t N, int32_t max_items, int32_t max_tiles, int64_t max_ckpt_tiles,
+                            pty_group** out);
+pty_status pty_group_workspace_bytes(int32_t N, int32_t max_items, int32_t max_tiles,
+                                     int64_t max_ckpt_tiles, size_t* bytes);
+pty_status pty_group_reconstruct_step(pty_group* grp, void* stream, const pty_group_item* items,
+                                      int32_t n_items);
+const char* pty_group_last_error(const pty_group* grp);
+void pty_group_destroy(pty_group* grp);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTY_H */

@@ -183,8 +183,9 @@ def loss_and_weight(I, Ie, kind, eps=0.0, sigma=1.0):
     amplitude / anscombe (c = 0 / 3/8): l = 1/2 (sqrt(I+c) - sqrt(Ie+c))^2 and the
         regularised weight w = 1 - sqrt(Ie+c) / (eps + sqrt(I+c)) (w := 0 where
         eps + sqrt(I+c) = 0, a pixel where every mode's far field vanishes);
-    poisson: l = I - Ie - Ie (ln(I+eps) - ln(Ie+eps)), l := I where Ie = 0,
-        w = 2 (1 - Ie / (I + eps));
+    poisson: l = I - Ie - Ie (ln(I+eps) - ln(Ie+eps)), l := I where Ie = 0 (the
+        limit Ie ln Ie -> 0 of the Stirling form), w = 2 (1 - Ie / (I + eps)); negative
+        or NaN counts give a non-finite loss;
     gaussian: l = (I - Ie)^2 / (2 sigma^2), w = 2 (I - Ie) / sigma^2.
 
     The gradient of the loss with respect to a detector-plane wave Psi_m is
@@ -204,10 +205,9 @@ def loss_and_weight(I, Ie, kind, eps=0.0, sigma=1.0):
         return ell, w
     if kind == "poisson":
         with np.errstate(divide="ignore", invalid="ignore"):
-            ell = np.where(Ie > 0,
-                           I - Ie - Ie * (np.log(I + eps) - np.log(Ie + eps)),
-                           I)
-            w = 2.0 * (1.0 - np.where(Ie > 0, Ie / (I + eps), 0.0))
+            ell = np.where(Ie == 0, I,
+                           I - Ie - Ie * (np.log(I + eps) - np.log(Ie + eps)))
+            w = 2.0 * (1.0 - np.where(Ie == 0, 0.0, Ie / (I + eps)))
         return ell, w
     if kind == "gaussian":
         return (I - Ie) ** 2 / (2.0 * sigma ** 2), 2.0 * (I - Ie) / sigma ** 2

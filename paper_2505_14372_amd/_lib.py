@@ -1,0 +1,104 @@
+"""ctypes declarations of the libpty C ABI (include/pty.h).
+
+Loading fails loudly when the in-tree library is missing: there is no other
+implementation of these entry points in this package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpty.so")
+
+PTY_OK, PTY_EINVAL, PTY_EBOUNDS, PTY_EUNSUPPORTED, PTY_ENOMEM, PTY_EHIP, PTY_ENONFINITE, PTY_ESTATE = range(8)
+STATUS_NAMES = {0: "PTY_OK", 1: "PTY_EINVAL", 2: "PTY_EBOUNDS", 3: "PTY_EUNSUPPORTED", 4: "PTY_ENOMEM",
+                5: "PTY_EHIP", 6: "PTY_ENONFINITE", 7: "PTY_ESTATE"}
+LOSS_IDS = {"amplitude": 0, "anscombe": 1, "poisson": 2, "gaussian": 3}
+OPT_SGD, OPT_ADAM = 0, 1
+PTY_ACCUMULATE = 1
+
+# every exported symbol of include/pty.h
+EXPORTS = (
+    "pty_create", "pty_workspace_bytes", "pty_checkpoint_every", "pty_forward", "pty_loss_and_grad",
+    "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
+    "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
+    "pty_group_last_error", "pty_group_destroy",
+)
+
+
+class Geometry(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32), ("n_modes", C.c_int32), ("n_slices", C.c_int32),
+        ("obj_h", C.c_int32), ("obj_w", C.c_int32), ("n_positions", C.c_int32),
+        ("dx", C.c_double), ("wavelength", C.c_double), ("dz", C.POINTER(C.c_double)),
+        ("bandlimit", C.c_double), ("loss", C.c_int32), ("eps", C.c_double), ("sigma", C.c_double),
+    ]
+
+
+class State(C.Structure):
+    _fields_ = [
+        ("probe", C.c_void_p), ("object", C.c_void_p), ("positions", C.c_void_p),
+        ("m_probe", C.c_void_p), ("v_probe", C.c_void_p),
+        ("m_object", C.c_void_p), ("v_object", C.c_void_p),
+        ("m_pos", C.c_void_p), ("v_pos", C.c_void_p),
+        ("step", C.c_int64),
+    ]
+
+
+class Optim(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("lr_object", C.c_double), ("lr_probe", C.c_double), ("lr_pos", C.c_double),
+        ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+    ]
+
+
+class GroupItem(C.Structure):
+    _fields_ = [
+        ("ctx", C.c_void_p), ("state", C.POINTER(State)), ("patterns", C.c_void_p),
+        ("batch_idx", C.c_void_p), ("batch", C.c_int32), ("opt", C.POINTER(Optim)), ("loss", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libpty.so (built in-tree by build_lib); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2505_14372_amd.build_lib`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64, u32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint32, C.c_size_t
+    sig = {
+        "pty_create": ([C.POINTER(Geometry), i32, i32, sz, C.POINTER(vp)], i32),
+        "pty_workspace_bytes": ([C.POINTER(Geometry), i32, i32, C.POINTER(sz)], i32),
+        "pty_checkpoint_every": ([vp], i32),
+        "pty_forward": ([vp, vp, vp, vp, vp, vp, i32, vp, vp, vp], i32),
+        "pty_loss_and_grad": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, u32], i32),
+        "pty_forward_save": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp], i32),
+        "pty_backward": ([vp, vp, f64, vp, vp, vp, u32], i32),
+        "pty_reconstruct_step": ([vp, vp, C.POINTER(State), vp, vp, i32, C.POINTER(Optim), vp], i32),
+        "pty_check": ([vp, vp], i32),
+        "pty_last_error": ([vp], C.c_char_p),
+        "pty_destroy": ([vp], None),
+        "pty_group_create": ([i32, i32, i32, i64, C.POINTER(vp)], i32),
+        "pty_group_workspace_bytes": ([i32, i32, i32, i64, C.POINTER(sz)], i32),
+        "pty_group_reconstruct_step": ([vp, vp, C.POINTER(GroupItem), i32], i32),
+        "pty_group_last_error": ([vp], C.c_char_p),
+        "pty_group_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class PtyError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status

@@ -1,0 +1,265 @@
+"""Python binding of libpty: torch tensors in, C ABI calls out.
+
+Every step of the hot path runs in the HIP library; this module only checks
+shapes and dtypes, hands device pointers and the current HIP stream to the
+C entry points, and raises PtyError on a non-OK status.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import PtyError
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _need(t, dtype, shape, name):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+@dataclass
+class Optimizer:
+    """SGD or Adam settings of pty_reconstruct_step (learning rate 0 freezes a variable)."""
+    kind: str = "adam"
+    lr_object: float = 1e-3
+    lr_probe: float = 1e-3
+    lr_pos: float = 0.0
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def c(self):
+        return _lib.Optim(_lib.OPT_ADAM if self.kind == "adam" else _lib.OPT_SGD, self.lr_object, self.lr_probe,
+                          self.lr_pos, self.beta1, self.beta2, self.eps)
+
+
+class ReconState:
+    """Resident reconstruction state (probe, object, positions, Adam moments)."""
+
+    def __init__(self, probe: torch.Tensor, obj: torch.Tensor, positions: torch.Tensor, adam: bool = True):
+        self.probe = probe.contiguous()
+        self.object = obj.contiguous()
+        self.positions = positions.contiguous()
+        z = lambda t: torch.zeros(torch.view_as_real(t).shape if t.is_complex() else t.shape,  # noqa: E731
+                                  dtype=torch.float32, device=t.device)
+        self.m_probe = z(self.probe) if adam else None
+        self.v_probe = z(self.probe) if adam else None
+        self.m_object = z(self.object) if adam else None
+        self.v_object = z(self.object) if adam else None
+        self.m_pos = z(self.positions) if adam else None
+        self.v_pos = z(self.positions) if adam else None
+        self.step = 0
+
+    def c(self):
+        return _lib.State(_ptr(self.probe), _ptr(self.object), _ptr(self.positions), _ptr(self.m_probe),
+                          _ptr(self.v_probe), _ptr(self.m_object), _ptr(self.v_object), _ptr(self.m_pos),
+                          _ptr(self.v_pos), self.step)
+
+    def nbytes(self):
+        return sum(t.numel() * t.element_size() for t in (self.probe, self.object, self.positions, self.m_probe,
+                                                          self.v_probe, self.m_object, self.v_object, self.m_pos,
+                                                          self.v_pos) if t is not None)
+
+
+def _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma):
+    dz = list(dz) if dz is not None else []
+    if len(dz) != max(S - 1, 0):
+        raise ValueError(f"need {S - 1} slice gaps, got {len(dz)}")
+    arr = (C.c_double * max(len(dz), 1))(*dz) if dz else None
+    g = _lib.Geometry(N, M, S, H, W, J, dx, wavelength, C.cast(arr, C.POINTER(C.c_double)) if arr else None,
+                      bandlimit, _lib.LOSS_IDS[loss], eps, sigma)
+    return g, arr
+
+
+def workspace_bytes(N, M, S, H, W, J, max_batch, checkpoint_every=1, dx=0.2, wavelength=0.019688,
+                    dz=None, bandlimit=2 / 3, loss="poisson", eps=0.0, sigma=1.0):
+    lib = _lib.load()
+    g, _keep = _geometry(N, M, S, H, W, J, dx, wavelength, dz if dz is not None else [1.0] * (S - 1),
+                         bandlimit, loss, eps, sigma)
+    out = C.c_size_t()
+    st = lib.pty_workspace_bytes(C.byref(g), max_batch, checkpoint_every, C.byref(out))
+    if st:
+        raise PtyError(st, "pty_workspace_bytes")
+    return out.value
+
+
+class Problem:
+    """One reconstruction geometry bound to a libpty context (pty_create)."""
+
+    def __init__(self, N: int, M: int, S: int, H: int, W: int, J: int, dz: Sequence[float] = (),
+                 dx: float = 0.2, wavelength: float = 0.019688, bandlimit: float = 2 / 3,
+                 loss: str = "poisson", eps: float = 0.0, sigma: float = 1.0, max_batch: int = 256,
+                 checkpoint_every: int = 1, hbm_budget: int = 0):
+        self.lib = _lib.load()
+        self.N, self.M, self.S, self.H, self.W, self.J = N, M, S, H, W, J
+        self.loss_kind = loss
+        self.max_batch = max_batch
+        g, self._dz_keep = _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma)
+        self._g = g
+        ctx = C.c_void_p()
+        st = self.lib.pty_create(C.byref(g), max_batch, checkpoint_every, hbm_budget, C.byref(ctx))
+        if st:
+            raise PtyError(st, "pty_create")
+        self.ctx = ctx
+        self.checkpoint_every = self.lib.pty_checkpoint_every(ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pty_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st, what):
+        msg = self.lib.pty_last_error(self.ctx).decode() if self.ctx else ""
+        raise PtyError(st, f"{what}: {msg}")
+
+    def _check_inputs(self, probe, obj, positions, batch_idx, patterns=None):
+        _need(probe, torch.complex64, (self.M, self.N, self.N), "probe")
+        _need(obj, torch.complex64, (self.S, self.H, self.W), "object")
+        _need(positions, torch.float32, (self.J, 2), "positions")
+        _need(batch_idx, torch.int32, None, "batch_idx")
+        if batch_idx.dim() != 1:
+            raise ValueError("batch_idx must be 1-D")
+        if patterns is not None:
+            _need(patterns, torch.float32, (self.J, self.N, self.N), "patterns")
+        return batch_idx.numel()
+
+    def forward(self, probe, obj, positions, batch_idx, patterns=None, intensities=True):
+        """Intensities [B][N][N] (and the group loss if patterns are given)."""
+        B = self._check_inputs(probe, obj, positions, batch_idx, patterns)
+        I = torch.empty((B, self.N, self.N), dtype=torch.float32, device=probe.device) if intensities else None
+        loss = torch.zeros(1, dtype=torch.float64, device=probe.device) if patterns is not None else None
+        st = self.lib.pty_forward(self.ctx, _stream(), _ptr(probe), _ptr(obj), _ptr(positions), _ptr(batch_idx), B,
+                                  _ptr(patterns), _ptr(I), _ptr(loss))
+        if st:
+            self._err(st, "pty_forward")
+        return I, loss
+
+    def loss_and_grad(self, probe, obj, positions, patterns, batch_idx, g_object=None, g_probe=None, g_pos=None,
+                      accumulate=False, want=("object", "probe", "pos")):
+        """Group loss and gradients (dL/dRe + i dL/dIm) of object, probe and per-entry positions."""
+        B = self._check_inputs(probe, obj, positions, batch_idx, patterns)
+        dev = probe.device
+        if "object" in want and g_object is None:
+            g_object = torch.empty_like(obj)
+        if "probe" in want and g_probe is None:
+            g_probe = torch.empty_like(probe)
+        if "pos" in want and g_pos is None:
+            g_pos = torch.empty((B, 2), dtype=torch.float32, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        st = self.lib.pty_loss_and_grad(self.ctx, _stream(), _ptr(probe), _ptr(obj), _ptr(positions),
+                                        _ptr(patterns), _ptr(batch_idx), B, _ptr(loss), _ptr(g_object),
+                                        _ptr(g_probe), _ptr(g_pos), _lib.PTY_ACCUMULATE if accumulate else 0)
+        if st:
+            self._err(st, "pty_loss_and_grad")
+        return loss, g_object, g_probe, g_pos
+
+    def forward_save(self, probe, obj, positions, patterns, batch_idx, intensities=False):
+        B = self._check_inputs(probe, obj, positions, batch_idx, patterns)
+        I = torch.empty((B, self.N, self.N), dtype=torch.float32, device=probe.device) if intensities else None
+        loss = torch.zeros(1, dtype=torch.float64, device=probe.device)
+        st = self.lib.pty_forward_save(self.ctx, _stream(), _ptr(probe), _ptr(obj), _ptr(positions), _ptr(patterns),
+                                       _ptr(batch_idx), B, _ptr(I), _ptr(loss))
+        if st:
+            self._err(st, "pty_forward_save")
+        return loss, I
+
+    def backward(self, grad_scale, g_object=None, g_probe=None, g_pos=None, accumulate=False):
+        st = self.lib.pty_backward(self.ctx, _stream(), float(grad_scale), _ptr(g_object), _ptr(g_probe),
+                                   _ptr(g_pos), _lib.PTY_ACCUMULATE if accumulate else 0)
+        if st:
+            self._err(st, "pty_backward")
+
+    def reconstruct_step(self, state: ReconState, patterns, batch_idx, opt: Optimizer, loss=None):
+        B = self._check_inputs(state.probe, state.object, state.positions, batch_idx, patterns)
+        if loss is None:
+            loss = torch.zeros(1, dtype=torch.float64, device=state.probe.device)
+        cs = state.c()
+        co = opt.c()
+        st = self.lib.pty_reconstruct_step(self.ctx, _stream(), C.byref(cs), _ptr(patterns), _ptr(batch_idx), B,
+                                           C.byref(co), _ptr(loss))
+        if st:
+            self._err(st, "pty_reconstruct_step")
+        state.step = cs.step
+        return loss
+
+    def check(self):
+        """Synchronise and raise on a device-side flag (window out of bounds, non-finite loss)."""
+        st = self.lib.pty_check(self.ctx, _stream())
+        if st:
+            self._err(st, "pty_check")
+
+
+class Group:
+    """Shared-launch workspace for reconstructions with one window size (pty_group_*)."""
+
+    def __init__(self, N: int, max_items: int, max_tiles: int, max_ckpt_tiles: int):
+        self.lib = _lib.load()
+        self.N = N
+        g = C.c_void_p()
+        st = self.lib.pty_group_create(N, max_items, max_tiles, max_ckpt_tiles, C.byref(g))
+        if st:
+            raise PtyError(st, "pty_group_create")
+        self.grp = g
+
+    @staticmethod
+    def workspace_bytes(N, max_items, max_tiles, max_ckpt_tiles):
+        lib = _lib.load()
+        out = C.c_size_t()
+        st = lib.pty_group_workspace_bytes(N, max_items, max_tiles, max_ckpt_tiles, C.byref(out))
+        if st:
+            raise PtyError(st, "pty_group_workspace_bytes")
+        return out.value
+
+    def step(self, entries):
+        """entries: list of (Problem, ReconState, patterns, batch_idx, Optimizer, loss_tensor)."""
+        n = len(entries)
+        items = (_lib.GroupItem * n)()
+        keep = []
+        for q, (prob, state, pats, bidx, opt, loss) in enumerate(entries):
+            cs, co = state.c(), opt.c()
+            keep.append((cs, co))
+            items[q] = _lib.GroupItem(prob.ctx, C.pointer(cs), _ptr(pats), _ptr(bidx), bidx.numel(), C.pointer(co),
+                                      _ptr(loss))
+        st = self.lib.pty_group_reconstruct_step(self.grp, _stream(), items, n)
+        if st:
+            raise PtyError(st, "pty_group_reconstruct_step: " + self.lib.pty_group_last_error(self.grp).decode())
+        for (prob, state, *_), (cs, _co) in zip(entries, keep):
+            state.step = cs.step
+
+    def close(self):
+        if getattr(self, "grp", None):
+            self.lib.pty_group_destroy(self.grp)
+            self.grp = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,673 @@
+// pty_api.cpp -- host side of libpty: contexts, workspace, propagator tables,
+// and the launch sequences of forward, loss-and-gradient and one optimiser
+// step (arXiv 2505.14372, Sec. 2.2 engine loop, Sec. 3 - 3.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pty.h"
+#include "pty_internal.h"
+
+using namespace pty;
+
+namespace {
+
+constexpr double kPiD = 3.141592653589793238462643383279502884;
+
+bool supported_N(int N) { return N == 64 || N == 128 || N == 192 || N == 256; }
+
+template <typename T>
+pty_status dmalloc(T** p, size_t count, std::string& err) {
+  *p = nullptr;
+  if (count == 0) return PTY_OK;
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    err = "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed";
+    return PTY_ENOMEM;
+  }
+  return PTY_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// Roots of unity w_N^k = exp(-2 pi i k / N), computed in double.
+std::vector<float2> roots(int N) {
+  std::vector<float2> t(N);
+  for (int k = 0; k < N; ++k) {
+    double a = 2.0 * kPiD * (double)k / (double)N;
+    t[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  return t;
+}
+
+// Propagator for one gap, divided by N^2 (the normalisation of the unnormalised
+// forward and inverse 2D DFTs around it): H(u) = B(u) exp(-i pi lambda dz |q|^2),
+// q = f(u) / dx, B the circular band limit on signed integer bins.
+std::vector<float2> propagator(int N, double dx, double lam, double dz, double frac) {
+  std::vector<float2> H((size_t)N * N);
+  const double r = frac * N / 2.0;
+  const double r2 = r * r * (1.0 + 1e-9);
+  const double inv_n2 = 1.0 / ((double)N * (double)N);
+  for (int y = 0; y < N; ++y) {
+    const int ky = y < (N + 1) / 2 ? y : y - N;
+    const double qy = (double)ky / N / dx;
+    for (int x = 0; x < N; ++x) {
+      const int kx = x < (N + 1) / 2 ? x : x - N;
+      const double qx = (double)kx / N / dx;
+      const bool keep = frac <= 0.0 || (double)(ky * ky + kx * kx) <= r2;
+      const double ph = -kPiD * lam * dz * (qy * qy + qx * qx);
+      H[(size_t)y * N + x] = keep ? make_float2((float)(std::cos(ph) * inv_n2), (float)(std::sin(ph) * inv_n2))
+                                  : make_float2(0.f, 0.f);
+    }
+  }
+  return H;
+}
+
+struct Sizes {
+  size_t tiles = 0, ck_tiles = 0, seg_tiles = 0, ws2_tiles = 0;
+  size_t bytes = 0;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Device bytes of one context (fixed part + batch workspace).
+Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k) {
+  Sizes s;
+  const size_t N2 = (size_t)g->N * g->N;
+  const int S = g->n_slices, M = g->n_modes;
+  const int n_ck = (S + k - 1) / k;
+  s.tiles = (size_t)max_batch * M;
+  s.ck_tiles = (size_t)max_batch * M * n_ck;
+  s.seg_tiles = k > 1 ? (size_t)max_batch * M * (k - 1) : 0;
+  s.ws2_tiles = k > 1 ? s.tiles : 0;
+  size_t b = 0;
+  b += align256(g->N * sizeof(float2));                             // roots
+  b += align256((size_t)std::max(S - 1, 0) * N2 * sizeof(float2));  // propagators
+  b += 3 * align256((size_t)M * N2 * sizeof(float2));               // phat, gphat, gprobe
+  b += align256((size_t)S * g->obj_h * g->obj_w * sizeof(float2));  // object gradient
+  b += align256((size_t)g->n_positions * 2 * sizeof(float));        // dense position gradient
+  b += align256(sizeof(int) * 4);                                   // flags
+  if (max_batch > 0) {
+    const int nblk = col_blocks(g->N);
+    b += align256((s.tiles + s.ck_tiles + s.seg_tiles + s.ws2_tiles) * N2 * sizeof(float2));
+    b += align256((size_t)max_batch * sizeof(Item));
+    b += align256((size_t)max_batch * 2 * g->N * sizeof(float2));
+    b += align256((size_t)max_batch * nblk * sizeof(float));
+    b += align256((size_t)max_batch * M * nblk * 2 * sizeof(float));
+  }
+  s.bytes = b;
+  return s;
+}
+
+pty_status validate_geometry(const pty_geometry* g, std::string& err) {
+  if (!g) { err = "geometry is NULL"; return PTY_EINVAL; }
+  if (!supported_N(g->N)) { err = "N must be 64, 128, 192 or 256"; return PTY_EUNSUPPORTED; }
+  if (g->n_modes < 1 || g->n_slices < 1 || g->n_positions < 1) { err = "n_modes, n_slices, n_positions must be >= 1"; return PTY_EINVAL; }
+  if (g->obj_h < g->N || g->obj_w < g->N) { err = "object smaller than the window"; return PTY_EINVAL; }
+  if (g->n_slices > 1 && !g->dz) { err = "dz is NULL"; return PTY_EINVAL; }
+  if (g->loss < PTY_LOSS_AMPLITUDE || g->loss > PTY_LOSS_GAUSSIAN) { err = "unknown loss kind"; return PTY_EINVAL; }
+  if (!(g->dx > 0) || !(g->wavelength > 0)) { err = "dx and wavelength must be positive"; return PTY_EINVAL; }
+  if (g->loss == PTY_LOSS_GAUSSIAN && !(g->sigma > 0)) { err = "sigma must be positive"; return PTY_EINVAL; }
+  if ((size_t)g->n_slices * g->obj_h * g->obj_w > ((size_t)1 << 40)) { err = "object too large"; return PTY_EUNSUPPORTED; }
+  return PTY_OK;
+}
+
+}  // namespace
+
+struct pty_ctx {
+  pty_geometry g{};
+  std::vector<double> dz;
+  int max_batch = 0, ck_every = 1, n_ck = 1;
+  Sizes sz;
+  float2 *tw = nullptr, *prop = nullptr, *phat = nullptr, *gphat = nullptr, *gprobe = nullptr, *gobj = nullptr;
+  float* gpos = nullptr;
+  int* flags = nullptr;
+  float2 *ws = nullptr, *ws2 = nullptr, *ck = nullptr, *seg = nullptr;
+  Item* items = nullptr;
+  float2* ramps = nullptr;
+  float *loss_part = nullptr, *pos_part = nullptr;
+  // tape of pty_forward_save
+  bool tape_valid = false;
+  LaunchCtx tape{};
+  std::string err;
+};
+
+struct pty_group {
+  int N = 0, max_items = 0, max_tiles = 0;
+  long long max_ck = 0;
+  float2 *tw = nullptr, *ws = nullptr, *ck = nullptr, *ramps = nullptr;
+  Item* items = nullptr;
+  float *loss_part = nullptr, *pos_part = nullptr;
+  int* flags = nullptr;
+  std::string err;
+};
+
+namespace {
+
+#define HIPCHECK(ctxp, call)                                               \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess) {                                                \
+      (ctxp)->err = std::string(#call) + ": " + hipGetErrorString(e_);     \
+      return PTY_EHIP;                                                     \
+    }                                                                      \
+  } while (0)
+
+ReqDev base_req(pty_ctx* c) {
+  ReqDev r{};
+  r.prop = c->prop;
+  r.phat = c->phat;
+  r.gphat = c->gphat;
+  r.S = c->g.n_slices;
+  r.M = c->g.n_modes;
+  r.H = c->g.obj_h;
+  r.W = c->g.obj_w;
+  r.J = c->g.n_positions;
+  r.loss = c->g.loss;
+  r.eps = (float)c->g.eps;
+  r.inv_sigma2 = c->g.loss == PTY_LOSS_GAUSSIAN ? (float)(1.0 / (c->g.sigma * c->g.sigma)) : 1.f;
+  r.ck_every = c->ck_every;
+  r.n_ck = c->n_ck;
+  return r;
+}
+
+LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
+  LaunchCtx L{};
+  L.stream = s;
+  L.reqs.r[0] = r;
+  L.reqs.r[0].item0 = 0;
+  L.reqs.r[0].n_items = B;
+  L.n_reqs = 1;
+  L.n_items = B;
+  L.max_modes = c->g.n_modes;
+  L.items = c->items;
+  L.ws = c->ws;
+  L.ck = c->ck;
+  L.ramps = c->ramps;
+  L.tw = c->tw;
+  L.loss_part = c->loss_part;
+  L.pos_part = c->pos_part;
+  L.flags = c->flags;
+  return L;
+}
+
+// Forward sequence over all requests of L (steps up to the largest S).
+// save: store entry-wave checkpoints and leave the detector-plane gradient
+// seed (after its inverse column DFT) in the workspace.
+void run_forward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& far_steps, bool save,
+                 bool want_loss) {
+  launch_items(L, N);
+  launch_col(L, N, COL_SHIFT, 0);
+  PsiStore st{};
+  st.mode = save ? 1 : 0;
+  for (int i = 0; i < S_max; ++i) {
+    launch_rows_fwd(L, N, i, st, false);
+    if (i < S_max - 1) launch_col(L, N, COL_PROP, i);
+    if (std::find(far_steps.begin(), far_steps.end(), i) != far_steps.end()) launch_far_loss(L, N, i, save);
+  }
+  if (want_loss) launch_loss_reduce(L, N);
+}
+
+// Adjoint sequence (after run_forward with save). Single-request contexts may
+// use checkpoint intervals k > 1; grouped launches store every slice.
+void run_backward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& final_steps, float scale,
+                  int k, float2* ws2, float2* seg) {
+  int seg_lo = -1, seg_hi = -1;   // slices currently held in the segment buffer
+  for (int t = 0; t < S_max; ++t) {
+    const int i = S_max - 1 - t;   // single-request slice index (k > 1 only)
+    PsiLoad psi{};
+    if (k > 1 && i % k != 0) {
+      const int i0 = (i / k) * k;
+      const int i1 = std::min(i0 + k - 1, S_max - 1);
+      if (!(seg_lo == i0 + 1 && seg_hi == i1)) {
+        // recompute entry waves i0+1 .. i1 from the checkpoint at i0
+        LaunchCtx R = L;
+        R.ws = ws2;
+        PsiStore st{};
+        st.mode = 0;
+        st.src = L.ck;
+        st.src_slot = i0 / k;
+        launch_rows_fwd(R, N, i0, st, true);
+        for (int s = i0 + 1; s <= i1; ++s) {
+          launch_col(R, N, COL_PROP, s - 1);
+          PsiStore ss{};
+          ss.mode = 2;
+          ss.seg = seg;
+          ss.seg_len = k - 1;
+          ss.seg_slot = s - i0 - 1;
+          ss.stop_after_store = (s == i1) ? 1 : 0;
+          launch_rows_fwd(R, N, s, ss, false);
+        }
+        seg_lo = i0 + 1;
+        seg_hi = i1;
+      }
+      psi.from_seg = 1;
+      psi.seg = seg;
+      psi.seg_len = k - 1;
+      psi.seg_base = i0 + 1;
+    }
+    launch_rows_adj(L, N, t, psi, scale);
+    launch_col(L, N, COL_PROP_ADJ, t);
+    if (std::find(final_steps.begin(), final_steps.end(), t) != final_steps.end()) launch_col(L, N, COL_FINAL, t);
+  }
+  launch_probe_grad(L, N, scale);
+  launch_pos_reduce(L, N, scale);
+}
+
+pty_status check_call(pty_ctx* c, const void* probe, const void* object, const void* positions,
+                      const int32_t* batch_idx, int32_t B) {
+  if (!c) return PTY_EINVAL;
+  if (!probe || !object || !positions || !batch_idx) { c->err = "NULL input pointer"; return PTY_EINVAL; }
+  if (B < 1 || B > c->max_batch) {
+    c->err = "batch " + std::to_string(B) + " outside [1, max_batch=" + std::to_string(c->max_batch) + "]";
+    return PTY_EINVAL;
+  }
+  return PTY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pty_status pty_workspace_bytes(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every,
+                               size_t* bytes) {
+  std::string err;
+  pty_status st = validate_geometry(g, err);
+  if (st != PTY_OK) return st;
+  if (!bytes || max_batch < 0 || checkpoint_every < 1) return PTY_EINVAL;
+  *bytes = ctx_sizes(g, max_batch, std::min<int>(checkpoint_every, g->n_slices)).bytes;
+  return PTY_OK;
+}
+
+int32_t pty_checkpoint_every(const pty_ctx* ctx) { return ctx ? ctx->ck_every : 0; }
+
+pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every, size_t hbm_budget,
+                      pty_ctx** out) {
+  if (!out) return PTY_EINVAL;
+  *out = nullptr;
+  std::string err;
+  pty_status st = validate_geometry(g, err);
+  if (st != PTY_OK) return st;
+  if (max_batch < 0 || checkpoint_every < 0) return PTY_EINVAL;
+  const int S = g->n_slices;
+  int k = checkpoint_every;
+  if (k == 0) {
+    k = 1;
+    if (hbm_budget > 0) {
+      while (k <= S && ctx_sizes(g, max_batch, k).bytes > hbm_budget) ++k;
+      if (k > S) return PTY_ENOMEM;
+    }
+  }
+  k = std::min(k, S);
+  pty_ctx* c = new pty_ctx();
+  c->g = *g;
+  c->dz.assign(g->dz ? g->dz : nullptr, g->dz ? g->dz + std::max(S - 1, 0) : nullptr);
+  c->g.dz = c->dz.data();
+  c->max_batch = max_batch;
+  c->ck_every = k;
+  c->n_ck = (S + k - 1) / k;
+  c->sz = ctx_sizes(g, max_batch, k);
+  const int N = g->N, M = g->n_modes;
+  const size_t N2 = (size_t)N * N;
+  std::string& e = c->err;
+  auto fail = [&](pty_status s) { pty_destroy(c); return s; };
+  if ((st = dmalloc(&c->tw, N, e)) || (st = dmalloc(&c->prop, (size_t)std::max(S - 1, 0) * N2, e)) ||
+      (st = dmalloc(&c->phat, (size_t)M * N2, e)) || (st = dmalloc(&c->gphat, (size_t)M * N2, e)) ||
+      (st = dmalloc(&c->gprobe, (size_t)M * N2, e)) ||
+      (st = dmalloc(&c->gobj, (size_t)S * g->obj_h * g->obj_w, e)) ||
+      (st = dmalloc(&c->gpos, (size_t)g->n_positions * 2, e)) || (st = dmalloc(&c->flags, 4, e)))
+    return fail(st);
+  if (max_batch > 0) {
+    const int nblk = col_blocks(N);
+    if ((st = dmalloc(&c->ws, c->sz.tiles * N2, e)) || (st = dmalloc(&c->ck, c->sz.ck_tiles * N2, e)) ||
+        (st = dmalloc(&c->seg, c->sz.seg_tiles * N2, e)) || (st = dmalloc(&c->ws2, c->sz.ws2_tiles * N2, e)) ||
+        (st = dmalloc(&c->items, (size_t)max_batch, e)) || (st = dmalloc(&c->ramps, (size_t)max_batch * 2 * N, e)) ||
+        (st = dmalloc(&c->loss_part, (size_t)max_batch * nblk, e)) ||
+        (st = dmalloc(&c->pos_part, (size_t)max_batch * M * nblk * 2, e)))
+      return fail(st);
+  }
+  std::vector<float2> tw = roots(N);
+  if (hipMemcpy(c->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return fail(PTY_EHIP);
+  for (int i = 0; i < S - 1; ++i) {
+    std::vector<float2> H = propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit);
+    if (hipMemcpy(c->prop + (size_t)i * N2, H.data(), N2 * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(PTY_EHIP);
+  }
+  if (hipMemset(c->flags, 0, 4 * sizeof(int)) != hipSuccess) return fail(PTY_EHIP);
+  *out = c;
+  return PTY_OK;
+}
+
+void pty_destroy(pty_ctx* c) {
+  if (!c) return;
+  dfree(c->tw); dfree(c->prop); dfree(c->phat); dfree(c->gphat); dfree(c->gprobe); dfree(c->gobj);
+  dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
+  dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
+  delete c;
+}
+
+const char* pty_last_error(const pty_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+pty_status pty_check(pty_ctx* c, void* stream) {
+  if (!c) return PTY_EINVAL;
+  HIPCHECK(c, hipStreamSynchronize((hipStream_t)stream));
+  int f = 0;
+  HIPCHECK(c, hipMemcpy(&f, c->flags, sizeof(int), hipMemcpyDeviceToHost));
+  if (f) HIPCHECK(c, hipMemset(c->flags, 0, sizeof(int)));
+  if (f & kFlagBounds) { c->err = "a probe window left the object"; return PTY_EBOUNDS; }
+  if (f & kFlagNonFinite) { c->err = "non-finite loss or detector weight"; return PTY_ENONFINITE; }
+  return PTY_OK;
+}
+
+pty_status pty_forward(pty_ctx* c, void* stream, const pty_c64* probe, const pty_c64* object,
+                       const float* positions, const int32_t* batch_idx, int32_t B, const float* patterns,
+                       float* intensities, double* loss) {
+  pty_status st = check_call(c, probe, object, positions, batch_idx, B);
+  if (st != PTY_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->tape_valid = false;
+  const int N = c->g.N, S = c->g.n_slices;
+  launch_plain2d(N, s, c->tw, (const float2*)probe, c->phat, c->g.n_modes, false, 1.f / N, false);
+  ReqDev r = base_req(c);
+  r.obj = (const float2*)object;
+  r.positions = positions;
+  r.batch_idx = batch_idx;
+  r.patterns = patterns;
+  r.I_out = intensities;
+  r.loss_out = (patterns && loss) ? loss : nullptr;
+  LaunchCtx L = ctx_launch(c, s, r, B);
+  run_forward(L, N, S, {S - 1}, false, r.loss_out != nullptr);
+  HIPCHECK(c, hipGetLastError());
+  return PTY_OK;
+}
+
+pty_status pty_forward_save(pty_ctx* c, void* stream, const pty_c64* probe, const pty_c64* object,
+                            const float* positions, const float* patterns, const int32_t* batch_idx, int32_t B,
+                            float* intensities, double* loss) {
+  pty_status st = check_call(c, probe, object, positions, batch_idx, B);
+  if (st != PTY_OK) return st;
+  if (!patterns) { c->err = "patterns are required for the gradient"; return PTY_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  c->tape_valid = false;
+  const int N = c->g.N, S = c->g.n_slices;
+  launch_plain2d(N, s, c->tw, (const float2*)probe, c->phat, c->g.n_modes, false, 1.f / N, false);
+  ReqDev r = base_req(c);
+  r.obj = (const float2*)object;
+  r.positions = positions;
+  r.batch_idx = batch_idx;
+  r.patterns = patterns;
+  r.I_out = intensities;
+  r.loss_out = loss;
+  LaunchCtx L = ctx_launch(c, s, r, B);
+  run_forward(L, N, S, {S - 1}, true, loss != nullptr);
+  HIPCHECK(c, hipGetLastError());
+  c->tape = L;
+  c->tape_valid = true;
+  return PTY_OK;
+}
+
+pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_object, pty_c64* g_probe,
+                        float* g_pos, uint32_t flags) {
+  if (!c) return PTY_EINVAL;
+  if (!c->tape_valid) { c->err = "pty_backward needs a preceding pty_forward_save"; return PTY_ESTATE; }
+  hipStream_t s = (hipStream_t)stream;
+  const int N = c->g.N, S = c->g.n_slices;
+  const bool acc = (flags & PTY_ACCUMULATE) != 0;
+  LaunchCtx L = c->tape;
+  L.stream = s;
+  ReqDev& r = L.reqs.r[0];
+  r.gobj = (float2*)g_object;
+  r.gpos = g_pos;
+  r.gpos_dense = nullptr;
+  r.accumulate = acc ? 1 : 0;
+  r.I_out = nullptr;
+  r.loss_out = nullptr;
+  r.gphat = g_probe ? c->gphat : nullptr;
+  if (g_object && !acc)
+    launch_fill(s, (float*)g_object, (size_t)S * c->g.obj_h * c->g.obj_w * 2, 0.f);
+  run_backward(L, N, S, {S - 1}, (float)grad_scale, c->ck_every, c->ws2, c->seg);
+  if (g_probe)
+    launch_plain2d(N, s, c->tw, c->gphat, (float2*)g_probe, c->g.n_modes, true, 1.f / N, acc);
+  c->tape_valid = false;
+  HIPCHECK(c, hipGetLastError());
+  return PTY_OK;
+}
+
+pty_status pty_loss_and_grad(pty_ctx* c, void* stream, const pty_c64* probe, const pty_c64* object,
+                             const float* positions, const float* patterns, const int32_t* batch_idx, int32_t B,
+                             double* loss, pty_c64* g_object, pty_c64* g_probe, float* g_pos, uint32_t flags) {
+  pty_status st = pty_forward_save(c, stream, probe, object, positions, patterns, batch_idx, B, nullptr, loss);
+  if (st != PTY_OK) return st;
+  return pty_backward(c, stream, 1.0, g_object, g_probe, g_pos, flags);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Optimiser step of one variable with n real components.
+void opt_update(hipStream_t s, const pty_optim* o, int64_t t, float* th, const float* g, float* m, float* v,
+                double lr, size_t n) {
+  if (lr == 0.0 || n == 0) return;
+  if (o->kind == PTY_OPT_SGD) {
+    launch_sgd(s, th, g, n, (float)lr);
+  } else {
+    const double bc1 = 1.0 - std::pow(o->beta1, (double)t);
+    const double bc2 = 1.0 - std::pow(o->beta2, (double)t);
+    launch_adam(s, th, g, m, v, n, (float)(lr / bc1), (float)(1.0 / std::sqrt(bc2)), (float)o->beta1,
+                (float)o->beta2, (float)o->eps);
+  }
+}
+
+pty_status check_state(pty_ctx* c, const pty_state* st, const pty_optim* o) {
+  if (!st || !o || !st->probe || !st->object || !st->positions) { c->err = "NULL state"; return PTY_EINVAL; }
+  if (o->kind != PTY_OPT_SGD && o->kind != PTY_OPT_ADAM) { c->err = "unknown optimiser"; return PTY_EINVAL; }
+  if (o->kind == PTY_OPT_ADAM) {
+    if ((o->lr_object != 0 && (!st->m_object || !st->v_object)) || (o->lr_probe != 0 && (!st->m_probe || !st->v_probe)) ||
+        (o->lr_pos != 0 && (!st->m_pos || !st->v_pos))) {
+      c->err = "Adam needs moment buffers";
+      return PTY_EINVAL;
+    }
+  }
+  return PTY_OK;
+}
+
+void apply_optimizer(pty_ctx* c, hipStream_t s, pty_state* st, const pty_optim* o) {
+  const pty_geometry& g = c->g;
+  const size_t nO = (size_t)g.n_slices * g.obj_h * g.obj_w * 2;
+  const size_t nP = (size_t)g.n_modes * g.N * g.N * 2;
+  const size_t nX = (size_t)g.n_positions * 2;
+  const int64_t t = st->step + 1;
+  opt_update(s, o, t, (float*)st->object, (const float*)c->gobj, st->m_object, st->v_object, o->lr_object, nO);
+  opt_update(s, o, t, (float*)st->probe, (const float*)c->gprobe, st->m_probe, st->v_probe, o->lr_probe, nP);
+  opt_update(s, o, t, st->positions, c->gpos, st->m_pos, st->v_pos, o->lr_pos, nX);
+  if (o->kind == PTY_OPT_ADAM) st->step = t;
+}
+
+}  // namespace
+
+extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* st, const float* patterns,
+                                           const int32_t* batch_idx, int32_t B, const pty_optim* o, double* loss) {
+  if (!c) return PTY_EINVAL;
+  pty_status s0 = check_state(c, st, o);
+  if (s0 != PTY_OK) return s0;
+  hipStream_t s = (hipStream_t)stream;
+  s0 = pty_forward_save(c, stream, st->probe, st->object, st->positions, patterns, batch_idx, B, nullptr, loss);
+  if (s0 != PTY_OK) return s0;
+  const pty_geometry& g = c->g;
+  const int N = g.N, S = g.n_slices;
+  LaunchCtx L = c->tape;
+  ReqDev& r = L.reqs.r[0];
+  r.gobj = c->gobj;
+  r.gpos = nullptr;
+  r.gpos_dense = c->gpos;
+  r.gphat = c->gphat;
+  r.I_out = nullptr;
+  r.loss_out = nullptr;
+  launch_fill(s, (float*)c->gobj, (size_t)S * g.obj_h * g.obj_w * 2, 0.f);
+  launch_fill(s, c->gpos, (size_t)g.n_positions * 2, 0.f);
+  run_backward(L, N, S, {S - 1}, 1.f, c->ck_every, c->ws2, c->seg);
+  launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, g.n_modes, true, 1.f / N, false);
+  c->tape_valid = false;
+  apply_optimizer(c, s, st, o);
+  HIPCHECK(c, hipGetLastError());
+  return PTY_OK;
+}
+
+// ---------------------------------------------------------------- grouped launches
+
+namespace {
+
+Sizes group_sizes(int N, int max_items, int max_tiles, long long max_ck) {
+  Sizes s;
+  const size_t N2 = (size_t)N * N;
+  const int nblk = col_blocks(N);
+  s.tiles = max_tiles;
+  s.ck_tiles = max_ck;
+  size_t b = align256(N * sizeof(float2));
+  b += align256(((size_t)max_tiles + (size_t)max_ck) * N2 * sizeof(float2));
+  b += align256((size_t)max_items * sizeof(Item));
+  b += align256((size_t)max_items * 2 * N * sizeof(float2));
+  b += align256((size_t)max_items * nblk * sizeof(float));
+  b += align256((size_t)max_tiles * nblk * 2 * sizeof(float));
+  b += align256(4 * sizeof(int));
+  s.bytes = b;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+pty_status pty_group_workspace_bytes(int32_t N, int32_t max_items, int32_t max_tiles, int64_t max_ckpt_tiles,
+                                     size_t* bytes) {
+  if (!supported_N(N)) return PTY_EUNSUPPORTED;
+  if (!bytes || max_items < 1 || max_tiles < 1 || max_ckpt_tiles < 1) return PTY_EINVAL;
+  *bytes = group_sizes(N, max_items, max_tiles, max_ckpt_tiles).bytes;
+  return PTY_OK;
+}
+
+pty_status pty_group_create(int32_t N, int32_t max_items, int32_t max_tiles, int64_t max_ckpt_tiles,
+                            pty_group** out) {
+  if (!out) return PTY_EINVAL;
+  *out = nullptr;
+  if (!supported_N(N)) return PTY_EUNSUPPORTED;
+  if (max_items < 1 || max_tiles < 1 || max_ckpt_tiles < 1) return PTY_EINVAL;
+  pty_group* G = new pty_group();
+  G->N = N;
+  G->max_items = max_items;
+  G->max_tiles = max_tiles;
+  G->max_ck = max_ckpt_tiles;
+  const size_t N2 = (size_t)N * N;
+  const int nblk = col_blocks(N);
+  pty_status st;
+  auto fail = [&](pty_status s) { pty_group_destroy(G); return s; };
+  if ((st = dmalloc(&G->tw, N, G->err)) || (st = dmalloc(&G->ws, (size_t)max_tiles * N2, G->err)) ||
+      (st = dmalloc(&G->ck, (size_t)max_ckpt_tiles * N2, G->err)) || (st = dmalloc(&G->items, (size_t)max_items, G->err)) ||
+      (st = dmalloc(&G->ramps, (size_t)max_items * 2 * N, G->err)) ||
+      (st = dmalloc(&G->loss_part, (size_t)max_items * nblk, G->err)) ||
+      (st = dmalloc(&G->pos_part, (size_t)max_tiles * nblk * 2, G->err)) || (st = dmalloc(&G->flags, 4, G->err)))
+    return fail(st);
+  std::vector<float2> tw = roots(N);
+  if (hipMemcpy(G->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return fail(PTY_EHIP);
+  if (hipMemset(G->flags, 0, 4 * sizeof(int)) != hipSuccess) return fail(PTY_EHIP);
+  *out = G;
+  return PTY_OK;
+}
+
+void pty_group_destroy(pty_group* G) {
+  if (!G) return;
+  dfree(G->tw); dfree(G->ws); dfree(G->ck); dfree(G->items); dfree(G->ramps);
+  dfree(G->loss_part); dfree(G->pos_part); dfree(G->flags);
+  delete G;
+}
+
+const char* pty_group_last_error(const pty_group* G) { return G ? G->err.c_str() : "NULL group"; }
+
+pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_group_item* items, int32_t n) {
+  if (!G) return PTY_EINVAL;
+  if (!items || n < 1 || n > kMaxReqs) { G->err = "1 to 16 items per grouped step"; return PTY_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  const int N = G->N;
+  LaunchCtx L{};
+  L.stream = s;
+  L.items = G->items;
+  L.ws = G->ws;
+  L.ck = G->ck;
+  L.ramps = G->ramps;
+  L.tw = G->tw;
+  L.loss_part = G->loss_part;
+  L.pos_part = G->pos_part;
+  L.flags = G->flags;
+  int item0 = 0, tile0 = 0, S_max = 0, M_max = 0;
+  long long ck0 = 0;
+  std::vector<int> last_steps;
+  for (int q = 0; q < n; ++q) {
+    const pty_group_item& it = items[q];
+    pty_ctx* c = it.ctx;
+    if (!c || c->g.N != N) { G->err = "item context missing or of another N"; return PTY_EINVAL; }
+    pty_status st0 = check_state(c, it.state, it.opt);
+    if (st0 != PTY_OK) { G->err = c->err; return st0; }
+    if (!it.patterns || !it.batch_idx || it.batch < 1) { G->err = "item needs patterns and a batch"; return PTY_EINVAL; }
+    const int M = c->g.n_modes, S = c->g.n_slices;
+    ReqDev r = base_req(c);
+    r.obj = (const float2*)it.state->object;
+    r.positions = it.state->positions;
+    r.batch_idx = it.batch_idx;
+    r.patterns = it.patterns;
+    r.loss_out = it.loss;
+    r.gobj = c->gobj;
+    r.gpos_dense = c->gpos;
+    r.item0 = item0;
+    r.n_items = it.batch;
+    r.tile_base = tile0;
+    r.ck_base = ck0;
+    r.ck_every = 1;
+    r.n_ck = S;
+    L.reqs.r[q] = r;
+    item0 += it.batch;
+    tile0 += it.batch * M;
+    ck0 += (long long)it.batch * M * S;
+    S_max = std::max(S_max, S);
+    M_max = std::max(M_max, M);
+    last_steps.push_back(S - 1);
+  }
+  if (item0 > G->max_items || tile0 > G->max_tiles || ck0 > G->max_ck) {
+    G->err = "grouped step exceeds the group's workspace";
+    return PTY_EINVAL;
+  }
+  L.n_reqs = n;
+  L.n_items = item0;
+  L.max_modes = M_max;
+  for (int q = 0; q < n; ++q) {
+    pty_ctx* c = items[q].ctx;
+    launch_plain2d(N, s, G->tw, (const float2*)items[q].state->probe, c->phat, c->g.n_modes, false, 1.f / N, false);
+    launch_fill(s, (float*)c->gobj, (size_t)c->g.n_slices * c->g.obj_h * c->g.obj_w * 2, 0.f);
+    launch_fill(s, c->gpos, (size_t)c->g.n_positions * 2, 0.f);
+  }
+  std::sort(last_steps.begin(), last_steps.end());
+  last_steps.erase(std::unique(last_steps.begin(), last_steps.end()), last_steps.end());
+  run_forward(L, N, S_max, last_steps, true, true);
+  // adjoint step t handles slice S_q - 1 - t of request q; slice 0 at t = S_q - 1
+  run_backward(L, N, S_max, last_steps, 1.f, 1, nullptr, nullptr);
+  for (int q = 0; q < n; ++q) {
+    pty_ctx* c = items[q].ctx;
+    launch_plain2d(N, s, G->tw, c->gphat, c->gprobe, c->g.n_modes, true, 1.f / N, false);
+    apply_optimizer(c, s, items[q].state, items[q].opt);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { G->err = hipGetErrorString(e); return PTY_EHIP; }
+  return PTY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// pty_internal.h -- device-side descriptors shared by the kernels and the
+// host orchestration of libpty (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "pty.h"
+
+namespace pty {
+
+constexpr int kFlagBounds = 1;
+constexpr int kFlagNonFinite = 2;
+constexpr int kMaxReqs = 16;   // reconstructions per shared launch
+
+// One batch entry (probe position) of a launch; filled on the device.
+struct Item {
+  int req;          // index into the launch's request table
+  int j;            // position index
+  int ny, nx;       // integer window offset (top-left corner)
+  float dy, dx;     // subpixel remainder of the position
+  int valid;        // window inside the object
+  int tile0;        // first workspace tile (modes follow)
+  long long ck0;    // first checkpoint tile (modes x stored slices follow)
+};
+
+// One reconstruction taking part in a launch. Passed by value in the kernel
+// arguments (a table of kMaxReqs), so no host-to-device staging is needed.
+struct ReqDev {
+  const float2* obj;        // [S][H][W]
+  float2* gobj;             // [S][H][W] or null
+  const float2* phat;       // [M][N][N] unitary probe spectrum
+  float2* gphat;            // [M][N][N] probe-spectrum gradient (scratch) or null
+  const float2* prop;       // [S-1][N][N] propagators divided by N^2
+  const float* patterns;    // [J][N][N] or null
+  const float* positions;   // [J][2]
+  const int32_t* batch_idx; // [n_items]
+  float* I_out;             // [n_items][N][N] or null
+  double* loss_out;         // device double or null
+  float* gpos;              // [n_items][2] or null
+  float* gpos_dense;        // [J][2] or null
+  int S, M, H, W, J;
+  int loss;
+  float eps, inv_sigma2;
+  int item0, n_items;
+  int tile_base;            // first workspace tile of this request
+  long long ck_base;        // first checkpoint tile of this request
+  int ck_every, n_ck;       // checkpoint interval and stored slices per mode
+  int accumulate;           // add into gpos instead of overwriting
+};
+
+struct ReqTable {
+  ReqDev r[kMaxReqs];
+};
+
+// Where the forward row pass stores entry waves.
+struct PsiStore {
+  int mode;                 // 0: nowhere, 1: checkpoint slots, 2: segment buffer
+  float2* seg;              // segment buffer [tiles][seg_len][N][N]
+  int seg_len, seg_slot;
+  const float2* src;        // FROM_REAL source (checkpoint buffer)
+  int src_slot;
+  int stop_after_store;     // skip the transmission and forward DFT
+};
+
+// Where the adjoint row pass reads entry waves.
+struct PsiLoad {
+  int from_seg;             // 0: checkpoint slot i / ck_every, 1: segment buffer
+  const float2* seg;
+  int seg_len, seg_base;    // slice i is at slot i - seg_base
+};
+
+struct LaunchCtx {
+  hipStream_t stream;
+  ReqTable reqs;
+  int n_reqs, n_items, max_modes;
+  Item* items;
+  float2* ws;               // tile workspace
+  float2* ck;               // checkpoint buffer
+  float2* ramps;            // [n_items][2][N]
+  const float2* tw;         // [N] roots of unity
+  float* loss_part;         // [n_items][col blocks]
+  float* pos_part;          // [tiles][col blocks][2] (tile = item tile0 + mode)
+  int* flags;
+};
+
+void launch_items(const LaunchCtx& L, int N);
+void launch_rows_fwd(const LaunchCtx& L, int N, int step, PsiStore st, bool from_real);
+void launch_rows_adj(const LaunchCtx& L, int N, int step, PsiLoad psi, float scale);
+void launch_col(const LaunchCtx& L, int N, int op, int step);
+void launch_far_loss(const LaunchCtx& L, int N, int step, bool grad);
+void launch_probe_grad(const LaunchCtx& L, int N, float scale);
+void launch_loss_reduce(const LaunchCtx& L, int N);
+void launch_pos_reduce(const LaunchCtx& L, int N, float scale);
+void launch_plain2d(int N, hipStream_t s, const float2* tw, const float2* src, float2* dst, int n_tiles,
+                    bool inverse, float scale, bool accumulate);
+void launch_fill(hipStream_t s, float* p, size_t n, float v);
+void launch_sgd(hipStream_t s, float* th, const float* g, size_t n, float lr);
+void launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, size_t n, float step_size,
+                 float inv_sqrt_bc2, float b1, float b2, float eps);
+int col_blocks(int N);
+
+enum ColOp { COL_SHIFT = 0, COL_PROP = 1, COL_PROP_ADJ = 2, COL_FINAL = 3 };
+
+}  // namespace pty

@@ -1,0 +1,689 @@
+// pty_kernels.hip -- HIP kernels (gfx950) of the multislice forward model,
+// noise-model loss and exact adjoint of arXiv 2505.14372 (Sec. 3 - 3.2).
+//
+// Data layout (all row-major, complex = float2):
+//   workspace tile (item b, mode m):  ws[(tile0(b) + m) * N*N + y*N + x]
+//   object slice i:                   obj[(i*H + y)*W + x]
+//   propagator for the gap after slice i (already divided by N^2):
+//                                     prop[i*N*N + u_y*N + u_x]
+//   probe spectrum (unitary):         phat[m*N*N + u_y*N + u_x]
+//   entry-wave checkpoints:           ck[(ck0(b) + m*n_ck + slot) * N*N + ...]
+//
+// One slice step is two passes over a tile, each a batched launch:
+//   row pass    : inverse row DFT -> entry wave psi_i (real space, optionally
+//                 checkpointed) -> times the object patch -> forward row DFT
+//   column pass : forward column DFT -> times the propagator -> inverse
+//                 column DFT
+// so that F^-1 H F between slices costs one read and one write of the tile
+// per pass. The adjoint runs the same passes backwards with conjugated
+// multipliers and accumulates the object gradient in the row pass.
+#include <hip/hip_runtime.h>
+
+#include "pty_fft.hpp"
+#include "pty_internal.h"
+
+namespace pty {
+
+constexpr int kThreads = 256;
+
+// Rows of a tile per row-pass workgroup, columns per column-pass workgroup.
+template <int N> struct Pass {
+  static constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
+  static constexpr int LINES = kThreads / L;      // lines held by one workgroup at once
+  static constexpr int NBLK = N / LINES;          // workgroups per tile
+};
+
+__device__ __forceinline__ void raise_flag(int* flags, int bit) {
+  if (flags) atomicOr(flags, bit);
+}
+
+template <int N>
+__device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw_glb) {
+  for (int k = threadIdx.x; k < N; k += kThreads) tw_lds[k] = tw_glb[k];
+}
+
+// ============================================================ items
+
+// One workgroup per batch entry: find its request, integer window offset and
+// subpixel remainder (in double, so n = floor(X + 0.5) is exact for float32
+// positions), bounds check, workspace offsets, and the two 1D shift ramps
+// exp(-2 pi i f(u) d) with f(u) = fftfreq(N).
+__global__ void k_items(const ReqTable reqs, int n_reqs, Item* __restrict__ items,
+                        float2* __restrict__ ramps, int n_items, int N, int* flags) {
+  const int b = blockIdx.x;
+  if (b >= n_items) return;
+  int q = 0;
+  for (int k = 0; k < n_reqs; ++k)
+    if (b >= reqs.r[k].item0 && b < reqs.r[k].item0 + reqs.r[k].n_items) q = k;
+  const ReqDev& r = reqs.r[q];
+  const int local = b - r.item0;
+  const int j = r.batch_idx[local];
+  const bool ok_idx = (j >= 0 && j < r.J);
+  const double X0 = ok_idx ? (double)r.positions[2 * j] : 0.0;
+  const double X1 = ok_idx ? (double)r.positions[2 * j + 1] : 0.0;
+  const double n0 = floor(X0 + 0.5), n1 = floor(X1 + 0.5);
+  const bool ok = ok_idx && (n0 >= 0.0) && (n1 >= 0.0) && (n0 + N <= (double)r.H) &&
+                  (n1 + N <= (double)r.W);
+  const float d0 = ok ? (float)(X0 - n0) : 0.f, d1 = ok ? (float)(X1 - n1) : 0.f;
+  if (threadIdx.x == 0) {
+    Item it;
+    it.req = q;
+    it.j = ok_idx ? j : 0;
+    it.ny = ok ? (int)n0 : 0;
+    it.nx = ok ? (int)n1 : 0;
+    it.dy = d0;
+    it.dx = d1;
+    it.valid = ok ? 1 : 0;
+    it.tile0 = r.tile_base + local * r.M;
+    it.ck0 = r.ck_base + (long long)local * r.M * r.n_ck;
+    items[b] = it;
+    if (!ok) raise_flag(flags, kFlagBounds);
+  }
+  for (int u = threadIdx.x; u < N; u += blockDim.x) {
+    const int k = (u < (N + 1) / 2) ? u : u - N;
+    const float f = (float)k / (float)N;
+    float s0, c0, s1, c1;
+    sincospif(2.f * f * d0, &s0, &c0);
+    sincospif(2.f * f * d1, &s1, &c1);
+    ramps[(size_t)b * 2 * N + u] = make_float2(c0, -s0);
+    ramps[(size_t)b * 2 * N + N + u] = make_float2(c1, -s1);
+  }
+}
+
+// ============================================================ row passes
+
+// Slice step of the forward model, row part (slice i = step):
+//   psi = IDFT_x(tile row) ; [checkpoint psi] ; phi = psi * O_i ; tile row = DFT_x(phi)
+// With FROM_REAL the entry wave is read from a real-space buffer (the start
+// of a recomputed segment) instead of inverse-transforming the tile.
+template <int N, bool FROM_REAL>
+__global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ items,
+                                                      const ReqTable reqs,
+                                                      float2* __restrict__ ws, float2* __restrict__ ck,
+                                                      const float2* __restrict__ twg, int step,
+                                                      PsiStore store) {
+  constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
+  __shared__ float2 tw[N];
+  __shared__ float2 xch[LINES * Xch<N>::SIZE];
+  const Item it = items[blockIdx.y];
+  const ReqDev& r = reqs.r[it.req];
+  const int i = step;
+  if (!it.valid || i >= r.S) return;
+  load_twiddles<N>(tw, twg);
+  __syncthreads();
+  const int l = threadIdx.x % L, line = threadIdx.x / L;
+  const int y = blockIdx.x * LINES + line;
+  float2* sx = xch + line * Xch<N>::SIZE;
+  // object patch row, shared by every mode
+  float2 o[E];
+  const float2* orow = r.obj + ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
+#pragma unroll
+  for (int a = 0; a < E; ++a) o[a] = orow[l + L * a];
+  const int n_ck = r.n_ck;
+  for (int m = 0; m < r.M; ++m) {
+    float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
+    float2 v[E];
+    if constexpr (FROM_REAL) {
+      const float2* src = store.src + (((size_t)it.ck0 + (size_t)m * n_ck + store.src_slot) * N + y) * N;
+#pragma unroll
+      for (int a = 0; a < E; ++a) v[a] = src[l + L * a];
+    } else {
+#pragma unroll
+      for (int a = 0; a < E; ++a) v[a] = trow[l + L * a];
+      line_fft<N, true>(v, l, tw, sx, WaveSync{});
+    }
+    if (store.mode == 1 && (i % r.ck_every) == 0) {
+      float2* dst = ck + (((size_t)it.ck0 + (size_t)m * n_ck + i / r.ck_every) * N + y) * N;
+#pragma unroll
+      for (int a = 0; a < E; ++a) dst[l + L * a] = v[a];
+    } else if (store.mode == 2) {
+      float2* dst = store.seg + (((size_t)(it.tile0 + m) * store.seg_len + store.seg_slot) * N + y) * N;
+#pragma unroll
+      for (int a = 0; a < E; ++a) dst[l + L * a] = v[a];
+    }
+    if (store.stop_after_store) continue;
+#pragma unroll
+    for (int a = 0; a < E; ++a) v[a] = cmul(v[a], o[a]);
+    line_fft<N, false>(v, l, tw, sx, WaveSync{});
+#pragma unroll
+    for (int a = 0; a < E; ++a) trow[l + L * a] = v[a];
+  }
+}
+
+// Adjoint slice step, row part (slice i = S - 1 - step for each item):
+//   g = IDFT_x(tile row)                (gradient wrt phi_i, real space)
+//   grad O_i += sum_m conj(psi_i,m) g   (scatter-added into the object gradient)
+//   h = conj(O_i) g ; tile row = DFT_x(h)
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ items,
+                                                      const ReqTable reqs,
+                                                      float2* __restrict__ ws, const float2* __restrict__ ck,
+                                                      const float2* __restrict__ twg, int step,
+                                                      PsiLoad psi, float scale) {
+  constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
+  __shared__ float2 tw[N];
+  __shared__ float2 xch[LINES * Xch<N>::SIZE];
+  const Item it = items[blockIdx.y];
+  const ReqDev& r = reqs.r[it.req];
+  const int i = r.S - 1 - step;
+  if (!it.valid || i < 0) return;
+  load_twiddles<N>(tw, twg);
+  __syncthreads();
+  const int l = threadIdx.x % L, line = threadIdx.x / L;
+  const int y = blockIdx.x * LINES + line;
+  float2* sx = xch + line * Xch<N>::SIZE;
+  float2 o[E], acc[E];
+  const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
+#pragma unroll
+  for (int a = 0; a < E; ++a) { o[a] = r.obj[orow + l + L * a]; acc[a] = make_float2(0.f, 0.f); }
+  for (int m = 0; m < r.M; ++m) {
+    float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
+    float2 v[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) v[a] = trow[l + L * a];
+    line_fft<N, true>(v, l, tw, sx, WaveSync{});
+    const float2* prow;
+    if (psi.from_seg) prow = psi.seg + (((size_t)(it.tile0 + m) * psi.seg_len + (i - psi.seg_base)) * N + y) * N;
+    else prow = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i / r.ck_every) * N + y) * N;
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      float2 p = prow[l + L * a];
+      acc[a] = cadd(acc[a], cjmul(p, v[a]));
+      v[a] = cjmul(o[a], v[a]);
+    }
+    line_fft<N, false>(v, l, tw, sx, WaveSync{});
+#pragma unroll
+    for (int a = 0; a < E; ++a) trow[l + L * a] = v[a];
+  }
+  if (r.gobj) {
+    float* g = reinterpret_cast<float*>(r.gobj + orow);
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      unsafeAtomicAdd(g + 2 * (l + L * a), scale * acc[a].x);
+      unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * acc[a].y);
+    }
+  }
+}
+
+// Plain row DFT of M probe-sized tiles: dst = DFT_x(src) (or inverse).
+template <int N, bool INV>
+__global__ __launch_bounds__(kThreads) void k_row_plain(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                        const float2* __restrict__ twg, float scale,
+                                                        int accumulate) {
+  constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
+  __shared__ float2 tw[N];
+  __shared__ float2 xch[LINES * Xch<N>::SIZE];
+  load_twiddles<N>(tw, twg);
+  __syncthreads();
+  const int l = threadIdx.x % L, line = threadIdx.x / L;
+  const int y = blockIdx.x * LINES + line;
+  const size_t base = ((size_t)blockIdx.y * N + y) * N;
+  float2 v[E];
+#pragma unroll
+  for (int a = 0; a < E; ++a) v[a] = src[base + l + L * a];
+  line_fft<N, INV>(v, l, tw, xch + line * Xch<N>::SIZE, WaveSync{});
+#pragma unroll
+  for (int a = 0; a < E; ++a) {
+    float2 w = cscale(v[a], scale);
+    if (accumulate) w = cadd(w, dst[base + l + L * a]);
+    dst[base + l + L * a] = w;
+  }
+}
+
+// ============================================================ column passes
+
+// Column-pass thread layout: thread t holds column c = t % CB of the block
+// and lane l = t / CB of that column's line, so that a load of register a
+// reads CB consecutive complex values of row l + L a (coalesced).
+template <int N> struct ColPass {
+  static constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
+  static constexpr int CB = kThreads / L;
+  static constexpr int NBLK = N / CB;
+};
+
+// Column passes over (item, mode) tiles:
+//   COL_SHIFT    tile = IDFT_y(phat_m * R_j) / N         (start of the forward model)
+//   COL_PROP     tile = IDFT_y(H_i * DFT_y(tile))        (forward, slice i = step < S-1)
+//   COL_PROP_ADJ tile = IDFT_y(conj(H_{i-1}) * DFT_y(tile)) (adjoint, i = S-1-step >= 1)
+//   COL_FINAL    tile = DFT_y(tile) / N = h_hat          (adjoint, i = 0) and the
+//                per-block sums of Im(conj(h_hat) phat R) u_a for the position gradient
+template <int N, int OP>
+__global__ __launch_bounds__(kThreads) void k_col(const Item* __restrict__ items,
+                                                  const ReqTable reqs,
+                                                  float2* __restrict__ ws, const float2* __restrict__ ramps,
+                                                  const float2* __restrict__ twg, int step,
+                                                  float* __restrict__ pos_part) {
+  constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
+  __shared__ float2 tw[N];
+  __shared__ float2 xch[CB * Xch<N>::SIZE];
+  __shared__ float red[2][kThreads / 64];
+  const int b = blockIdx.y, m = blockIdx.z;
+  const Item it = items[b];
+  const ReqDev& r = reqs.r[it.req];
+  if (!it.valid || m >= r.M) return;
+  int i = 0;
+  if constexpr (OP == COL_PROP) { i = step; if (i >= r.S - 1) return; }
+  if constexpr (OP == COL_PROP_ADJ) { i = r.S - 1 - step; if (i < 1) return; }
+  if constexpr (OP == COL_FINAL) { if (r.S - 1 - step != 0) return; }
+  load_twiddles<N>(tw, twg);
+  __syncthreads();
+  const int c = threadIdx.x % CB, l = threadIdx.x / CB;
+  const int ux = blockIdx.x * CB + c;
+  float2* sx = xch + c * Xch<N>::SIZE;
+  float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
+  float2 v[E];
+  if constexpr (OP == COL_SHIFT) {
+    const float2* ry = ramps + (size_t)b * 2 * N;
+    const float2 rx = ramps[(size_t)b * 2 * N + N + ux];
+    const float2* ph = r.phat + (size_t)m * N * N;
+    const float inv = 1.f / (float)N;
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      int uy = l + L * a;
+      v[a] = cscale(cmul(cmul(ph[(size_t)uy * N + ux], ry[uy]), rx), inv);
+    }
+    line_fft<N, true>(v, l, tw, sx, BlockSync{});
+  } else {
+#pragma unroll
+    for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
+    line_fft<N, false>(v, l, tw, sx, BlockSync{});
+    if constexpr (OP == COL_PROP || OP == COL_PROP_ADJ) {
+      const float2* H = r.prop + (size_t)(OP == COL_PROP ? i : i - 1) * N * N;
+#pragma unroll
+      for (int a = 0; a < E; ++a) {
+        float2 h = H[(size_t)(l + L * a) * N + ux];
+        v[a] = (OP == COL_PROP) ? cmul(v[a], h) : cjmul(h, v[a]);
+      }
+      line_fft<N, true>(v, l, tw, sx, BlockSync{});
+    } else {  // COL_FINAL
+      const float inv = 1.f / (float)N;
+      const float2* ry = ramps + (size_t)b * 2 * N;
+      const float2 rx = ramps[(size_t)b * 2 * N + N + ux];
+      const float2* ph = r.phat + (size_t)m * N * N;
+      const float fx = (float)((ux < (N + 1) / 2) ? ux : ux - N) / (float)N;
+      float sy = 0.f, sxx = 0.f;
+#pragma unroll
+      for (int a = 0; a < E; ++a) {
+        int uy = l + L * a;
+        v[a] = cscale(v[a], inv);
+        float2 A = cmul(cmul(ph[(size_t)uy * N + ux], ry[uy]), rx);
+        float2 z = cjmul(v[a], A);          // conj(h_hat) * A
+        float fy = (float)((uy < (N + 1) / 2) ? uy : uy - N) / (float)N;
+        sy += fy * z.y;
+        sxx += fx * z.y;
+      }
+      // block reduction of (sy, sxx)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        sy += __shfl_xor(sy, off);
+        sxx += __shfl_xor(sxx, off);
+      }
+      if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = sy; red[1][threadIdx.x >> 6] = sxx; }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float t0 = 0.f, t1 = 0.f;
+        for (int w = 0; w < kThreads / 64; ++w) { t0 += red[0][w]; t1 += red[1][w]; }
+        float* dst = pos_part + ((size_t)(it.tile0 + m) * ColPass<N>::NBLK + blockIdx.x) * 2;
+        dst[0] = t0;
+        dst[1] = t1;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = v[a];
+}
+
+// Plain column DFT of M probe-sized tiles (in place): tile = scale * DFT_y(tile).
+template <int N, bool INV>
+__global__ __launch_bounds__(kThreads) void k_col_plain(float2* __restrict__ t, const float2* __restrict__ twg,
+                                                        float scale) {
+  constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
+  __shared__ float2 tw[N];
+  __shared__ float2 xch[CB * Xch<N>::SIZE];
+  load_twiddles<N>(tw, twg);
+  __syncthreads();
+  const int c = threadIdx.x % CB, l = threadIdx.x / CB;
+  const int ux = blockIdx.x * CB + c;
+  float2* tile = t + (size_t)blockIdx.y * N * N;
+  float2 v[E];
+#pragma unroll
+  for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
+  line_fft<N, INV>(v, l, tw, xch + c * Xch<N>::SIZE, BlockSync{});
+#pragma unroll
+  for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = cscale(v[a], scale);
+}
+
+// ============================================================ far field + loss
+
+__device__ __forceinline__ void loss_weight(int kind, float I, float Ie, float eps, float inv_sigma2,
+                                            float& ell, float& w) {
+  if (kind == PTY_LOSS_POISSON) {
+    if (Ie == 0.f) {
+      ell = I;
+      w = 2.f;
+    } else {
+      // I - Ie - Ie (ln(I+eps) - ln(Ie+eps)), the log ratio as log1p for accuracy;
+      // invalid counts (negative, NaN) give a non-finite loss and raise the flag
+      float den = Ie + eps;
+      ell = (I - Ie) - Ie * log1pf((I - Ie) / den);
+      w = 2.f * (1.f - Ie / (I + eps));
+    }
+  } else if (kind == PTY_LOSS_GAUSSIAN) {
+    float d = I - Ie;
+    ell = 0.5f * d * d * inv_sigma2;
+    w = 2.f * d * inv_sigma2;
+  } else {
+    float c = (kind == PTY_LOSS_ANSCOMBE) ? 0.375f : 0.f;
+    float a = sqrtf(I + c), ae = sqrtf(Ie + c);
+    ell = 0.5f * (a - ae) * (a - ae);
+    float den = eps + a;
+    w = (den > 0.f) ? 1.f - ae / den : 0.f;
+  }
+}
+
+// Far field of the last slice, incoherent mode sum and noise model, per
+// (item, column block), looping over modes:
+//   Psi_m = DFT_y(tile_m) / N ; I = sum_m |Psi_m|^2 ; (l, w) from (I, Ie)
+// then, if GRAD, the first adjoint step for every mode:
+//   tile_m = IDFT_y(w * Psi_m) / N
+// Writes intensities (if requested) and per-block loss partial sums.
+template <int N, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_far_loss(const Item* __restrict__ items,
+                                                       const ReqTable reqs,
+                                                       float2* __restrict__ ws, const float2* __restrict__ twg,
+                                                       int step, float* __restrict__ loss_part, int* flags) {
+  constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
+  __shared__ float2 tw[N];
+  __shared__ float2 xch[CB * Xch<N>::SIZE];
+  __shared__ float red[kThreads / 64];
+  const int b = blockIdx.y;
+  const Item it = items[b];
+  const ReqDev& r = reqs.r[it.req];
+  if (step != r.S - 1) return;
+  const int c = threadIdx.x % CB, l = threadIdx.x / CB;
+  const int ux = blockIdx.x * CB + c;
+  if (!it.valid) {
+    if (r.I_out) {
+      float* Io = r.I_out + (size_t)(b - r.item0) * N * N;
+#pragma unroll
+      for (int a = 0; a < E; ++a) Io[(size_t)(l + L * a) * N + ux] = 0.f;
+    }
+    if (threadIdx.x == 0) loss_part[(size_t)b * ColPass<N>::NBLK + blockIdx.x] = 0.f;
+    return;
+  }
+  load_twiddles<N>(tw, twg);
+  __syncthreads();
+  float2* sx = xch + c * Xch<N>::SIZE;
+  const float inv = 1.f / (float)N;
+  float I[E];
+#pragma unroll
+  for (int a = 0; a < E; ++a) I[a] = 0.f;
+  for (int m = 0; m < r.M; ++m) {
+    float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
+    float2 v[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
+    line_fft<N, false>(v, l, tw, sx, BlockSync{});
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      v[a] = cscale(v[a], inv);
+      I[a] += cabs2(v[a]);
+      if (GRAD) tile[(size_t)(l + L * a) * N + ux] = v[a];
+    }
+  }
+  float wgt[E];
+  float lsum = 0.f;
+  bool bad = false;
+  const float* pat = r.patterns ? r.patterns + (size_t)it.j * N * N : nullptr;
+#pragma unroll
+  for (int a = 0; a < E; ++a) {
+    size_t p = (size_t)(l + L * a) * N + ux;
+    float ell = 0.f, w = 0.f;
+    if (pat) loss_weight(r.loss, I[a], pat[p], r.eps, r.inv_sigma2, ell, w);
+    wgt[a] = w;
+    lsum += ell;
+    bad |= !isfinite(ell) || !isfinite(w);
+  }
+  if (r.I_out) {
+    float* Io = r.I_out + (size_t)(b - r.item0) * N * N;
+#pragma unroll
+    for (int a = 0; a < E; ++a) Io[(size_t)(l + L * a) * N + ux] = I[a];
+  }
+  if (bad) raise_flag(flags, kFlagNonFinite);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+    loss_part[(size_t)b * ColPass<N>::NBLK + blockIdx.x] = t;
+  }
+  if constexpr (GRAD) {
+    for (int m = 0; m < r.M; ++m) {
+      float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
+      float2 v[E];
+#pragma unroll
+      for (int a = 0; a < E; ++a) v[a] = cscale(tile[(size_t)(l + L * a) * N + ux], wgt[a] * inv);
+      line_fft<N, true>(v, l, tw, sx, BlockSync{});
+#pragma unroll
+      for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = v[a];
+    }
+  }
+}
+
+// ============================================================ reductions
+
+// Per request: loss = sum over its items and blocks (double).
+__global__ void k_loss_reduce(const ReqTable reqs, const float* __restrict__ loss_part, int nblk) {
+  const ReqDev& r = reqs.r[blockIdx.x];
+  __shared__ double red[kThreads];
+  double acc = 0.0;
+  for (int b = r.item0; b < r.item0 + r.n_items; ++b) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) s += (double)loss_part[(size_t)b * nblk + k];
+    acc += s;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && r.loss_out) *r.loss_out = red[0];
+}
+
+// Probe-spectrum gradient per request: gphat_m(u) = scale * sum_b h_hat_{b,m}(u) conj(R_b(u)).
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_probe_grad(const Item* __restrict__ items,
+                                                         const ReqTable reqs,
+                                                         const float2* __restrict__ ws,
+                                                         const float2* __restrict__ ramps, float scale) {
+  const ReqDev& r = reqs.r[blockIdx.z];
+  const int m = blockIdx.y;
+  if (m >= r.M || !r.gphat) return;
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  const int uy = p / N, ux = p % N;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int b = r.item0; b < r.item0 + r.n_items; ++b) {
+    const Item it = items[b];
+    if (!it.valid) continue;
+    float2 R = cmul(ramps[(size_t)b * 2 * N + uy], ramps[(size_t)b * 2 * N + N + ux]);
+    float2 h = ws[(size_t)(it.tile0 + m) * N * N + p];
+    acc = cadd(acc, cmul(h, cconj(R)));
+  }
+  r.gphat[(size_t)m * N * N + p] = cscale(acc, scale);
+}
+
+// Per item: dL/dX = 2 pi * scale * sum over modes and blocks of the partials;
+// written to g_pos[local] (per batch entry) and/or added to a dense [J][2] gradient.
+__global__ void k_pos_reduce(const Item* __restrict__ items, const ReqTable reqs,
+                             const float* __restrict__ pos_part, int nblk, int n_items, float scale) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_items) return;
+  const Item it = items[b];
+  const ReqDev& r = reqs.r[it.req];
+  float g0 = 0.f, g1 = 0.f;
+  if (it.valid) {
+    for (int m = 0; m < r.M; ++m)
+      for (int k = 0; k < nblk; ++k) {
+        const float* p = pos_part + ((size_t)(it.tile0 + m) * nblk + k) * 2;
+        g0 += p[0];
+        g1 += p[1];
+      }
+  }
+  const float f = 6.283185307179586f * scale;
+  g0 *= f;
+  g1 *= f;
+  int local = b - r.item0;
+  if (r.gpos) {
+    if (r.accumulate) { r.gpos[2 * local] += g0; r.gpos[2 * local + 1] += g1; }
+    else { r.gpos[2 * local] = g0; r.gpos[2 * local + 1] = g1; }
+  }
+  if (r.gpos_dense && it.valid) {
+    atomicAdd(r.gpos_dense + 2 * it.j, g0);
+    atomicAdd(r.gpos_dense + 2 * it.j + 1, g1);
+  }
+}
+
+// ============================================================ elementwise
+
+__global__ void k_fill(float* __restrict__ p, size_t n, float v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_sgd(float* __restrict__ th, const float* __restrict__ g, size_t n, float lr) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) th[i] -= lr * g[i];
+}
+
+// Adam per real component: m = b1 m + (1-b1) g ; v = b2 v + (1-b2) g^2 ;
+// th -= step_size * m / (sqrt(v) * inv_sqrt_bc2 + eps), step_size = lr / (1 - b1^t).
+__global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ mo,
+                       float* __restrict__ ve, size_t n, float step_size, float inv_sqrt_bc2, float b1,
+                       float b2, float eps) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    float gi = g[i];
+    float m = b1 * mo[i] + (1.f - b1) * gi;
+    float v = b2 * ve[i] + (1.f - b2) * gi * gi;
+    mo[i] = m;
+    ve[i] = v;
+    th[i] -= step_size * m / (sqrtf(v) * inv_sqrt_bc2 + eps);
+  }
+}
+
+// ============================================================ launchers
+
+static inline dim3 grid1(size_t n) {
+  size_t b = (n + kThreads - 1) / kThreads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+template <int N>
+struct Launch {
+  static void rows_fwd(const LaunchCtx& L, int step, PsiStore st, bool from_real) {
+    dim3 g(Pass<N>::NBLK, L.n_items);
+    if (from_real)
+      hipLaunchKernelGGL((k_row_fwd<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st);
+    else
+      hipLaunchKernelGGL((k_row_fwd<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st);
+  }
+  static void rows_adj(const LaunchCtx& L, int step, PsiLoad psi, float scale) {
+    dim3 g(Pass<N>::NBLK, L.n_items);
+    hipLaunchKernelGGL((k_row_adj<N>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale);
+  }
+  static void col(const LaunchCtx& L, int op, int step) {
+    dim3 g(ColPass<N>::NBLK, L.n_items, L.max_modes);
+    switch (op) {
+      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
+      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
+      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
+      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
+    }
+  }
+  static void far_loss(const LaunchCtx& L, int step, bool grad) {
+    dim3 g(ColPass<N>::NBLK, L.n_items);
+    if (grad)
+      hipLaunchKernelGGL((k_far_loss<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.tw, step, L.loss_part, L.flags);
+    else
+      hipLaunchKernelGGL((k_far_loss<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.tw, step, L.loss_part, L.flags);
+  }
+  static void probe_grad(const LaunchCtx& L, float scale) {
+    dim3 g(N * N / kThreads, L.max_modes, L.n_reqs);
+    hipLaunchKernelGGL((k_probe_grad<N>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, scale);
+  }
+  static void plain2d(hipStream_t s, const float2* tw, const float2* src, float2* dst, int n_tiles, bool inverse,
+                      float scale, bool accumulate) {
+    // forward: rows then columns ; inverse: columns then rows (in place on dst)
+    dim3 gr(Pass<N>::NBLK, n_tiles), gc(ColPass<N>::NBLK, n_tiles);
+    if (!inverse) {
+      hipLaunchKernelGGL((k_row_plain<N, false>), gr, dim3(kThreads), 0, s, src, dst, tw, 1.f, 0);
+      hipLaunchKernelGGL((k_col_plain<N, false>), gc, dim3(kThreads), 0, s, dst, tw, scale);
+    } else {
+      // columns in place on a copy living in dst is not possible when accumulating:
+      // the caller passes src as scratch that may be overwritten.
+      hipLaunchKernelGGL((k_col_plain<N, true>), gc, dim3(kThreads), 0, s, const_cast<float2*>(src), tw, scale);
+      hipLaunchKernelGGL((k_row_plain<N, true>), gr, dim3(kThreads), 0, s, src, dst, tw, 1.f, accumulate ? 1 : 0);
+    }
+  }
+};
+
+void launch_items(const LaunchCtx& L, int N) {
+  hipLaunchKernelGGL(k_items, dim3(L.n_items), dim3(64), 0, L.stream, L.reqs, L.n_reqs, L.items, L.ramps,
+                     L.n_items, N, L.flags);
+}
+
+#define PTY_DISPATCH(N, CALL)                    \
+  switch (N) {                                   \
+    case 64: Launch<64>::CALL; break;            \
+    case 128: Launch<128>::CALL; break;          \
+    case 192: Launch<192>::CALL; break;          \
+    default: Launch<256>::CALL; break;           \
+  }
+
+void launch_rows_fwd(const LaunchCtx& L, int N, int step, PsiStore st, bool from_real) {
+  PTY_DISPATCH(N, rows_fwd(L, step, st, from_real));
+}
+void launch_rows_adj(const LaunchCtx& L, int N, int step, PsiLoad psi, float scale) {
+  PTY_DISPATCH(N, rows_adj(L, step, psi, scale));
+}
+void launch_col(const LaunchCtx& L, int N, int op, int step) { PTY_DISPATCH(N, col(L, op, step)); }
+void launch_far_loss(const LaunchCtx& L, int N, int step, bool grad) { PTY_DISPATCH(N, far_loss(L, step, grad)); }
+void launch_probe_grad(const LaunchCtx& L, int N, float scale) { PTY_DISPATCH(N, probe_grad(L, scale)); }
+void launch_plain2d(int N, hipStream_t s, const float2* tw, const float2* src, float2* dst, int n_tiles,
+                    bool inverse, float scale, bool accumulate) {
+  PTY_DISPATCH(N, plain2d(s, tw, src, dst, n_tiles, inverse, scale, accumulate));
+}
+void launch_loss_reduce(const LaunchCtx& L, int N) {
+  hipLaunchKernelGGL(k_loss_reduce, dim3(L.n_reqs), dim3(kThreads), 0, L.stream, L.reqs, L.loss_part,
+                     col_blocks(N));
+}
+void launch_pos_reduce(const LaunchCtx& L, int N, float scale) {
+  hipLaunchKernelGGL(k_pos_reduce, dim3((L.n_items + 127) / 128), dim3(128), 0, L.stream, L.items, L.reqs,
+                     L.pos_part, col_blocks(N), L.n_items, scale);
+}
+void launch_fill(hipStream_t s, float* p, size_t n, float v) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill, grid1(n), dim3(kThreads), 0, s, p, n, v);
+}
+void launch_sgd(hipStream_t s, float* th, const float* g, size_t n, float lr) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_sgd, grid1(n), dim3(kThreads), 0, s, th, g, n, lr);
+}
+void launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, size_t n, float step_size,
+                 float inv_sqrt_bc2, float b1, float b2, float eps) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_adam, grid1(n), dim3(kThreads), 0, s, th, g, m, v, n, step_size, inv_sqrt_bc2, b1, b2, eps);
+}
+int col_blocks(int N) {
+  return N == 256 ? ColPass<256>::NBLK : N == 192 ? ColPass<192>::NBLK : N == 128 ? ColPass<128>::NBLK : ColPass<64>::NBLK;
+}
+
+}  // namespace pty
