@@ -1,0 +1,216 @@
+"""Throughput of the hot path on one MI355X: probe positions per second of one
+gradient iteration (forward model, noise-model loss, exact adjoint to object,
+probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 512]
+                    [--no-cpu-baseline] [--cpu-positions 8]
+
+A step is one reconstruct_step over one group of `batch` positions drawn
+from a seeded permutation of the 128 x 128 scan (16384 positions = 32 groups
+per epoch), with every input resident in HBM before the timed region.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "probe positions/s per fwd+adjoint iteration (256², 8 modes, 30 slices); p50/p99"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=32)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--batch", type=int, default=512)
+    p.add_argument("--workload", default="cfg3_ms256")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-positions", type=int, default=8)
+    p.add_argument("--checkpoint-every", type=int, default=1)
+    return p.parse_args()
+
+
+def kernel_bytes_per_launch(name, N, M, B, S):
+    """Algorithmic HBM bytes one launch of a kernel class must move (complex64
+    tile T = 8 N^2 bytes, per launch over B positions and M modes)."""
+    T = 8 * N * N
+    if name == "row_fwd":      # read + write every mode tile, write the entry-wave checkpoint, read the object patch
+        return B * (3 * M + 1) * T
+    if name == "row_adj":      # read + write tiles, read checkpoints, read object patch, RMW object gradient
+        return B * (3 * M + 3) * T
+    if name in ("col_prop", "col_prop_adj"):   # read + write every tile
+        return B * 2 * M * T
+    if name == "far_loss":     # tiles read, far field written and re-read, seed written; pattern read
+        return B * (4 * M * T + T // 2)
+    if name == "col_shift":    # write every tile (the probe spectrum stays in cache)
+        return B * M * T
+    if name == "col_final":    # read + write every tile
+        return B * 2 * M * T
+    if name == "probe_grad":   # read every tile
+        return B * M * T
+    return 0
+
+
+def kernel_flops_per_launch(name, N, M, B, S):
+    """FFT flops of one launch by the 5 n log2 n convention per 1D transform."""
+    per_line = 5 * N * np.log2(N)
+    lines = B * M * N
+    n_fft = {"row_fwd": 2, "row_adj": 2, "col_prop": 2, "col_prop_adj": 2, "far_loss": 2, "col_shift": 1,
+             "col_final": 1}.get(name, 0)
+    return n_fft * lines * per_line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (how the path would shard "
+                                   "over GPUs is described in the design notes)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2505_14372_amd import _lib, api, synth
+
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    t0 = time.time()
+    wl = synth.make_workload(args.workload, pattern_pool=64)
+    N, M, S, H, W, J = wl.N, wl.M, wl.S, wl.H, wl.W, wl.J
+    B = args.batch
+    print(f"[bench] inputs built in {time.time() - t0:.1f}s: N={N} M={M} S={S} object {H}x{W}x{S} J={J} B={B}",
+          file=sys.stderr, flush=True)
+    probe = torch.from_numpy(wl.probe.astype(np.complex64)).to(dev)
+    obj = torch.from_numpy(wl.obj.astype(np.complex64)).to(dev)
+    pos = torch.from_numpy(wl.positions.astype(np.float32)).to(dev)
+    pats = torch.empty((J, N, N), dtype=torch.float32, device=dev)
+    chunk = 1024
+    for s0 in range(0, J, chunk):
+        pats[s0:s0 + chunk].copy_(torch.from_numpy(wl.patterns[s0:s0 + chunk]))
+    prob = api.Problem(N, M, S, H, W, J, dz=wl.dz, dx=wl.dx, wavelength=wl.wavelength, loss=wl.loss, eps=wl.eps,
+                       max_batch=B, checkpoint_every=args.checkpoint_every)
+    state = api.ReconState(probe, obj, pos, adam=True)
+    opt = api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2)
+    rng = np.random.default_rng(12345)
+    n_groups = J // B
+
+    def groups():
+        while True:
+            perm = rng.permutation(J).astype(np.int32)
+            for g in range(n_groups):
+                yield torch.from_numpy(np.sort(perm[g * B:(g + 1) * B])).to(dev)
+
+    gen = groups()
+    batches = [next(gen) for _ in range(args.warmup + args.steps)]
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        prob.reconstruct_step(state, pats, batches[w], opt, loss)
+        print(f"[bench] warmup step {w} done", file=sys.stderr, flush=True)
+    prob.check()
+    torch.cuda.synchronize()
+
+    lib = _lib.load()
+    lib.pty_profile_enable(1)
+    lib.pty_profile_collect(None, 0, None, None, 0)   # drop anything recorded before
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        prob.reconstruct_step(state, pats, batches[args.warmup + k], opt, loss)
+        ends[k].record(stream)
+        if (k + 1) % 8 == 0:
+            print(f"[bench] timed step {k + 1}/{args.steps} queued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    lib.pty_profile_enable(0)
+    names = C.create_string_buffer(4096)
+    tot = (C.c_double * 64)()
+    cnt = (C.c_int64 * 64)()
+    n_cls = lib.pty_profile_collect(names, 4096, tot, cnt, 64)
+    prof = {nm: (tot[i], cnt[i]) for i, nm in enumerate(names.value.decode().split("\n")[:n_cls])}
+    prob.check()
+    step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    ms_per_step = t_total * 1000.0 / args.steps
+    value = B * args.steps / t_total
+    p50, p99 = np.percentile(step_ms, 50), np.percentile(step_ms, 99)
+
+    # dominant kernel class and its roofline
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    avg_s = dom_ms / dom_n / 1000.0
+    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S)
+    flops_launch = kernel_flops_per_launch(dom, N, M, B, S)
+    gbs = bytes_launch / avg_s / 1e9
+    tfl = flops_launch / avg_s / 1e12
+    if gbs / HBM_PEAK_GBS >= tfl / FP32_PEAK_TFLOPS:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
+    roof.update({"kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4), "traffic": None})
+    kernels = {k: {"total_ms": round(v[0], 3), "launches": int(v[1]), "avg_ms": round(v[0] / v[1], 4),
+                   "share": round(v[0] / sum(x[0] for x in prof.values()), 4)} for k, v in prof.items()}
+    flop_pos = 4 * S * M * 5 * N * N * np.log2(N * N)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: probe {N}x{N}, {M} modes, {S} slices of {wl.dz[0] if S > 1 else 0} A, "
+                               f"object {H}x{W}x{S} complex64, {J} positions, groups of {B}, Poisson loss, Adam",
+                   "global_batch": B, "checkpoint_every": prob.checkpoint_every},
+        "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
+        "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
+        "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),
+        "roofline": roof, "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_positions)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, n_pos):
+    """The FP64 oracle on the host: loss and gradients of a small group of the same workload."""
+    import oracle as orc
+    geom = orc.Geometry(N=wl.N, dx=wl.dx, wavelength=wl.wavelength, dz=list(wl.dz), bandlimit=wl.bandlimit,
+                        loss=wl.loss, eps=wl.eps, sigma=wl.sigma)
+    idx = list(range(0, wl.J, max(1, wl.J // n_pos)))[:n_pos]
+    P = wl.probe.astype(np.complex64).astype(np.complex128)
+    O = wl.obj.astype(np.complex64).astype(np.complex128)
+    X = wl.positions.astype(np.float32).astype(np.float64)
+    pats = {j: wl.patterns[j].astype(np.float64) for j in idx}
+    patt = _PatternView(pats)
+    t0 = time.perf_counter()
+    orc.loss_and_grad(P, O, X, patt, idx, geom)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(idx) / dt, 3), "unit": "positions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(idx)} positions of the same workload (all {wl.M} modes, {wl.S} slices), one "
+                      f"loss_and_grad group, numpy FP64 single-threaded, {dt:.1f} s"}
+
+
+class _PatternView:
+    """Index-only view of the sampled patterns (the oracle reads patterns[j])."""
+
+    def __init__(self, d):
+        self.d = d
+
+    def __getitem__(self, j):
+        return self.d[int(j)]
+
+
+if __name__ == "__main__":
+    main()

@@ -215,6 +215,17 @@ pty_status pty_group_reconstruct_step(pty_group* grp, void* stream, const pty_gr
 const char* pty_group_last_error(const pty_group* grp);
 void pty_group_destroy(pty_group* grp);
 
+/* ---- launch timing ------------------------------------------------------
+ * When enabled (process-wide), every kernel launch of the library is
+ * bracketed by two hipEvents on the stream it is launched on, grouped by
+ * kernel class ("row_fwd", "col_prop", "row_adj", ...). pty_profile_collect
+ * waits for the recorded events, writes up to max_entries classes (names
+ * separated by '\n' into names, total milliseconds and launch counts) and
+ * resets the totals; it returns the number of classes written. */
+void pty_profile_enable(int32_t on);
+int32_t pty_profile_collect(char* names, size_t names_len, double* total_ms, int64_t* counts,
+                            int32_t max_entries);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,7 @@ EXPORTS = (
     "pty_create", "pty_workspace_bytes", "pty_checkpoint_every", "pty_forward", "pty_loss_and_grad",
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
-    "pty_group_last_error", "pty_group_destroy",
+    "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
 )
 
 
@@ -89,6 +89,8 @@ def load():
         "pty_group_reconstruct_step": ([vp, vp, C.POINTER(GroupItem), i32], i32),
         "pty_group_last_error": ([vp], C.c_char_p),
         "pty_group_destroy": ([vp], None),
+        "pty_profile_enable": ([i32], None),
+        "pty_profile_collect": ([C.c_char_p, sz, C.POINTER(f64), C.POINTER(i64), i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

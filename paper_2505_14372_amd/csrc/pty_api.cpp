@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -122,6 +123,54 @@ pty_status validate_geometry(const pty_geometry* g, std::string& err) {
   return PTY_OK;
 }
 
+
+// ---------------------------------------------------------------- launch timing
+// Optional per-kernel-class timing: when enabled, every launch is bracketed by
+// two hipEvents on its own stream; pty_profile_collect() waits for them and
+// returns total milliseconds and launch counts per class.
+enum ProfClass {
+  P_ITEMS, P_COL_SHIFT, P_ROW_FWD, P_COL_PROP, P_FAR_LOSS, P_LOSS_REDUCE, P_ROW_ADJ, P_COL_PROP_ADJ,
+  P_COL_FINAL, P_PROBE_GRAD, P_POS_REDUCE, P_PLAIN2D, P_FILL, P_OPTIM, P_RECOMPUTE, P_NCLASS
+};
+const char* kProfNames[P_NCLASS] = {"items", "col_shift", "row_fwd", "col_prop", "far_loss", "loss_reduce",
+                                    "row_adj", "col_prop_adj", "col_final", "probe_grad", "pos_reduce",
+                                    "plain2d", "fill", "optimizer", "recompute"};
+
+struct ProfRec { int cls; hipEvent_t a, b; };
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[P_NCLASS] = {};
+  long long count[P_NCLASS] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler g_prof;
+
+struct ProfScope {
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    a = g_prof.get();
+    if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+  }
+  ~ProfScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    hipEvent_t b = g_prof.get();
+    if (b && hipEventRecord(b, s) == hipSuccess) g_prof.pending.push_back({cls, a, b});
+  }
+};
 }  // namespace
 
 struct pty_ctx {
@@ -206,16 +255,19 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
 // seed (after its inverse column DFT) in the workspace.
 void run_forward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& far_steps, bool save,
                  bool want_loss) {
-  launch_items(L, N);
-  launch_col(L, N, COL_SHIFT, 0);
+  { ProfScope p(P_ITEMS, L.stream); launch_items(L, N); }
+  { ProfScope p(P_COL_SHIFT, L.stream); launch_col(L, N, COL_SHIFT, 0); }
   PsiStore st{};
   st.mode = save ? 1 : 0;
   for (int i = 0; i < S_max; ++i) {
-    launch_rows_fwd(L, N, i, st, false);
-    if (i < S_max - 1) launch_col(L, N, COL_PROP, i);
-    if (std::find(far_steps.begin(), far_steps.end(), i) != far_steps.end()) launch_far_loss(L, N, i, save);
+    { ProfScope p(P_ROW_FWD, L.stream); launch_rows_fwd(L, N, i, st, false); }
+    if (i < S_max - 1) { ProfScope p(P_COL_PROP, L.stream); launch_col(L, N, COL_PROP, i); }
+    if (std::find(far_steps.begin(), far_steps.end(), i) != far_steps.end()) {
+      ProfScope p(P_FAR_LOSS, L.stream);
+      launch_far_loss(L, N, i, save);
+    }
   }
-  if (want_loss) launch_loss_reduce(L, N);
+  if (want_loss) { ProfScope p(P_LOSS_REDUCE, L.stream); launch_loss_reduce(L, N); }
 }
 
 // Adjoint sequence (after run_forward with save). Single-request contexts may
@@ -237,6 +289,7 @@ void run_backward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& 
         st.mode = 0;
         st.src = L.ck;
         st.src_slot = i0 / k;
+        ProfScope p(P_RECOMPUTE, L.stream);
         launch_rows_fwd(R, N, i0, st, true);
         for (int s = i0 + 1; s <= i1; ++s) {
           launch_col(R, N, COL_PROP, s - 1);
@@ -256,12 +309,15 @@ void run_backward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& 
       psi.seg_len = k - 1;
       psi.seg_base = i0 + 1;
     }
-    launch_rows_adj(L, N, t, psi, scale);
-    launch_col(L, N, COL_PROP_ADJ, t);
-    if (std::find(final_steps.begin(), final_steps.end(), t) != final_steps.end()) launch_col(L, N, COL_FINAL, t);
+    { ProfScope p(P_ROW_ADJ, L.stream); launch_rows_adj(L, N, t, psi, scale); }
+    if (t < S_max - 1) { ProfScope p(P_COL_PROP_ADJ, L.stream); launch_col(L, N, COL_PROP_ADJ, t); }
+    if (std::find(final_steps.begin(), final_steps.end(), t) != final_steps.end()) {
+      ProfScope p(P_COL_FINAL, L.stream);
+      launch_col(L, N, COL_FINAL, t);
+    }
   }
-  launch_probe_grad(L, N, scale);
-  launch_pos_reduce(L, N, scale);
+  { ProfScope p(P_PROBE_GRAD, L.stream); launch_probe_grad(L, N, scale); }
+  { ProfScope p(P_POS_REDUCE, L.stream); launch_pos_reduce(L, N, scale); }
 }
 
 pty_status check_call(pty_ctx* c, const void* probe, const void* object, const void* positions,
@@ -377,7 +433,7 @@ pty_status pty_forward(pty_ctx* c, void* stream, const pty_c64* probe, const pty
   hipStream_t s = (hipStream_t)stream;
   c->tape_valid = false;
   const int N = c->g.N, S = c->g.n_slices;
-  launch_plain2d(N, s, c->tw, (const float2*)probe, c->phat, c->g.n_modes, false, 1.f / N, false);
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, (const float2*)probe, c->phat, c->g.n_modes, false, 1.f / N, false); }
   ReqDev r = base_req(c);
   r.obj = (const float2*)object;
   r.positions = positions;
@@ -400,7 +456,7 @@ pty_status pty_forward_save(pty_ctx* c, void* stream, const pty_c64* probe, cons
   hipStream_t s = (hipStream_t)stream;
   c->tape_valid = false;
   const int N = c->g.N, S = c->g.n_slices;
-  launch_plain2d(N, s, c->tw, (const float2*)probe, c->phat, c->g.n_modes, false, 1.f / N, false);
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, (const float2*)probe, c->phat, c->g.n_modes, false, 1.f / N, false); }
   ReqDev r = base_req(c);
   r.obj = (const float2*)object;
   r.positions = positions;
@@ -433,11 +489,13 @@ pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_
   r.I_out = nullptr;
   r.loss_out = nullptr;
   r.gphat = g_probe ? c->gphat : nullptr;
-  if (g_object && !acc)
+  if (g_object && !acc) {
+    ProfScope p(P_FILL, s);
     launch_fill(s, (float*)g_object, (size_t)S * c->g.obj_h * c->g.obj_w * 2, 0.f);
+  }
   run_backward(L, N, S, {S - 1}, (float)grad_scale, c->ck_every, c->ws2, c->seg);
   if (g_probe)
-    launch_plain2d(N, s, c->tw, c->gphat, (float2*)g_probe, c->g.n_modes, true, 1.f / N, acc);
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, (float2*)g_probe, c->g.n_modes, true, 1.f / N, acc); }
   c->tape_valid = false;
   HIPCHECK(c, hipGetLastError());
   return PTY_OK;
@@ -483,6 +541,7 @@ pty_status check_state(pty_ctx* c, const pty_state* st, const pty_optim* o) {
 }
 
 void apply_optimizer(pty_ctx* c, hipStream_t s, pty_state* st, const pty_optim* o) {
+  ProfScope p(P_OPTIM, s);
   const pty_geometry& g = c->g;
   const size_t nO = (size_t)g.n_slices * g.obj_h * g.obj_w * 2;
   const size_t nP = (size_t)g.n_modes * g.N * g.N * 2;
@@ -514,10 +573,13 @@ extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* 
   r.gphat = c->gphat;
   r.I_out = nullptr;
   r.loss_out = nullptr;
-  launch_fill(s, (float*)c->gobj, (size_t)S * g.obj_h * g.obj_w * 2, 0.f);
-  launch_fill(s, c->gpos, (size_t)g.n_positions * 2, 0.f);
+  {
+    ProfScope p(P_FILL, s);
+    launch_fill(s, (float*)c->gobj, (size_t)S * g.obj_h * g.obj_w * 2, 0.f);
+    launch_fill(s, c->gpos, (size_t)g.n_positions * 2, 0.f);
+  }
   run_backward(L, N, S, {S - 1}, 1.f, c->ck_every, c->ws2, c->seg);
-  launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, g.n_modes, true, 1.f / N, false);
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, g.n_modes, true, 1.f / N, false); }
   c->tape_valid = false;
   apply_optimizer(c, s, st, o);
   HIPCHECK(c, hipGetLastError());
@@ -671,3 +733,45 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
 }
 
 }  // extern "C"
+
+extern "C" void pty_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+}
+
+extern "C" int32_t pty_profile_collect(char* names, size_t names_len, double* total_ms, int64_t* counts,
+                                       int32_t max_entries) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (const ProfRec& r : g_prof.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      g_prof.total_ms[r.cls] += ms;
+      g_prof.count[r.cls] += 1;
+    }
+    g_prof.pool.push_back(r.a);
+    g_prof.pool.push_back(r.b);
+  }
+  g_prof.pending.clear();
+  std::string all;
+  int n = 0;
+  for (int k = 0; k < P_NCLASS; ++k) {
+    if (g_prof.count[k] == 0) continue;
+    if (n < max_entries && total_ms && counts) {
+      total_ms[n] = g_prof.total_ms[k];
+      counts[n] = g_prof.count[k];
+    }
+    if (n < max_entries) {
+      all += kProfNames[k];
+      all += '\n';
+    }
+    ++n;
+    g_prof.total_ms[k] = 0.0;
+    g_prof.count[k] = 0;
+  }
+  if (names && names_len > 0) {
+    size_t m = std::min(all.size(), names_len - 1);
+    std::memcpy(names, all.data(), m);
+    names[m] = '\0';
+  }
+  return std::min(n, max_entries);
+}
