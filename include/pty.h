@@ -120,6 +120,14 @@ pty_status pty_workspace_bytes(const pty_geometry* g, int32_t max_batch, int32_t
 /* Checkpoint interval chosen at create (1 = store all). */
 int32_t pty_checkpoint_every(const pty_ctx* ctx);
 
+/* Schedule of pty_loss_and_grad and pty_reconstruct_step: the group is taken
+ * through the forward and adjoint passes in consecutive chunks of
+ * `positions` batch entries, one chunk after the other, so that a chunk's
+ * work tiles can stay in the last-level cache between passes; 0 (the
+ * default) processes the whole group in every launch. Results do not depend
+ * on the chunk size beyond the order of floating-point atomic additions. */
+pty_status pty_set_chunk(pty_ctx* ctx, int32_t positions);
+
 /* Forward model (Sec. 3) for the positions batch_idx[0..batch) (device int32,
  * values in [0, J)). probe [M][N][N], object [S][H][W], positions [J][2]
  * float32 (row, col). Writes intensities [batch][N][N] (FFT order) if not

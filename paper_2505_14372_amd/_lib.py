@@ -20,7 +20,7 @@ PTY_ACCUMULATE = 1
 
 # every exported symbol of include/pty.h
 EXPORTS = (
-    "pty_create", "pty_workspace_bytes", "pty_checkpoint_every", "pty_forward", "pty_loss_and_grad",
+    "pty_create", "pty_workspace_bytes", "pty_checkpoint_every", "pty_set_chunk", "pty_forward", "pty_loss_and_grad",
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
@@ -76,6 +76,7 @@ def load():
         "pty_create": ([C.POINTER(Geometry), i32, i32, sz, C.POINTER(vp)], i32),
         "pty_workspace_bytes": ([C.POINTER(Geometry), i32, i32, C.POINTER(sz)], i32),
         "pty_checkpoint_every": ([vp], i32),
+        "pty_set_chunk": ([vp, i32], i32),
         "pty_forward": ([vp, vp, vp, vp, vp, vp, i32, vp, vp, vp], i32),
         "pty_loss_and_grad": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, u32], i32),
         "pty_forward_save": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp], i32),

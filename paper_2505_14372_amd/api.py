@@ -135,6 +135,12 @@ class Problem:
         except Exception:
             pass
 
+    def set_chunk(self, positions: int):
+        """Positions per launch in loss_and_grad / reconstruct_step (0: the whole group)."""
+        st = self.lib.pty_set_chunk(self.ctx, int(positions))
+        if st:
+            self._err(st, "pty_set_chunk")
+
     def _err(self, st, what):
         msg = self.lib.pty_last_error(self.ctx).decode() if self.ctx else ""
         raise PtyError(st, f"{what}: {msg}")

@@ -35,14 +35,17 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    """Compile every source and link libpty.so; returns its path."""
+def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB) -> str:
+    """Compile every source and link libpty.so (or `out`); returns its path.
+    `defines` are extra -D macros (tuning constants of the kernels)."""
     cc = hipcc()
     objs = []
     procs = []
+    tag = str(abs(hash((tuple(defines), out))))
     for src in SOURCES:
-        obj = os.path.join(CSRC, src + ".o")
-        cmd = [cc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(CSRC, f"{src}.{tag}.o")
+        cmd = [cc, *HIP_FLAGS, *[f"-D{d}" for d in defines], "-I", INCLUDE, "-I", CSRC, "-c",
+               os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
@@ -51,17 +54,17 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
             _wait(procs.pop(0), verbose)
     for p in procs:
         _wait(p, verbose)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 def _wait(item, verbose):

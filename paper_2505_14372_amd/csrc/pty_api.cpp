@@ -177,6 +177,7 @@ struct pty_ctx {
   pty_geometry g{};
   std::vector<double> dz;
   int max_batch = 0, ck_every = 1, n_ck = 1;
+  int chunk = 0;              // positions per launch in fused loss-and-gradient calls (0: all)
   Sizes sz;
   float2 *tw = nullptr, *prop = nullptr, *phat = nullptr, *gphat = nullptr, *gprobe = nullptr, *gobj = nullptr;
   float* gpos = nullptr;
@@ -250,12 +251,32 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
   return L;
 }
 
-// Forward sequence over all requests of L (steps up to the largest S).
-// save: store entry-wave checkpoints and leave the detector-plane gradient
-// seed (after its inverse column DFT) in the workspace.
-void run_forward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& far_steps, bool save,
-                 bool want_loss) {
-  { ProfScope p(P_ITEMS, L.stream); launch_items(L, N); }
+// Launch sequences. A launch context L covers items [L.item_off,
+// L.item_off + L.n_items); prepare/finish steps always cover every item.
+
+std::vector<std::pair<int, int>> split_chunks(int n, int chunk) {
+  std::vector<std::pair<int, int>> out;
+  if (chunk <= 0 || chunk >= n) { out.push_back({0, n}); return out; }
+  for (int a = 0; a < n; a += chunk) out.push_back({a, std::min(chunk, n - a)});
+  return out;
+}
+
+LaunchCtx sub(const LaunchCtx& L, int off, int n) {
+  LaunchCtx R = L;
+  R.item_off = off;
+  R.n_items = n;
+  return R;
+}
+
+void run_prepare(const LaunchCtx& L, int N) {
+  ProfScope p(P_ITEMS, L.stream);
+  launch_items(L, N);
+}
+
+// Forward passes of the items of L (steps up to the largest S). save: store
+// entry-wave checkpoints and leave the detector-plane gradient seed (after
+// its inverse column DFT) in the workspace.
+void run_forward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<int>& far_steps, bool save) {
   { ProfScope p(P_COL_SHIFT, L.stream); launch_col(L, N, COL_SHIFT, 0); }
   PsiStore st{};
   st.mode = save ? 1 : 0;
@@ -267,13 +288,18 @@ void run_forward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& f
       launch_far_loss(L, N, i, save);
     }
   }
-  if (want_loss) { ProfScope p(P_LOSS_REDUCE, L.stream); launch_loss_reduce(L, N); }
 }
 
-// Adjoint sequence (after run_forward with save). Single-request contexts may
-// use checkpoint intervals k > 1; grouped launches store every slice.
-void run_backward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& final_steps, float scale,
-                  int k, float2* ws2, float2* seg) {
+void run_finish_forward(const LaunchCtx& L, int N) {
+  ProfScope p(P_LOSS_REDUCE, L.stream);
+  launch_loss_reduce(L, N);
+}
+
+// Adjoint passes of the items of L (after their forward with save).
+// Single-request contexts may use checkpoint intervals k > 1 (entry waves
+// recomputed per segment); grouped launches store every slice.
+void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<int>& final_steps, float scale,
+                        int k, float2* ws2, float2* seg) {
   int seg_lo = -1, seg_hi = -1;   // slices currently held in the segment buffer
   for (int t = 0; t < S_max; ++t) {
     const int i = S_max - 1 - t;   // single-request slice index (k > 1 only)
@@ -283,13 +309,13 @@ void run_backward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& 
       const int i1 = std::min(i0 + k - 1, S_max - 1);
       if (!(seg_lo == i0 + 1 && seg_hi == i1)) {
         // recompute entry waves i0+1 .. i1 from the checkpoint at i0
+        ProfScope p(P_RECOMPUTE, L.stream);
         LaunchCtx R = L;
         R.ws = ws2;
         PsiStore st{};
         st.mode = 0;
         st.src = L.ck;
         st.src_slot = i0 / k;
-        ProfScope p(P_RECOMPUTE, L.stream);
         launch_rows_fwd(R, N, i0, st, true);
         for (int s = i0 + 1; s <= i1; ++s) {
           launch_col(R, N, COL_PROP, s - 1);
@@ -316,6 +342,9 @@ void run_backward(const LaunchCtx& L, int N, int S_max, const std::vector<int>& 
       launch_col(L, N, COL_FINAL, t);
     }
   }
+}
+
+void run_finish_backward(const LaunchCtx& L, int N, float scale) {
   { ProfScope p(P_PROBE_GRAD, L.stream); launch_probe_grad(L, N, scale); }
   { ProfScope p(P_POS_REDUCE, L.stream); launch_pos_reduce(L, N, scale); }
 }
@@ -329,6 +358,20 @@ pty_status check_call(pty_ctx* c, const void* probe, const void* object, const v
     return PTY_EINVAL;
   }
   return PTY_OK;
+}
+
+// Forward and adjoint of every chunk in turn (so that one chunk's tiles stay
+// cached between its passes), then the group reductions.
+void run_fused(pty_ctx* c, const LaunchCtx& L, float scale) {
+  const int N = c->g.N, S = c->g.n_slices;
+  run_prepare(L, N);
+  for (auto& ch : split_chunks(L.n_items, c->chunk)) {
+    LaunchCtx C = sub(L, ch.first, ch.second);
+    run_forward_chunk(C, N, S, {S - 1}, true);
+    run_backward_chunk(C, N, S, {S - 1}, scale, c->ck_every, c->ws2, c->seg);
+  }
+  if (L.reqs.r[0].loss_out) run_finish_forward(L, N);
+  run_finish_backward(L, N, scale);
 }
 
 }  // namespace
@@ -442,7 +485,9 @@ pty_status pty_forward(pty_ctx* c, void* stream, const pty_c64* probe, const pty
   r.I_out = intensities;
   r.loss_out = (patterns && loss) ? loss : nullptr;
   LaunchCtx L = ctx_launch(c, s, r, B);
-  run_forward(L, N, S, {S - 1}, false, r.loss_out != nullptr);
+  run_prepare(L, N);
+  for (auto& ch : split_chunks(B, c->chunk)) run_forward_chunk(sub(L, ch.first, ch.second), N, S, {S - 1}, false);
+  if (r.loss_out) run_finish_forward(L, N);
   HIPCHECK(c, hipGetLastError());
   return PTY_OK;
 }
@@ -465,7 +510,9 @@ pty_status pty_forward_save(pty_ctx* c, void* stream, const pty_c64* probe, cons
   r.I_out = intensities;
   r.loss_out = loss;
   LaunchCtx L = ctx_launch(c, s, r, B);
-  run_forward(L, N, S, {S - 1}, true, loss != nullptr);
+  run_prepare(L, N);
+  for (auto& ch : split_chunks(B, c->chunk)) run_forward_chunk(sub(L, ch.first, ch.second), N, S, {S - 1}, true);
+  if (loss) run_finish_forward(L, N);
   HIPCHECK(c, hipGetLastError());
   c->tape = L;
   c->tape_valid = true;
@@ -493,7 +540,9 @@ pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_
     ProfScope p(P_FILL, s);
     launch_fill(s, (float*)g_object, (size_t)S * c->g.obj_h * c->g.obj_w * 2, 0.f);
   }
-  run_backward(L, N, S, {S - 1}, (float)grad_scale, c->ck_every, c->ws2, c->seg);
+  for (auto& ch : split_chunks(L.n_items, c->chunk))
+    run_backward_chunk(sub(L, ch.first, ch.second), N, S, {S - 1}, (float)grad_scale, c->ck_every, c->ws2, c->seg);
+  run_finish_backward(L, N, (float)grad_scale);
   if (g_probe)
   { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, (float2*)g_probe, c->g.n_modes, true, 1.f / N, acc); }
   c->tape_valid = false;
@@ -504,9 +553,33 @@ pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_
 pty_status pty_loss_and_grad(pty_ctx* c, void* stream, const pty_c64* probe, const pty_c64* object,
                              const float* positions, const float* patterns, const int32_t* batch_idx, int32_t B,
                              double* loss, pty_c64* g_object, pty_c64* g_probe, float* g_pos, uint32_t flags) {
-  pty_status st = pty_forward_save(c, stream, probe, object, positions, patterns, batch_idx, B, nullptr, loss);
+  pty_status st = check_call(c, probe, object, positions, batch_idx, B);
   if (st != PTY_OK) return st;
-  return pty_backward(c, stream, 1.0, g_object, g_probe, g_pos, flags);
+  if (!patterns) { c->err = "patterns are required for the gradient"; return PTY_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  c->tape_valid = false;
+  const int N = c->g.N, S = c->g.n_slices;
+  const bool acc = (flags & PTY_ACCUMULATE) != 0;
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, (const float2*)probe, c->phat, c->g.n_modes, false, 1.f / N, false); }
+  ReqDev r = base_req(c);
+  r.obj = (const float2*)object;
+  r.positions = positions;
+  r.batch_idx = batch_idx;
+  r.patterns = patterns;
+  r.loss_out = loss;
+  r.gobj = (float2*)g_object;
+  r.gpos = g_pos;
+  r.accumulate = acc ? 1 : 0;
+  r.gphat = g_probe ? c->gphat : nullptr;
+  if (g_object && !acc) {
+    ProfScope p(P_FILL, s);
+    launch_fill(s, (float*)g_object, (size_t)S * c->g.obj_h * c->g.obj_w * 2, 0.f);
+  }
+  LaunchCtx L = ctx_launch(c, s, r, B);
+  run_fused(c, L, 1.f);
+  if (g_probe) { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, (float2*)g_probe, c->g.n_modes, true, 1.f / N, acc); }
+  HIPCHECK(c, hipGetLastError());
+  return PTY_OK;
 }
 
 }  // extern "C"
@@ -561,26 +634,30 @@ extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* 
   pty_status s0 = check_state(c, st, o);
   if (s0 != PTY_OK) return s0;
   hipStream_t s = (hipStream_t)stream;
-  s0 = pty_forward_save(c, stream, st->probe, st->object, st->positions, patterns, batch_idx, B, nullptr, loss);
+  s0 = check_call(c, st->probe, st->object, st->positions, batch_idx, B);
   if (s0 != PTY_OK) return s0;
+  if (!patterns) { c->err = "patterns are required for the gradient"; return PTY_EINVAL; }
+  c->tape_valid = false;
   const pty_geometry& g = c->g;
   const int N = g.N, S = g.n_slices;
-  LaunchCtx L = c->tape;
-  ReqDev& r = L.reqs.r[0];
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, (const float2*)st->probe, c->phat, g.n_modes, false, 1.f / N, false); }
+  ReqDev r = base_req(c);
+  r.obj = (const float2*)st->object;
+  r.positions = st->positions;
+  r.batch_idx = batch_idx;
+  r.patterns = patterns;
+  r.loss_out = loss;
   r.gobj = c->gobj;
-  r.gpos = nullptr;
   r.gpos_dense = c->gpos;
   r.gphat = c->gphat;
-  r.I_out = nullptr;
-  r.loss_out = nullptr;
+  LaunchCtx L = ctx_launch(c, s, r, B);
   {
     ProfScope p(P_FILL, s);
     launch_fill(s, (float*)c->gobj, (size_t)S * g.obj_h * g.obj_w * 2, 0.f);
     launch_fill(s, c->gpos, (size_t)g.n_positions * 2, 0.f);
   }
-  run_backward(L, N, S, {S - 1}, 1.f, c->ck_every, c->ws2, c->seg);
+  run_fused(c, L, 1.f);
   { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, g.n_modes, true, 1.f / N, false); }
-  c->tape_valid = false;
   apply_optimizer(c, s, st, o);
   HIPCHECK(c, hipGetLastError());
   return PTY_OK;
@@ -719,9 +796,12 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   }
   std::sort(last_steps.begin(), last_steps.end());
   last_steps.erase(std::unique(last_steps.begin(), last_steps.end()), last_steps.end());
-  run_forward(L, N, S_max, last_steps, true, true);
   // adjoint step t handles slice S_q - 1 - t of request q; slice 0 at t = S_q - 1
-  run_backward(L, N, S_max, last_steps, 1.f, 1, nullptr, nullptr);
+  run_prepare(L, N);
+  run_forward_chunk(L, N, S_max, last_steps, true);
+  run_backward_chunk(L, N, S_max, last_steps, 1.f, 1, nullptr, nullptr);
+  run_finish_forward(L, N);
+  run_finish_backward(L, N, 1.f);
   for (int q = 0; q < n; ++q) {
     pty_ctx* c = items[q].ctx;
     launch_plain2d(N, s, G->tw, c->gphat, c->gprobe, c->g.n_modes, true, 1.f / N, false);
@@ -774,4 +854,10 @@ extern "C" int32_t pty_profile_collect(char* names, size_t names_len, double* to
     names[m] = '\0';
   }
   return std::min(n, max_entries);
+}
+
+extern "C" pty_status pty_set_chunk(pty_ctx* c, int32_t positions) {
+  if (!c || positions < 0) return PTY_EINVAL;
+  c->chunk = positions;
+  return PTY_OK;
 }

@@ -181,8 +181,21 @@ template <> struct Cfg<128> { static constexpr int L = 8,  E = 16; };
 template <> struct Cfg<192> { static constexpr int L = 8,  E = 24; };
 template <> struct Cfg<256> { static constexpr int L = 16, E = 16; };
 
+constexpr int pad_to(int x, int mod, int rem) { return x + ((rem - x % mod) % mod + mod) % mod; }
+
 // Exchange scratch of one line: Z[l][k1] at xch[k1 * XP + l], XP = L + 1.
-template <int N> struct Xch { static constexpr int XP = Cfg<N>::L + 1; static constexpr int SIZE = Cfg<N>::E * XP; };
+// Lines of one workgroup are ROW_STRIDE (row passes: the lines of a wave
+// are consecutive) or COL_STRIDE (column passes: consecutive lanes belong
+// to consecutive columns) float2 apart. Both strides are padded so that the
+// 64 lanes of a wave spread over all 64 four-byte LDS banks: a float2
+// access then takes the minimum of two bank cycles per wave.
+template <int N> struct Xch {
+  static constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
+  static constexpr int XP = L + 1;
+  static constexpr int SIZE = E * XP;
+  static constexpr int ROW_STRIDE = (L == 16) ? pad_to(SIZE, 32, 16) : pad_to(SIZE, 32, 8);
+  static constexpr int COL_STRIDE = (L == 16) ? pad_to(SIZE, 32, 4) : pad_to(SIZE, 2, 1);
+};
 
 // Line FFT of v (layout above), in two stages around the LDS exchange.
 // tw: table tw[k] = w_N^k (forward roots), k in [0, N). xch: this line's

@@ -76,6 +76,7 @@ struct LaunchCtx {
   hipStream_t stream;
   ReqTable reqs;
   int n_reqs, n_items, max_modes;
+  int item_off;             // first item of this launch (chunked schedules)
   Item* items;
   float2* ws;               // tile workspace
   float2* ck;               // checkpoint buffer

@@ -39,7 +39,29 @@ __device__ __forceinline__ void raise_flag(int* flags, int bit) {
 
 template <int N>
 __device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw_glb) {
-  for (int k = threadIdx.x; k < N; k += kThreads) tw_lds[k] = tw_glb[k];
+  for (int k = threadIdx.x; k < N; k += blockDim.x) tw_lds[k] = tw_glb[k];
+}
+
+
+#ifndef PTY_NT_CKPT
+#define PTY_NT_CKPT 0
+#endif
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// Checkpoint stores/loads: streamed past the caches when PTY_NT_CKPT is set.
+__device__ __forceinline__ void ck_store(float2* p, float2 v) {
+  if (PTY_NT_CKPT) {
+    f32x2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p));
+  } else {
+    *p = v;
+  }
+}
+__device__ __forceinline__ float2 ck_load(const float2* p) {
+  if (PTY_NT_CKPT) {
+    f32x2 w = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+    return make_float2(w.x, w.y);
+  }
+  return *p;
 }
 
 // ============================================================ items
@@ -101,11 +123,11 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, float2* __restrict__ ck,
                                                       const float2* __restrict__ twg, int step,
-                                                      PsiStore store) {
+                                                      PsiStore store, int item_off) {
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[LINES * Xch<N>::SIZE];
-  const Item it = items[blockIdx.y];
+  __shared__ float2 xch[LINES * Xch<N>::ROW_STRIDE];
+  const Item it = items[item_off + blockIdx.y];
   const ReqDev& r = reqs.r[it.req];
   const int i = step;
   if (!it.valid || i >= r.S) return;
@@ -113,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
   __syncthreads();
   const int l = threadIdx.x % L, line = threadIdx.x / L;
   const int y = blockIdx.x * LINES + line;
-  float2* sx = xch + line * Xch<N>::SIZE;
+  float2* sx = xch + line * Xch<N>::ROW_STRIDE;
   // object patch row, shared by every mode
   float2 o[E];
   const float2* orow = r.obj + ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
@@ -135,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
     if (store.mode == 1 && (i % r.ck_every) == 0) {
       float2* dst = ck + (((size_t)it.ck0 + (size_t)m * n_ck + i / r.ck_every) * N + y) * N;
 #pragma unroll
-      for (int a = 0; a < E; ++a) dst[l + L * a] = v[a];
+      for (int a = 0; a < E; ++a) ck_store(dst + l + L * a, v[a]);
     } else if (store.mode == 2) {
       float2* dst = store.seg + (((size_t)(it.tile0 + m) * store.seg_len + store.seg_slot) * N + y) * N;
 #pragma unroll
@@ -159,11 +181,11 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, const float2* __restrict__ ck,
                                                       const float2* __restrict__ twg, int step,
-                                                      PsiLoad psi, float scale) {
+                                                      PsiLoad psi, float scale, int item_off) {
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[LINES * Xch<N>::SIZE];
-  const Item it = items[blockIdx.y];
+  __shared__ float2 xch[LINES * Xch<N>::ROW_STRIDE];
+  const Item it = items[item_off + blockIdx.y];
   const ReqDev& r = reqs.r[it.req];
   const int i = r.S - 1 - step;
   if (!it.valid || i < 0) return;
@@ -171,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   __syncthreads();
   const int l = threadIdx.x % L, line = threadIdx.x / L;
   const int y = blockIdx.x * LINES + line;
-  float2* sx = xch + line * Xch<N>::SIZE;
+  float2* sx = xch + line * Xch<N>::ROW_STRIDE;
   float2 o[E], acc[E];
   const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
 #pragma unroll
@@ -187,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     else prow = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i / r.ck_every) * N + y) * N;
 #pragma unroll
     for (int a = 0; a < E; ++a) {
-      float2 p = prow[l + L * a];
+      float2 p = ck_load(prow + l + L * a);
       acc[a] = cadd(acc[a], cjmul(p, v[a]));
       v[a] = cjmul(o[a], v[a]);
     }
@@ -212,7 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_row_plain(const float2* __restrict
                                                         int accumulate) {
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[LINES * Xch<N>::SIZE];
+  __shared__ float2 xch[LINES * Xch<N>::ROW_STRIDE];
   load_twiddles<N>(tw, twg);
   __syncthreads();
   const int l = threadIdx.x % L, line = threadIdx.x / L;
@@ -221,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_row_plain(const float2* __restrict
   float2 v[E];
 #pragma unroll
   for (int a = 0; a < E; ++a) v[a] = src[base + l + L * a];
-  line_fft<N, INV>(v, l, tw, xch + line * Xch<N>::SIZE, WaveSync{});
+  line_fft<N, INV>(v, l, tw, xch + line * Xch<N>::ROW_STRIDE, WaveSync{});
 #pragma unroll
   for (int a = 0; a < E; ++a) {
     float2 w = cscale(v[a], scale);
@@ -235,9 +257,16 @@ __global__ __launch_bounds__(kThreads) void k_row_plain(const float2* __restrict
 // Column-pass thread layout: thread t holds column c = t % CB of the block
 // and lane l = t / CB of that column's line, so that a load of register a
 // reads CB consecutive complex values of row l + L a (coalesced).
+#ifndef PTY_COL_CB_L16
+#define PTY_COL_CB_L16 16
+#endif
+#ifndef PTY_COL_CB_L8
+#define PTY_COL_CB_L8 32
+#endif
 template <int N> struct ColPass {
   static constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
-  static constexpr int CB = kThreads / L;
+  static constexpr int CB = (L == 16) ? PTY_COL_CB_L16 : PTY_COL_CB_L8;   // columns per workgroup
+  static constexpr int THREADS = CB * L;
   static constexpr int NBLK = N / CB;
 };
 
@@ -248,16 +277,16 @@ template <int N> struct ColPass {
 //   COL_FINAL    tile = DFT_y(tile) / N = h_hat          (adjoint, i = 0) and the
 //                per-block sums of Im(conj(h_hat) phat R) u_a for the position gradient
 template <int N, int OP>
-__global__ __launch_bounds__(kThreads) void k_col(const Item* __restrict__ items,
+__global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restrict__ items,
                                                   const ReqTable reqs,
                                                   float2* __restrict__ ws, const float2* __restrict__ ramps,
                                                   const float2* __restrict__ twg, int step,
-                                                  float* __restrict__ pos_part) {
+                                                  float* __restrict__ pos_part, int item_off) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[CB * Xch<N>::SIZE];
-  __shared__ float red[2][kThreads / 64];
-  const int b = blockIdx.y, m = blockIdx.z;
+  __shared__ float2 xch[CB * Xch<N>::COL_STRIDE];
+  __shared__ float red[2][ColPass<N>::THREADS / 64];
+  const int b = item_off + blockIdx.y, m = blockIdx.z;
   const Item it = items[b];
   const ReqDev& r = reqs.r[it.req];
   if (!it.valid || m >= r.M) return;
@@ -269,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Item* __restrict__ items
   __syncthreads();
   const int c = threadIdx.x % CB, l = threadIdx.x / CB;
   const int ux = blockIdx.x * CB + c;
-  float2* sx = xch + c * Xch<N>::SIZE;
+  float2* sx = xch + c * Xch<N>::COL_STRIDE;
   float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
   float2 v[E];
   if constexpr (OP == COL_SHIFT) {
@@ -322,7 +351,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Item* __restrict__ items
       __syncthreads();
       if (threadIdx.x == 0) {
         float t0 = 0.f, t1 = 0.f;
-        for (int w = 0; w < kThreads / 64; ++w) { t0 += red[0][w]; t1 += red[1][w]; }
+        for (int w = 0; w < ColPass<N>::THREADS / 64; ++w) { t0 += red[0][w]; t1 += red[1][w]; }
         float* dst = pos_part + ((size_t)(it.tile0 + m) * ColPass<N>::NBLK + blockIdx.x) * 2;
         dst[0] = t0;
         dst[1] = t1;
@@ -335,11 +364,11 @@ __global__ __launch_bounds__(kThreads) void k_col(const Item* __restrict__ items
 
 // Plain column DFT of M probe-sized tiles (in place): tile = scale * DFT_y(tile).
 template <int N, bool INV>
-__global__ __launch_bounds__(kThreads) void k_col_plain(float2* __restrict__ t, const float2* __restrict__ twg,
+__global__ __launch_bounds__(ColPass<N>::THREADS) void k_col_plain(float2* __restrict__ t, const float2* __restrict__ twg,
                                                         float scale) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[CB * Xch<N>::SIZE];
+  __shared__ float2 xch[CB * Xch<N>::COL_STRIDE];
   load_twiddles<N>(tw, twg);
   __syncthreads();
   const int c = threadIdx.x % CB, l = threadIdx.x / CB;
@@ -348,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_col_plain(float2* __restrict__ t, 
   float2 v[E];
 #pragma unroll
   for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
-  line_fft<N, INV>(v, l, tw, xch + c * Xch<N>::SIZE, BlockSync{});
+  line_fft<N, INV>(v, l, tw, xch + c * Xch<N>::COL_STRIDE, BlockSync{});
 #pragma unroll
   for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = cscale(v[a], scale);
 }
@@ -388,15 +417,16 @@ __device__ __forceinline__ void loss_weight(int kind, float I, float Ie, float e
 //   tile_m = IDFT_y(w * Psi_m) / N
 // Writes intensities (if requested) and per-block loss partial sums.
 template <int N, bool GRAD>
-__global__ __launch_bounds__(kThreads) void k_far_loss(const Item* __restrict__ items,
+__global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __restrict__ items,
                                                        const ReqTable reqs,
                                                        float2* __restrict__ ws, const float2* __restrict__ twg,
-                                                       int step, float* __restrict__ loss_part, int* flags) {
+                                                       int step, float* __restrict__ loss_part, int* flags,
+                                                       int item_off) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[CB * Xch<N>::SIZE];
-  __shared__ float red[kThreads / 64];
-  const int b = blockIdx.y;
+  __shared__ float2 xch[CB * Xch<N>::COL_STRIDE];
+  __shared__ float red[ColPass<N>::THREADS / 64];
+  const int b = item_off + blockIdx.y;
   const Item it = items[b];
   const ReqDev& r = reqs.r[it.req];
   if (step != r.S - 1) return;
@@ -413,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_far_loss(const Item* __restrict__ 
   }
   load_twiddles<N>(tw, twg);
   __syncthreads();
-  float2* sx = xch + c * Xch<N>::SIZE;
+  float2* sx = xch + c * Xch<N>::COL_STRIDE;
   const float inv = 1.f / (float)N;
   float I[E];
 #pragma unroll
@@ -456,7 +486,7 @@ __global__ __launch_bounds__(kThreads) void k_far_loss(const Item* __restrict__ 
   __syncthreads();
   if (threadIdx.x == 0) {
     float t = 0.f;
-    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+    for (int w = 0; w < ColPass<N>::THREADS / 64; ++w) t += red[w];
     loss_part[(size_t)b * ColPass<N>::NBLK + blockIdx.x] = t;
   }
   if constexpr (GRAD) {
@@ -591,29 +621,29 @@ struct Launch {
   static void rows_fwd(const LaunchCtx& L, int step, PsiStore st, bool from_real) {
     dim3 g(Pass<N>::NBLK, L.n_items);
     if (from_real)
-      hipLaunchKernelGGL((k_row_fwd<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st);
+      hipLaunchKernelGGL((k_row_fwd<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
     else
-      hipLaunchKernelGGL((k_row_fwd<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st);
+      hipLaunchKernelGGL((k_row_fwd<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
   }
   static void rows_adj(const LaunchCtx& L, int step, PsiLoad psi, float scale) {
     dim3 g(Pass<N>::NBLK, L.n_items);
-    hipLaunchKernelGGL((k_row_adj<N>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale);
+    hipLaunchKernelGGL((k_row_adj<N>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
   }
   static void col(const LaunchCtx& L, int op, int step) {
     dim3 g(ColPass<N>::NBLK, L.n_items, L.max_modes);
     switch (op) {
-      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
-      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
-      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
-      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part); break;
+      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
+      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
+      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
+      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
     }
   }
   static void far_loss(const LaunchCtx& L, int step, bool grad) {
     dim3 g(ColPass<N>::NBLK, L.n_items);
     if (grad)
-      hipLaunchKernelGGL((k_far_loss<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.tw, step, L.loss_part, L.flags);
+      hipLaunchKernelGGL((k_far_loss<N, true>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.tw, step, L.loss_part, L.flags, L.item_off);
     else
-      hipLaunchKernelGGL((k_far_loss<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.tw, step, L.loss_part, L.flags);
+      hipLaunchKernelGGL((k_far_loss<N, false>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.tw, step, L.loss_part, L.flags, L.item_off);
   }
   static void probe_grad(const LaunchCtx& L, float scale) {
     dim3 g(N * N / kThreads, L.max_modes, L.n_reqs);
@@ -625,11 +655,11 @@ struct Launch {
     dim3 gr(Pass<N>::NBLK, n_tiles), gc(ColPass<N>::NBLK, n_tiles);
     if (!inverse) {
       hipLaunchKernelGGL((k_row_plain<N, false>), gr, dim3(kThreads), 0, s, src, dst, tw, 1.f, 0);
-      hipLaunchKernelGGL((k_col_plain<N, false>), gc, dim3(kThreads), 0, s, dst, tw, scale);
+      hipLaunchKernelGGL((k_col_plain<N, false>), gc, dim3(ColPass<N>::THREADS), 0, s, dst, tw, scale);
     } else {
       // columns in place on a copy living in dst is not possible when accumulating:
       // the caller passes src as scratch that may be overwritten.
-      hipLaunchKernelGGL((k_col_plain<N, true>), gc, dim3(kThreads), 0, s, const_cast<float2*>(src), tw, scale);
+      hipLaunchKernelGGL((k_col_plain<N, true>), gc, dim3(ColPass<N>::THREADS), 0, s, const_cast<float2*>(src), tw, scale);
       hipLaunchKernelGGL((k_row_plain<N, true>), gr, dim3(kThreads), 0, s, src, dst, tw, 1.f, accumulate ? 1 : 0);
     }
   }
