@@ -40,6 +40,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-positions", type=int, default=8)
     p.add_argument("--checkpoint-every", type=int, default=1)
+    p.add_argument("--chunk", type=int, default=0)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    p.add_argument("--requests", type=int, default=16, help="serving stream: number of reconstructions")
+    p.add_argument("--iters", type=int, default=50, help="serving stream: iterations per reconstruction")
     return p.parse_args()
 
 
@@ -84,6 +89,15 @@ def main():
     from paper_2505_14372_amd import _lib, api, synth
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    if args.workload == "serving":
+        return bench_serving(args)
     dev = "cuda:0"
     t0 = time.time()
     wl = synth.make_workload(args.workload, pattern_pool=64)
@@ -100,6 +114,7 @@ def main():
         pats[s0:s0 + chunk].copy_(torch.from_numpy(wl.patterns[s0:s0 + chunk]))
     prob = api.Problem(N, M, S, H, W, J, dz=wl.dz, dx=wl.dx, wavelength=wl.wavelength, loss=wl.loss, eps=wl.eps,
                        max_batch=B, checkpoint_every=args.checkpoint_every)
+    prob.set_chunk(args.chunk)
     state = api.ReconState(probe, obj, pos, adam=True)
     opt = api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2)
     rng = np.random.default_rng(12345)
@@ -162,7 +177,9 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
-    roof.update({"kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4), "traffic": None})
+    traffic = measured_traffic(dom)
+    roof.update({"kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4),
+                 "traffic": traffic, "algorithmic_bytes": bytes_launch, "algorithmic_flops": flops_launch})
     kernels = {k: {"total_ms": round(v[0], 3), "launches": int(v[1]), "avg_ms": round(v[0] / v[1], 4),
                    "share": round(v[0] / sum(x[0] for x in prof.values()), 4)} for k, v in prof.items()}
     flop_pos = 4 * S * M * 5 * N * N * np.log2(N * N)
@@ -180,6 +197,75 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_positions)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in ("pty_kernels.hip", "pty_fft.hpp", "pty_internal.h"):
+        with open(os.path.join(ROOT, "paper_2505_14372_amd", "csrc", p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cfg3_ms256_b512.md")
+    try:
+        text = open(path).read()
+        data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("source_sha256") != kernel_source_hash() or kernel not in data.get("kernels", {}):
+        return None
+    k = data["kernels"][kernel]
+    return int(k["fetch_bytes"] + k["write_bytes"])
+
+
+def bench_serving(args):
+    """Served mixed-size stream against one reconstruction at a time (same
+    requests, same minibatch order), on one GPU."""
+    import torch
+
+    from paper_2505_14372_amd import serving
+    t0 = time.time()
+    reqs = serving.make_request_stream(args.requests, seed=0, rate_per_s=2.0, n_iters=args.iters,
+                                       scans=(16, 48))
+    work = sum(r.J * r.n_iters for r in reqs)
+    print(f"[bench] {len(reqs)} requests built in {time.time() - t0:.1f}s, "
+          f"{work} position-iterations", file=sys.stderr, flush=True)
+    srv = serving.Server(hbm_budget=int(0.5 * torch.cuda.get_device_properties(0).total_memory))
+    for r in reqs:
+        srv.submit(r)
+    t1 = time.perf_counter()
+    served = srv.run(log=lambda m: print("[bench] served " + m, file=sys.stderr, flush=True))
+    t_served = time.perf_counter() - t1
+    print(f"[bench] served stream done in {t_served:.1f}s", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    fifo = serving.run_fifo(reqs)
+    t_fifo = time.perf_counter() - t1
+    print(f"[bench] one-at-a-time done in {t_fifo:.1f}s", file=sys.stderr, flush=True)
+    p50, p99 = serving.latency_stats(served)
+    f50, f99 = serving.latency_stats(fifo)
+    diff = 0.0
+    for r in reqs:
+        a, b = served[r.rid].obj, fifo[r.rid].obj
+        diff = max(diff, float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+    out = {
+        "metric": "probe positions x iterations/s of a served stream of mixed reconstructions",
+        "value": round(work / t_served, 1), "unit": "position-iterations/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 0, "ms_per_step": round(1000 * t_served / len(reqs), 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving: {len(reqs)} Poisson arrivals (2/s), probe 64-256, 1-6 modes, "
+                               f"1-16 slices, 16^2-48^2 scans, {args.iters} Adam iterations each"},
+        "iteration_latency_p50_s": round(p50, 4), "iteration_latency_p99_s": round(p99, 4),
+        "one_at_a_time": {"value": round(work / t_fifo, 1), "iteration_latency_p50_s": round(f50, 4),
+                          "iteration_latency_p99_s": round(f99, 4), "wall_s": round(t_fifo, 2)},
+        "served_over_one_at_a_time": round(t_fifo / t_served, 3),
+        "max_rel_object_diff_served_vs_alone": diff, "rounds": srv.rounds,
+    }
     print(json.dumps(out), flush=True)
 
 

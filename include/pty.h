@@ -84,6 +84,7 @@ typedef enum {
 } pty_loss_kind;
 
 #define PTY_ACCUMULATE 1u   /* add into gradient outputs instead of overwriting */
+#define PTY_POS_DENSE 2u    /* g_pos is [J][2] indexed by position (batch entries summed) */
 
 /* One reconstruction's geometry (the unknowns of Sec. 3: probe modes, sliced
  * object with gaps dz, positions). */
@@ -138,8 +139,9 @@ pty_status pty_forward(pty_ctx* ctx, void* stream, const pty_c64* probe, const p
                        const float* patterns, float* intensities, double* loss);
 
 /* Loss of the group and its gradients (Sec. 3.1-3.2): g_object [S][H][W],
- * g_probe [M][N][N], g_pos [batch][2] (per batch entry, dL/dX). loss may be
- * NULL. flags: PTY_ACCUMULATE. */
+ * g_probe [M][N][N], g_pos [batch][2] (per batch entry, dL/dX; with
+ * PTY_POS_DENSE [J][2] per position). loss may be NULL.
+ * flags: PTY_ACCUMULATE | PTY_POS_DENSE. */
 pty_status pty_loss_and_grad(pty_ctx* ctx, void* stream, const pty_c64* probe,
                              const pty_c64* object, const float* positions, const float* patterns,
                              const int32_t* batch_idx, int32_t batch, double* loss,

@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "PTY_OK", 1: "PTY_EINVAL", 2: "PTY_EBOUNDS", 3: "PTY_EUNSUPPO
 LOSS_IDS = {"amplitude": 0, "anscombe": 1, "poisson": 2, "gaussian": 3}
 OPT_SGD, OPT_ADAM = 0, 1
 PTY_ACCUMULATE = 1
+PTY_POS_DENSE = 2
 
 # every exported symbol of include/pty.h
 EXPORTS = (

@@ -123,6 +123,7 @@ class Problem:
             raise PtyError(st, "pty_create")
         self.ctx = ctx
         self.checkpoint_every = self.lib.pty_checkpoint_every(ctx)
+        self.tape_id = 0          # incremented by every forward_save (identifies the tape)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -168,8 +169,9 @@ class Problem:
         return I, loss
 
     def loss_and_grad(self, probe, obj, positions, patterns, batch_idx, g_object=None, g_probe=None, g_pos=None,
-                      accumulate=False, want=("object", "probe", "pos")):
-        """Group loss and gradients (dL/dRe + i dL/dIm) of object, probe and per-entry positions."""
+                      accumulate=False, want=("object", "probe", "pos"), dense_pos=False):
+        """Group loss and gradients (dL/dRe + i dL/dIm) of object, probe and positions
+        (per batch entry [B][2], or per position [J][2] with dense_pos)."""
         B = self._check_inputs(probe, obj, positions, batch_idx, patterns)
         dev = probe.device
         if "object" in want and g_object is None:
@@ -177,11 +179,12 @@ class Problem:
         if "probe" in want and g_probe is None:
             g_probe = torch.empty_like(probe)
         if "pos" in want and g_pos is None:
-            g_pos = torch.empty((B, 2), dtype=torch.float32, device=dev)
+            g_pos = torch.empty((self.J if dense_pos else B, 2), dtype=torch.float32, device=dev)
         loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        flags = (_lib.PTY_ACCUMULATE if accumulate else 0) | (_lib.PTY_POS_DENSE if dense_pos else 0)
         st = self.lib.pty_loss_and_grad(self.ctx, _stream(), _ptr(probe), _ptr(obj), _ptr(positions),
                                         _ptr(patterns), _ptr(batch_idx), B, _ptr(loss), _ptr(g_object),
-                                        _ptr(g_probe), _ptr(g_pos), _lib.PTY_ACCUMULATE if accumulate else 0)
+                                        _ptr(g_probe), _ptr(g_pos), flags)
         if st:
             self._err(st, "pty_loss_and_grad")
         return loss, g_object, g_probe, g_pos
@@ -194,11 +197,13 @@ class Problem:
                                        _ptr(batch_idx), B, _ptr(I), _ptr(loss))
         if st:
             self._err(st, "pty_forward_save")
+        self.tape_id += 1
         return loss, I
 
-    def backward(self, grad_scale, g_object=None, g_probe=None, g_pos=None, accumulate=False):
+    def backward(self, grad_scale, g_object=None, g_probe=None, g_pos=None, accumulate=False, dense_pos=False):
+        flags = (_lib.PTY_ACCUMULATE if accumulate else 0) | (_lib.PTY_POS_DENSE if dense_pos else 0)
         st = self.lib.pty_backward(self.ctx, _stream(), float(grad_scale), _ptr(g_object), _ptr(g_probe),
-                                   _ptr(g_pos), _lib.PTY_ACCUMULATE if accumulate else 0)
+                                   _ptr(g_pos), flags)
         if st:
             self._err(st, "pty_backward")
 

@@ -529,10 +529,15 @@ pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_
   LaunchCtx L = c->tape;
   L.stream = s;
   ReqDev& r = L.reqs.r[0];
+  const bool dense = (flags & PTY_POS_DENSE) != 0;
   r.gobj = (float2*)g_object;
-  r.gpos = g_pos;
-  r.gpos_dense = nullptr;
+  r.gpos = dense ? nullptr : g_pos;
+  r.gpos_dense = dense ? g_pos : nullptr;
   r.accumulate = acc ? 1 : 0;
+  if (dense && g_pos && !acc) {
+    ProfScope p(P_FILL, s);
+    launch_fill(s, g_pos, (size_t)c->g.n_positions * 2, 0.f);
+  }
   r.I_out = nullptr;
   r.loss_out = nullptr;
   r.gphat = g_probe ? c->gphat : nullptr;
@@ -568,9 +573,15 @@ pty_status pty_loss_and_grad(pty_ctx* c, void* stream, const pty_c64* probe, con
   r.patterns = patterns;
   r.loss_out = loss;
   r.gobj = (float2*)g_object;
-  r.gpos = g_pos;
+  const bool dense = (flags & PTY_POS_DENSE) != 0;
+  r.gpos = dense ? nullptr : g_pos;
+  r.gpos_dense = dense ? g_pos : nullptr;
   r.accumulate = acc ? 1 : 0;
   r.gphat = g_probe ? c->gphat : nullptr;
+  if (dense && g_pos && !acc) {
+    ProfScope p(P_FILL, s);
+    launch_fill(s, g_pos, (size_t)c->g.n_positions * 2, 0.f);
+  }
   if (g_object && !acc) {
     ProfScope p(P_FILL, s);
     launch_fill(s, (float*)g_object, (size_t)S * c->g.obj_h * c->g.obj_w * 2, 0.f);

@@ -6,7 +6,8 @@ loss or adjoint arithmetic, and it is the one module that both the GPU path
 and the CPU checker take their inputs from.
 
 Recipe (the paper's benchmark datasets are not available; these stand in for
-them with the same sizes and value structure, Methods / Sec. 5):
+them with the same sizes and value structure; the benchmark datasets are
+described in the Methods section):
 
 * probe: a circular Fourier aperture of radius N/4 bins with a quadratic
   (defocus) phase of ``defocus_edge`` rad at its edge, transformed to real

@@ -1,0 +1,137 @@
+"""The torch.autograd binding at the differentiation workload's shapes (probe
+192 x 192, 6 modes, 20 slices, object 896 x 896 x 20, 64 x 64 scan): GPU
+gradients against the FP64 oracle's exact gradient and against FP64 central
+finite differences of the oracle loss on 32 random parameter entries, with
+every slice checkpointed and with entry waves recomputed under an HBM budget."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2505_14372_amd import synth
+
+from _cases import Case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    wl = synth.make_workload("cfg2_ms192", with_patterns=True, pattern_pool=16)
+    # a minibatch of 4 positions keeps the FP64 checks within seconds
+    return Case(wl, batch=[1000, 1001, 1065, 2222])
+
+
+def _run(c, budget=0):
+    from paper_2505_14372_amd.autograd import multislice_loss
+    d = c.device()
+    prob = c.problem(checkpoint_every=0 if budget else 1, hbm_budget=budget)
+    obj = d["obj"].clone().requires_grad_(True)
+    probe = d["probe"].clone().requires_grad_(True)
+    pos = d["pos"].clone().requires_grad_(True)
+    loss = multislice_loss(obj, probe, pos, prob, d["pats"], d["batch"])
+    (2.0 * loss).backward()
+    return prob, loss.item(), obj.grad.cpu().numpy(), probe.grad.cpu().numpy(), pos.grad.cpu().numpy()
+
+
+def test_autograd_matches_oracle_and_finite_differences(cfg2):
+    c = cfg2
+    print(f"cfg2 N={c.N} M={c.M} S={c.S} H={c.H} B={len(c.batch)}", flush=True)
+    prob, loss, gO, gP, gX = _run(c)
+    assert prob.checkpoint_every == 1
+    ref = c.oracle_grad()
+    assert abs(loss - ref["loss"]) < 1e-4 * abs(ref["loss"])
+    gX_ref = np.zeros_like(c.pos, dtype=np.float64)
+    for b, j in enumerate(c.batch):
+        gX_ref[j] += ref["g_pos"][b]
+    # the backward received d(2 L)/dL = 2
+    assert rel_l2(gO, 2 * ref["g_object"]) < 1e-3
+    assert rel_l2(gP, 2 * ref["g_probe"]) < 1e-3
+    assert rel_l2(gX, 2 * gX_ref) < 1e-3
+    # FP64 central finite differences of the oracle loss on 32 random entries
+    P, O, X = c.o_args()
+    pats = c.pats.astype(np.float64)
+    rng = np.random.default_rng(5)
+    n = np.floor(X[c.batch] + 0.5).astype(int)
+    fd, an = [], []
+
+    def loss_over(P_, O_, X_, batch):
+        return orc.total_loss(P_, O_, X_, pats, batch, c.geom)
+
+    for _ in range(16):   # object entries inside a window (only covering positions matter)
+        b = rng.integers(len(c.batch))
+        i, y, x = rng.integers(c.S), n[b, 0] + rng.integers(c.N), n[b, 1] + rng.integers(c.N)
+        cover = [int(j) for j, nn in zip(c.batch, n) if nn[0] <= y < nn[0] + c.N and nn[1] <= x < nn[1] + c.N]
+        part = 1 if rng.random() < 0.5 else 1j
+        h = 1e-6
+        Op, Om = O.copy(), O.copy()
+        Op[i, y, x] += h * part
+        Om[i, y, x] -= h * part
+        fd.append((loss_over(P, Op, X, cover) - loss_over(P, Om, X, cover)) / (2 * h))
+        an.append((gO[i, y, x].real if part == 1 else gO[i, y, x].imag) / 2)
+    for _ in range(8):    # probe entries
+        m, y, x = rng.integers(c.M), rng.integers(c.N), rng.integers(c.N)
+        part = 1 if rng.random() < 0.5 else 1j
+        h = 1e-6 * max(1.0, abs(P[m, y, x]))
+        Pp, Pm = P.copy(), P.copy()
+        Pp[m, y, x] += h * part
+        Pm[m, y, x] -= h * part
+        fd.append((loss_over(Pp, O, X, list(c.batch)) - loss_over(Pm, O, X, list(c.batch))) / (2 * h))
+        an.append((gP[m, y, x].real if part == 1 else gP[m, y, x].imag) / 2)
+    for k in range(8):    # positions
+        j = int(c.batch[k % len(c.batch)])
+        a = k // len(c.batch)
+        h = 1e-6
+        Xp, Xm = X.copy(), X.copy()
+        Xp[j, a] += h
+        Xm[j, a] -= h
+        fd.append((loss_over(P, O, Xp, [j]) - loss_over(P, O, Xm, [j])) / (2 * h))
+        an.append(gX[j, a] / 2)
+    fd, an = np.array(fd), np.array(an)
+    for group, sl in (("object", slice(0, 16)), ("probe", slice(16, 24)), ("pos", slice(24, 32))):
+        err = np.max(np.abs(fd[sl] - an[sl])) / np.max(np.abs(fd[sl]))
+        print(group, err, flush=True)
+        assert err < 1e-3, (group, err)
+
+
+def test_autograd_recompute_under_budget_matches(cfg2):
+    c = cfg2
+    from paper_2505_14372_amd import api
+    full = api.workspace_bytes(c.N, c.M, c.S, c.H, c.W, len(c.pos), len(c.batch), 1)
+    a = _run(c)
+    b = _run(c, budget=int(full * 0.8))
+    assert b[0].checkpoint_every > 1
+    assert abs(a[1] - b[1]) <= 1e-12 * abs(a[1])
+    for x, y in zip(a[2:], b[2:]):
+        assert rel_l2(y, x) < 1e-6
+
+
+def test_autograd_rejects_stale_tape(cfg2):
+    from paper_2505_14372_amd.autograd import multislice_loss
+    c = cfg2
+    d = c.device()
+    prob = c.problem()
+    obj = d["obj"].clone().requires_grad_(True)
+    l1 = multislice_loss(obj, d["probe"], d["pos"], prob, d["pats"], d["batch"])
+    multislice_loss(obj, d["probe"], d["pos"], prob, d["pats"], d["batch"])
+    with pytest.raises(RuntimeError):
+        l1.backward()
+
+
+def test_torch_optimizer_step_decreases_loss(cfg2):
+    """A few Adam steps of torch.optim on the autograd loss reduce it."""
+    from paper_2505_14372_amd.autograd import multislice_loss
+    c = cfg2
+    d = c.device()
+    prob = c.problem()
+    obj = d["obj"].clone().requires_grad_(True)
+    probe = d["probe"].clone().requires_grad_(True)
+    opt = torch.optim.Adam([obj, probe], lr=1e-3)
+    losses = []
+    for _ in range(4):
+        opt.zero_grad()
+        loss = multislice_loss(obj, probe, d["pos"], prob, d["pats"], d["batch"])
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    assert losses[-1] < losses[0]

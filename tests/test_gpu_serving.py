@@ -1,0 +1,63 @@
+"""The continuous-batching server: results of every reconstruction served in
+a mix of sizes equal its results served alone, admission respects the HBM
+budget, and a request that can never fit is refused."""
+import numpy as np
+import pytest
+
+from _cases import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _stream(n, seed, iters=2):
+    from paper_2505_14372_amd import serving
+    return serving.make_request_stream(n, seed=seed, rate_per_s=50.0, n_iters=iters, sizes=(64, 128),
+                                       max_modes=3, max_slices=5, scans=(6, 10), steps=(4, 6), batch=32)
+
+
+def test_served_mix_equals_alone():
+    from paper_2505_14372_amd import serving
+    reqs = _stream(6, seed=3)
+    print([(r.rid, r.N, r.M, r.S, r.J) for r in reqs], flush=True)
+    srv = serving.Server(hbm_budget=64 << 30)
+    for r in reqs:
+        srv.submit(r)
+    mixed = srv.run()
+    alone = serving.run_fifo(reqs)
+    assert set(mixed) == set(alone) == {r.rid for r in reqs}
+    for r in reqs:
+        a, b = mixed[r.rid], alone[r.rid]
+        assert len(a.losses) == len(b.losses) == r.n_iters
+        for la, lb in zip(a.losses, b.losses):
+            assert abs(la - lb) <= 1e-5 * abs(lb)
+        for x, y in ((a.obj, b.obj), (a.probe, b.probe), (a.positions, b.positions)):
+            assert rel_l2(x, y) < 1e-5
+        # the state moved away from the initial guess
+        assert rel_l2(a.obj, r.obj.astype(np.complex64)) > 1e-6
+    p50, p99 = serving.latency_stats(mixed)
+    assert 0 < p50 <= p99
+
+
+def test_admission_respects_budget():
+    from paper_2505_14372_amd import api, serving
+    reqs = _stream(4, seed=4, iters=1)
+    one = max(r.resident_bytes() for r in reqs)
+    grp = sum(api.Group.workspace_bytes(n, t, t, t * serving.MAX_SLICES)
+              for n, t in serving.DEFAULT_GROUP_TILES.items() if n in {r.N for r in reqs})
+    budget = grp + int(1.5 * one)        # room for about one request at a time
+    srv = serving.Server(hbm_budget=budget)
+    for r in reqs:
+        srv.submit(r)
+    res = srv.run()
+    assert len(res) == 4
+    assert srv.peak_used <= budget
+
+
+def test_request_over_budget_is_refused():
+    from paper_2505_14372_amd import serving
+    reqs = _stream(1, seed=5, iters=1)
+    srv = serving.Server(hbm_budget=1 << 20)
+    srv.submit(reqs[0])
+    with pytest.raises(MemoryError):
+        srv.run()
