@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--cpu-positions", type=int, default=8)
     p.add_argument("--checkpoint-every", type=int, default=1)
     p.add_argument("--chunk", type=int, default=0)
+    p.add_argument("--checkpoint-half", action="store_true",
+                   help="store entry-wave checkpoints as IEEE half pairs (reduced-precision storage)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     p.add_argument("--requests", type=int, default=16, help="serving stream: number of reconstructions")
@@ -48,14 +50,16 @@ def parse():
     return p.parse_args()
 
 
-def kernel_bytes_per_launch(name, N, M, B, S):
+def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False):
     """Algorithmic HBM bytes one launch of a kernel class must move (complex64
-    tile T = 8 N^2 bytes, per launch over B positions and M modes)."""
+    tile T = 8 N^2 bytes, per launch over B positions and M modes; a
+    checkpoint is T, or T/2 when stored as half floats)."""
     T = 8 * N * N
+    C = T // 2 if ck_half else T
     if name == "row_fwd":      # read + write every mode tile, write the entry-wave checkpoint, read the object patch
-        return B * (3 * M + 1) * T
+        return B * (M * (2 * T + C) + T)
     if name == "row_adj":      # read + write tiles, read checkpoints, read object patch, RMW object gradient
-        return B * (3 * M + 3) * T
+        return B * (M * (2 * T + C) + 3 * T)
     if name in ("col_prop", "col_prop_adj"):   # read + write every tile
         return B * 2 * M * T
     if name == "far_loss":     # tiles read, far field written and re-read, seed written; pattern read
@@ -113,7 +117,7 @@ def main():
     for s0 in range(0, J, chunk):
         pats[s0:s0 + chunk].copy_(torch.from_numpy(wl.patterns[s0:s0 + chunk]))
     prob = api.Problem(N, M, S, H, W, J, dz=wl.dz, dx=wl.dx, wavelength=wl.wavelength, loss=wl.loss, eps=wl.eps,
-                       max_batch=B, checkpoint_every=args.checkpoint_every)
+                       max_batch=B, checkpoint_every=args.checkpoint_every, checkpoint_half=args.checkpoint_half)
     prob.set_chunk(args.chunk)
     state = api.ReconState(probe, obj, pos, adam=True)
     opt = api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2)
@@ -167,7 +171,7 @@ def main():
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_s = dom_ms / dom_n / 1000.0
-    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S)
+    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half)
     flops_launch = kernel_flops_per_launch(dom, N, M, B, S)
     gbs = bytes_launch / avg_s / 1e9
     tfl = flops_launch / avg_s / 1e12
@@ -177,7 +181,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
-    traffic = measured_traffic(dom)
+    traffic = None if prob.checkpoint_half else measured_traffic(dom)
     roof.update({"kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4),
                  "traffic": traffic, "algorithmic_bytes": bytes_launch, "algorithmic_flops": flops_launch})
     kernels = {k: {"total_ms": round(v[0], 3), "launches": int(v[1]), "avg_ms": round(v[0] / v[1], 4),
@@ -189,7 +193,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: probe {N}x{N}, {M} modes, {S} slices of {wl.dz[0] if S > 1 else 0} A, "
                                f"object {H}x{W}x{S} complex64, {J} positions, groups of {B}, Poisson loss, Adam",
-                   "global_batch": B, "checkpoint_every": prob.checkpoint_every},
+                   "global_batch": B, "checkpoint_every": prob.checkpoint_every,
+                   "checkpoint_storage": "f16" if prob.checkpoint_half else "f32"},
         "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
         "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
         "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),

@@ -114,6 +114,23 @@ typedef struct pty_ctx pty_ctx;
 pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every,
                       size_t hbm_budget, pty_ctx** out);
 
+/* Creation options (pty_create_ex). */
+typedef struct {
+  int32_t max_batch;         /* positions per group (workspace size) */
+  int32_t checkpoint_every;  /* as in pty_create */
+  size_t hbm_budget;         /* as in pty_create; 0 = no limit */
+  int32_t checkpoint_half;   /* 1: store entry-wave checkpoints as pairs of IEEE
+                                half floats (round to nearest), halving their HBM
+                                traffic; only the object gradient reads them */
+} pty_options;
+
+/* pty_create with the options above; pty_create(g, b, k, budget, out) equals
+ * pty_create_ex with checkpoint_half = 0. */
+pty_status pty_create_ex(const pty_geometry* g, const pty_options* opt, pty_ctx** out);
+pty_status pty_workspace_bytes_ex(const pty_geometry* g, const pty_options* opt, size_t* bytes);
+/* Checkpoint storage chosen at create (1 = half floats). */
+int32_t pty_checkpoint_half(const pty_ctx* ctx);
+
 /* Device bytes pty_create would allocate for these arguments. */
 pty_status pty_workspace_bytes(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every,
                                size_t* bytes);

@@ -21,7 +21,8 @@ PTY_POS_DENSE = 2
 
 # every exported symbol of include/pty.h
 EXPORTS = (
-    "pty_create", "pty_workspace_bytes", "pty_checkpoint_every", "pty_set_chunk", "pty_forward", "pty_loss_and_grad",
+    "pty_create", "pty_create_ex", "pty_workspace_bytes", "pty_workspace_bytes_ex", "pty_checkpoint_every",
+    "pty_checkpoint_half", "pty_set_chunk", "pty_forward", "pty_loss_and_grad",
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
@@ -35,6 +36,11 @@ class Geometry(C.Structure):
         ("dx", C.c_double), ("wavelength", C.c_double), ("dz", C.POINTER(C.c_double)),
         ("bandlimit", C.c_double), ("loss", C.c_int32), ("eps", C.c_double), ("sigma", C.c_double),
     ]
+
+
+class Options(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("checkpoint_every", C.c_int32), ("hbm_budget", C.c_size_t),
+                ("checkpoint_half", C.c_int32)]
 
 
 class State(C.Structure):
@@ -76,6 +82,9 @@ def load():
     sig = {
         "pty_create": ([C.POINTER(Geometry), i32, i32, sz, C.POINTER(vp)], i32),
         "pty_workspace_bytes": ([C.POINTER(Geometry), i32, i32, C.POINTER(sz)], i32),
+        "pty_create_ex": ([C.POINTER(Geometry), C.POINTER(Options), C.POINTER(vp)], i32),
+        "pty_workspace_bytes_ex": ([C.POINTER(Geometry), C.POINTER(Options), C.POINTER(sz)], i32),
+        "pty_checkpoint_half": ([vp], i32),
         "pty_checkpoint_every": ([vp], i32),
         "pty_set_chunk": ([vp, i32], i32),
         "pty_forward": ([vp, vp, vp, vp, vp, vp, i32, vp, vp, vp], i32),

@@ -93,12 +93,13 @@ def _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma)
 
 
 def workspace_bytes(N, M, S, H, W, J, max_batch, checkpoint_every=1, dx=0.2, wavelength=0.019688,
-                    dz=None, bandlimit=2 / 3, loss="poisson", eps=0.0, sigma=1.0):
+                    dz=None, bandlimit=2 / 3, loss="poisson", eps=0.0, sigma=1.0, checkpoint_half=False):
     lib = _lib.load()
     g, _keep = _geometry(N, M, S, H, W, J, dx, wavelength, dz if dz is not None else [1.0] * (S - 1),
                          bandlimit, loss, eps, sigma)
     out = C.c_size_t()
-    st = lib.pty_workspace_bytes(C.byref(g), max_batch, checkpoint_every, C.byref(out))
+    opt = _lib.Options(max_batch, checkpoint_every, 0, 1 if checkpoint_half else 0)
+    st = lib.pty_workspace_bytes_ex(C.byref(g), C.byref(opt), C.byref(out))
     if st:
         raise PtyError(st, "pty_workspace_bytes")
     return out.value
@@ -110,7 +111,7 @@ class Problem:
     def __init__(self, N: int, M: int, S: int, H: int, W: int, J: int, dz: Sequence[float] = (),
                  dx: float = 0.2, wavelength: float = 0.019688, bandlimit: float = 2 / 3,
                  loss: str = "poisson", eps: float = 0.0, sigma: float = 1.0, max_batch: int = 256,
-                 checkpoint_every: int = 1, hbm_budget: int = 0):
+                 checkpoint_every: int = 1, hbm_budget: int = 0, checkpoint_half: bool = False):
         self.lib = _lib.load()
         self.N, self.M, self.S, self.H, self.W, self.J = N, M, S, H, W, J
         self.loss_kind = loss
@@ -118,11 +119,13 @@ class Problem:
         g, self._dz_keep = _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma)
         self._g = g
         ctx = C.c_void_p()
-        st = self.lib.pty_create(C.byref(g), max_batch, checkpoint_every, hbm_budget, C.byref(ctx))
+        opt = _lib.Options(max_batch, checkpoint_every, hbm_budget, 1 if checkpoint_half else 0)
+        st = self.lib.pty_create_ex(C.byref(g), C.byref(opt), C.byref(ctx))
         if st:
             raise PtyError(st, "pty_create")
         self.ctx = ctx
         self.checkpoint_every = self.lib.pty_checkpoint_every(ctx)
+        self.checkpoint_half = bool(self.lib.pty_checkpoint_half(ctx))
         self.tape_id = 0          # incremented by every forward_save (identifies the tape)
 
     def close(self):

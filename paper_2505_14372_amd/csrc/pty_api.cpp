@@ -81,8 +81,9 @@ struct Sizes {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Device bytes of one context (fixed part + batch workspace).
-Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k) {
+// Device bytes of one context (fixed part + batch workspace); checkpoints and
+// segment buffers hold ck_elem bytes per complex value.
+Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8) {
   Sizes s;
   const size_t N2 = (size_t)g->N * g->N;
   const int S = g->n_slices, M = g->n_modes;
@@ -100,7 +101,8 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k) {
   b += align256(sizeof(int) * 4);                                   // flags
   if (max_batch > 0) {
     const int nblk = col_blocks(g->N);
-    b += align256((s.tiles + s.ck_tiles + s.seg_tiles + s.ws2_tiles) * N2 * sizeof(float2));
+    b += align256((s.tiles + s.ws2_tiles) * N2 * sizeof(float2));
+    b += align256((s.ck_tiles + s.seg_tiles) * N2 * (size_t)ck_elem);
     b += align256((size_t)max_batch * sizeof(Item));
     b += align256((size_t)max_batch * 2 * g->N * sizeof(float2));
     b += align256((size_t)max_batch * nblk * sizeof(float));
@@ -182,7 +184,9 @@ struct pty_ctx {
   float2 *tw = nullptr, *prop = nullptr, *phat = nullptr, *gphat = nullptr, *gprobe = nullptr, *gobj = nullptr;
   float* gpos = nullptr;
   int* flags = nullptr;
-  float2 *ws = nullptr, *ws2 = nullptr, *ck = nullptr, *seg = nullptr;
+  float2 *ws = nullptr, *ws2 = nullptr;
+  unsigned char *ck = nullptr, *seg = nullptr;   // checkpoint storage (float2 or __half2)
+  int ck_half = 0;
   Item* items = nullptr;
   float2* ramps = nullptr;
   float *loss_part = nullptr, *pos_part = nullptr;
@@ -243,6 +247,7 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
   L.items = c->items;
   L.ws = c->ws;
   L.ck = c->ck;
+  L.ck_half = c->ck_half;
   L.ramps = c->ramps;
   L.tw = c->tw;
   L.loss_part = c->loss_part;
@@ -299,7 +304,7 @@ void run_finish_forward(const LaunchCtx& L, int N) {
 // Single-request contexts may use checkpoint intervals k > 1 (entry waves
 // recomputed per segment); grouped launches store every slice.
 void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<int>& final_steps, float scale,
-                        int k, float2* ws2, float2* seg) {
+                        int k, float2* ws2, void* seg) {
   int seg_lo = -1, seg_hi = -1;   // slices currently held in the segment buffer
   for (int t = 0; t < S_max; ++t) {
     const int i = S_max - 1 - t;   // single-request slice index (k > 1 only)
@@ -390,20 +395,22 @@ pty_status pty_workspace_bytes(const pty_geometry* g, int32_t max_batch, int32_t
 
 int32_t pty_checkpoint_every(const pty_ctx* ctx) { return ctx ? ctx->ck_every : 0; }
 
-pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every, size_t hbm_budget,
-                      pty_ctx** out) {
-  if (!out) return PTY_EINVAL;
+pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** out) {
+  if (!out || !o) return PTY_EINVAL;
   *out = nullptr;
   std::string err;
   pty_status st = validate_geometry(g, err);
   if (st != PTY_OK) return st;
+  const int max_batch = o->max_batch, checkpoint_every = o->checkpoint_every;
+  const size_t hbm_budget = o->hbm_budget;
   if (max_batch < 0 || checkpoint_every < 0) return PTY_EINVAL;
+  const int ck_elem = o->checkpoint_half ? 4 : 8;
   const int S = g->n_slices;
   int k = checkpoint_every;
   if (k == 0) {
     k = 1;
     if (hbm_budget > 0) {
-      while (k <= S && ctx_sizes(g, max_batch, k).bytes > hbm_budget) ++k;
+      while (k <= S && ctx_sizes(g, max_batch, k, ck_elem).bytes > hbm_budget) ++k;
       if (k > S) return PTY_ENOMEM;
     }
   }
@@ -415,7 +422,8 @@ pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoi
   c->max_batch = max_batch;
   c->ck_every = k;
   c->n_ck = (S + k - 1) / k;
-  c->sz = ctx_sizes(g, max_batch, k);
+  c->ck_half = o->checkpoint_half ? 1 : 0;
+  c->sz = ctx_sizes(g, max_batch, k, ck_elem);
   const int N = g->N, M = g->n_modes;
   const size_t N2 = (size_t)N * N;
   std::string& e = c->err;
@@ -428,8 +436,8 @@ pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoi
     return fail(st);
   if (max_batch > 0) {
     const int nblk = col_blocks(N);
-    if ((st = dmalloc(&c->ws, c->sz.tiles * N2, e)) || (st = dmalloc(&c->ck, c->sz.ck_tiles * N2, e)) ||
-        (st = dmalloc(&c->seg, c->sz.seg_tiles * N2, e)) || (st = dmalloc(&c->ws2, c->sz.ws2_tiles * N2, e)) ||
+    if ((st = dmalloc(&c->ws, c->sz.tiles * N2, e)) || (st = dmalloc(&c->ck, c->sz.ck_tiles * N2 * ck_elem, e)) ||
+        (st = dmalloc(&c->seg, c->sz.seg_tiles * N2 * ck_elem, e)) || (st = dmalloc(&c->ws2, c->sz.ws2_tiles * N2, e)) ||
         (st = dmalloc(&c->items, (size_t)max_batch, e)) || (st = dmalloc(&c->ramps, (size_t)max_batch * 2 * N, e)) ||
         (st = dmalloc(&c->loss_part, (size_t)max_batch * nblk, e)) ||
         (st = dmalloc(&c->pos_part, (size_t)max_batch * M * nblk * 2, e)))
@@ -446,6 +454,27 @@ pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoi
   *out = c;
   return PTY_OK;
 }
+
+pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every, size_t hbm_budget,
+                      pty_ctx** out) {
+  pty_options o{};
+  o.max_batch = max_batch;
+  o.checkpoint_every = checkpoint_every;
+  o.hbm_budget = hbm_budget;
+  o.checkpoint_half = 0;
+  return pty_create_ex(g, &o, out);
+}
+
+pty_status pty_workspace_bytes_ex(const pty_geometry* g, const pty_options* o, size_t* bytes) {
+  std::string err;
+  pty_status st = validate_geometry(g, err);
+  if (st != PTY_OK) return st;
+  if (!bytes || !o || o->max_batch < 0 || o->checkpoint_every < 1) return PTY_EINVAL;
+  *bytes = ctx_sizes(g, o->max_batch, std::min<int>(o->checkpoint_every, g->n_slices), o->checkpoint_half ? 4 : 8).bytes;
+  return PTY_OK;
+}
+
+int32_t pty_checkpoint_half(const pty_ctx* ctx) { return ctx ? ctx->ck_half : 0; }
 
 void pty_destroy(pty_ctx* c) {
   if (!c) return;
@@ -754,6 +783,7 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   L.items = G->items;
   L.ws = G->ws;
   L.ck = G->ck;
+  L.ck_half = 0;
   L.ramps = G->ramps;
   L.tw = G->tw;
   L.loss_part = G->loss_part;

@@ -58,9 +58,9 @@ struct ReqTable {
 // Where the forward row pass stores entry waves.
 struct PsiStore {
   int mode;                 // 0: nowhere, 1: checkpoint slots, 2: segment buffer
-  float2* seg;              // segment buffer [tiles][seg_len][N][N]
+  void* seg;                // segment buffer [tiles][seg_len][N][N] (checkpoint storage type)
   int seg_len, seg_slot;
-  const float2* src;        // FROM_REAL source (checkpoint buffer)
+  const void* src;          // FROM_REAL source (checkpoint buffer)
   int src_slot;
   int stop_after_store;     // skip the transmission and forward DFT
 };
@@ -68,7 +68,7 @@ struct PsiStore {
 // Where the adjoint row pass reads entry waves.
 struct PsiLoad {
   int from_seg;             // 0: checkpoint slot i / ck_every, 1: segment buffer
-  const float2* seg;
+  const void* seg;
   int seg_len, seg_base;    // slice i is at slot i - seg_base
 };
 
@@ -79,7 +79,8 @@ struct LaunchCtx {
   int item_off;             // first item of this launch (chunked schedules)
   Item* items;
   float2* ws;               // tile workspace
-  float2* ck;               // checkpoint buffer
+  void* ck;                 // checkpoint buffer (float2, or __half2 when ck_half)
+  int ck_half;
   float2* ramps;            // [n_items][2][N]
   const float2* tw;         // [N] roots of unity
   float* loss_part;         // [n_items][col blocks]

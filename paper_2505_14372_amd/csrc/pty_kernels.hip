@@ -19,6 +19,8 @@
 // multipliers and accumulates the object gradient in the row pass.
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_fp16.h>
+
 #include "pty_fft.hpp"
 #include "pty_internal.h"
 
@@ -47,22 +49,34 @@ __device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw_g
 #define PTY_NT_CKPT 0
 #endif
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-// Checkpoint stores/loads: streamed past the caches when PTY_NT_CKPT is set.
-__device__ __forceinline__ void ck_store(float2* p, float2 v) {
-  if (PTY_NT_CKPT) {
-    f32x2 w = {v.x, v.y};
-    __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p));
-  } else {
-    *p = v;
+
+// Entry-wave checkpoint storage: complex64 (float2) or two IEEE halves
+// (__half2, round to nearest). Stores/loads bypass the caches when
+// PTY_NT_CKPT is set.
+template <bool HALF> struct Ck;
+template <> struct Ck<false> {
+  using T = float2;
+  __device__ __forceinline__ static void store(T* p, float2 v) {
+    if (PTY_NT_CKPT) {
+      f32x2 w = {v.x, v.y};
+      __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p));
+    } else {
+      *p = v;
+    }
   }
-}
-__device__ __forceinline__ float2 ck_load(const float2* p) {
-  if (PTY_NT_CKPT) {
-    f32x2 w = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
-    return make_float2(w.x, w.y);
+  __device__ __forceinline__ static float2 load(const T* p) {
+    if (PTY_NT_CKPT) {
+      f32x2 w = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+      return make_float2(w.x, w.y);
+    }
+    return *p;
   }
-  return *p;
-}
+};
+template <> struct Ck<true> {
+  using T = __half2;
+  __device__ __forceinline__ static void store(T* p, float2 v) { *p = __floats2half2_rn(v.x, v.y); }
+  __device__ __forceinline__ static float2 load(const T* p) { return __half22float2(*p); }
+};
 
 // ============================================================ items
 
@@ -118,10 +132,10 @@ __global__ void k_items(const ReqTable reqs, int n_reqs, Item* __restrict__ item
 //   psi = IDFT_x(tile row) ; [checkpoint psi] ; phi = psi * O_i ; tile row = DFT_x(phi)
 // With FROM_REAL the entry wave is read from a real-space buffer (the start
 // of a recomputed segment) instead of inverse-transforming the tile.
-template <int N, bool FROM_REAL>
+template <int N, bool FROM_REAL, bool HALF>
 __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ items,
                                                       const ReqTable reqs,
-                                                      float2* __restrict__ ws, float2* __restrict__ ck,
+                                                      float2* __restrict__ ws, void* __restrict__ ck_,
                                                       const float2* __restrict__ twg, int step,
                                                       PsiStore store, int item_off) {
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
@@ -133,6 +147,8 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
   if (!it.valid || i >= r.S) return;
   load_twiddles<N>(tw, twg);
   __syncthreads();
+  using CT = typename Ck<HALF>::T;
+  CT* ck = static_cast<CT*>(ck_);
   const int l = threadIdx.x % L, line = threadIdx.x / L;
   const int y = blockIdx.x * LINES + line;
   float2* sx = xch + line * Xch<N>::ROW_STRIDE;
@@ -146,22 +162,22 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
     if constexpr (FROM_REAL) {
-      const float2* src = store.src + (((size_t)it.ck0 + (size_t)m * n_ck + store.src_slot) * N + y) * N;
+      const CT* src = static_cast<const CT*>(store.src) + (((size_t)it.ck0 + (size_t)m * n_ck + store.src_slot) * N + y) * N;
 #pragma unroll
-      for (int a = 0; a < E; ++a) v[a] = src[l + L * a];
+      for (int a = 0; a < E; ++a) v[a] = Ck<HALF>::load(src + l + L * a);
     } else {
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = trow[l + L * a];
       line_fft<N, true>(v, l, tw, sx, WaveSync{});
     }
     if (store.mode == 1 && (i % r.ck_every) == 0) {
-      float2* dst = ck + (((size_t)it.ck0 + (size_t)m * n_ck + i / r.ck_every) * N + y) * N;
+      CT* dst = ck + (((size_t)it.ck0 + (size_t)m * n_ck + i / r.ck_every) * N + y) * N;
 #pragma unroll
-      for (int a = 0; a < E; ++a) ck_store(dst + l + L * a, v[a]);
+      for (int a = 0; a < E; ++a) Ck<HALF>::store(dst + l + L * a, v[a]);
     } else if (store.mode == 2) {
-      float2* dst = store.seg + (((size_t)(it.tile0 + m) * store.seg_len + store.seg_slot) * N + y) * N;
+      CT* dst = static_cast<CT*>(store.seg) + (((size_t)(it.tile0 + m) * store.seg_len + store.seg_slot) * N + y) * N;
 #pragma unroll
-      for (int a = 0; a < E; ++a) dst[l + L * a] = v[a];
+      for (int a = 0; a < E; ++a) Ck<HALF>::store(dst + l + L * a, v[a]);
     }
     if (store.stop_after_store) continue;
 #pragma unroll
@@ -176,10 +192,10 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 //   g = IDFT_x(tile row)                (gradient wrt phi_i, real space)
 //   grad O_i += sum_m conj(psi_i,m) g   (scatter-added into the object gradient)
 //   h = conj(O_i) g ; tile row = DFT_x(h)
-template <int N>
+template <int N, bool HALF>
 __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ items,
                                                       const ReqTable reqs,
-                                                      float2* __restrict__ ws, const float2* __restrict__ ck,
+                                                      float2* __restrict__ ws, const void* __restrict__ ck_,
                                                       const float2* __restrict__ twg, int step,
                                                       PsiLoad psi, float scale, int item_off) {
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
@@ -194,6 +210,8 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   const int l = threadIdx.x % L, line = threadIdx.x / L;
   const int y = blockIdx.x * LINES + line;
   float2* sx = xch + line * Xch<N>::ROW_STRIDE;
+  using CT = typename Ck<HALF>::T;
+  const CT* ck = static_cast<const CT*>(ck_);
   float2 o[E], acc[E];
   const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
 #pragma unroll
@@ -204,12 +222,12 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) v[a] = trow[l + L * a];
     line_fft<N, true>(v, l, tw, sx, WaveSync{});
-    const float2* prow;
-    if (psi.from_seg) prow = psi.seg + (((size_t)(it.tile0 + m) * psi.seg_len + (i - psi.seg_base)) * N + y) * N;
+    const CT* prow;
+    if (psi.from_seg) prow = static_cast<const CT*>(psi.seg) + (((size_t)(it.tile0 + m) * psi.seg_len + (i - psi.seg_base)) * N + y) * N;
     else prow = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i / r.ck_every) * N + y) * N;
 #pragma unroll
     for (int a = 0; a < E; ++a) {
-      float2 p = ck_load(prow + l + L * a);
+      float2 p = Ck<HALF>::load(prow + l + L * a);
       acc[a] = cadd(acc[a], cjmul(p, v[a]));
       v[a] = cjmul(o[a], v[a]);
     }
@@ -618,16 +636,24 @@ static inline dim3 grid1(size_t n) {
 
 template <int N>
 struct Launch {
-  static void rows_fwd(const LaunchCtx& L, int step, PsiStore st, bool from_real) {
+  template <bool HALF>
+  static void rows_fwd_t(const LaunchCtx& L, int step, PsiStore st, bool from_real) {
     dim3 g(Pass<N>::NBLK, L.n_items);
     if (from_real)
-      hipLaunchKernelGGL((k_row_fwd<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
+      hipLaunchKernelGGL((k_row_fwd<N, true, HALF>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
     else
-      hipLaunchKernelGGL((k_row_fwd<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
+      hipLaunchKernelGGL((k_row_fwd<N, false, HALF>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
+  }
+  static void rows_fwd(const LaunchCtx& L, int step, PsiStore st, bool from_real) {
+    if (L.ck_half) rows_fwd_t<true>(L, step, st, from_real);
+    else rows_fwd_t<false>(L, step, st, from_real);
   }
   static void rows_adj(const LaunchCtx& L, int step, PsiLoad psi, float scale) {
     dim3 g(Pass<N>::NBLK, L.n_items);
-    hipLaunchKernelGGL((k_row_adj<N>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+    if (L.ck_half)
+      hipLaunchKernelGGL((k_row_adj<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+    else
+      hipLaunchKernelGGL((k_row_adj<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
   }
   static void col(const LaunchCtx& L, int op, int step) {
     dim3 g(ColPass<N>::NBLK, L.n_items, L.max_modes);

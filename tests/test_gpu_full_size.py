@@ -73,3 +73,30 @@ def test_full_size_two_position_gradients(full):
     assert rel_l2(_np(gO), ref["g_object"]) < 1e-3
     assert rel_l2(_np(gP), ref["g_probe"]) < 1e-3
     assert rel_l2(_np(gX), ref["g_pos"]) < 1e-3
+
+
+def test_full_size_half_checkpoints(full):
+    """Half-precision entry-wave checkpoints at full size: a two-position group
+    against the oracle, and the whole group against the float32 checkpoints."""
+    c = full
+    sub = Case(c.wl, batch=c.batch[[10, 11]])
+    ref = sub.oracle_grad()
+    d = sub.device()
+    prob = sub.problem(max_batch=2, checkpoint_half=True)
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    assert abs(loss.item() - ref["loss"]) < 1e-4 * abs(ref["loss"])
+    assert rel_l2(_np(gO), ref["g_object"]) < 1e-3
+    assert rel_l2(_np(gP), ref["g_probe"]) < 1e-3
+    assert rel_l2(_np(gX), ref["g_pos"]) < 1e-3
+    d = c.device()
+    full32 = c.problem(max_batch=B)
+    full16 = c.problem(max_batch=B, checkpoint_half=True)
+    a = full32.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    del full32
+    b = full16.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    full16.check()
+    assert a[0].item() == b[0].item()
+    for x, y in zip(a[1:], b[1:]):
+        print(rel_l2(_np(y), _np(x)))
+        assert rel_l2(_np(y), _np(x)) < 1e-3

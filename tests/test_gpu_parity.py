@@ -291,3 +291,21 @@ def test_group_step_matches_single_steps(kind):
                 assert max_rel(_np(a), _np(b)) < 1e-5
             else:
                 assert rel_l2(_np(a), _np(b)) < 1e-4
+
+
+@pytest.mark.parametrize("name,k", [("n64_ms_poisson", 1), ("n128_ms_poisson", 1), ("n256_ms_gaussian", 1),
+                                    ("n64_ms_poisson", 2)])
+def test_half_checkpoints_parity(cache, name, k):
+    """Entry waves stored as IEEE halves (with and without recompute): loss and
+    intensities are unchanged, gradients stay within the 1e-3 bar."""
+    c, ref = _get(cache, name)
+    d = c.device()
+    prob = c.problem(checkpoint_every=k, checkpoint_half=True)
+    assert prob.checkpoint_half
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    errs = dict(obj=rel_l2(_np(gO), ref["g_object"]), probe=rel_l2(_np(gP), ref["g_probe"]),
+                pos=rel_l2(_np(gX), ref["g_pos"]))
+    print(errs)
+    assert all(e < TOL_G for e in errs.values()), errs
