@@ -35,12 +35,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=32)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--batch", type=int, default=512)
+    p.add_argument("--batch", type=int, default=0, help="positions per group (0: the workload's)")
     p.add_argument("--workload", default="cfg3_ms256")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-positions", type=int, default=8)
     p.add_argument("--checkpoint-every", type=int, default=1)
     p.add_argument("--chunk", type=int, default=0)
+    p.add_argument("--strategy", default="auto", choices=["auto", "two_pass", "resident"])
     p.add_argument("--checkpoint-half", action="store_true",
                    help="store entry-wave checkpoints as IEEE half pairs (reduced-precision storage)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -106,7 +107,7 @@ def main():
     t0 = time.time()
     wl = synth.make_workload(args.workload, pattern_pool=64)
     N, M, S, H, W, J = wl.N, wl.M, wl.S, wl.H, wl.W, wl.J
-    B = args.batch
+    B = args.batch if args.batch > 0 else wl.batch
     print(f"[bench] inputs built in {time.time() - t0:.1f}s: N={N} M={M} S={S} object {H}x{W}x{S} J={J} B={B}",
           file=sys.stderr, flush=True)
     probe = torch.from_numpy(wl.probe.astype(np.complex64)).to(dev)
@@ -119,6 +120,7 @@ def main():
     prob = api.Problem(N, M, S, H, W, J, dz=wl.dz, dx=wl.dx, wavelength=wl.wavelength, loss=wl.loss, eps=wl.eps,
                        max_batch=B, checkpoint_every=args.checkpoint_every, checkpoint_half=args.checkpoint_half)
     prob.set_chunk(args.chunk)
+    prob.set_strategy(args.strategy)
     state = api.ReconState(probe, obj, pos, adam=True)
     opt = api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2)
     rng = np.random.default_rng(12345)
@@ -194,7 +196,7 @@ def main():
         "config": {"workload": f"{args.workload}: probe {N}x{N}, {M} modes, {S} slices of {wl.dz[0] if S > 1 else 0} A, "
                                f"object {H}x{W}x{S} complex64, {J} positions, groups of {B}, Poisson loss, Adam",
                    "global_batch": B, "checkpoint_every": prob.checkpoint_every,
-                   "checkpoint_storage": "f16" if prob.checkpoint_half else "f32"},
+                   "checkpoint_storage": "f16" if prob.checkpoint_half else "f32", "strategy": args.strategy},
         "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
         "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
         "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),

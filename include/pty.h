@@ -21,7 +21,8 @@
  *   - the propagator for gap dz is H(u) = B(u) exp(-i pi lambda dz |q|^2),
  *     q = fftfreq(N) / dx, B the circular band limit
  *     k_y^2 + k_x^2 <= (bandlimit * N / 2)^2 on signed integer bins
- *     (inclusive; bandlimit <= 0 disables it);
+ *     (inclusive; bandlimit <= 0 disables it) or a caller-given mask, times
+ *     the tilt phase exp(2 pi i dz q.tan(tilt));
  *   - S slices have S-1 gaps: S-1 propagations, none after the last slice;
  *   - position X_j = (row, col) of the window's top-left corner in object
  *     pixels; the window starts at n_j = floor(X_j + 0.5) and the probe is
@@ -101,6 +102,10 @@ typedef struct {
   int32_t loss;         /* pty_loss_kind */
   double eps;           /* noise-model epsilon (Sec. 3.1) */
   double sigma;         /* Gaussian noise standard deviation */
+  double tilt_y, tilt_x;  /* propagator tilt (Sec. 1), radians: every gap also
+                             multiplies by exp(2 pi i dz (q_y tan tilt_y + q_x tan tilt_x)) */
+  const uint8_t* bandlimit_mask;  /* optional host [N][N] mask in FFT order (nonzero =
+                                     kept) replacing the circular limit; copied */
 } pty_geometry;
 
 typedef struct pty_ctx pty_ctx;
@@ -137,6 +142,16 @@ pty_status pty_workspace_bytes(const pty_geometry* g, int32_t max_batch, int32_t
 
 /* Checkpoint interval chosen at create (1 = store all). */
 int32_t pty_checkpoint_every(const pty_ctx* ctx);
+
+/* Kernel strategy. TWO_PASS: every slice step is a row pass and a column pass
+ * over tiles in the workspace (all N). RESIDENT: for N = 64 and 128 a tile fits
+ * in LDS and one workgroup per (position, mode) runs every slice with its
+ * tile resident (used when every slice is checkpointed, else two-pass).
+ * AUTO (default): RESIDENT where it applies, else TWO_PASS. */
+#define PTY_STRATEGY_AUTO 0
+#define PTY_STRATEGY_TWO_PASS 1
+#define PTY_STRATEGY_RESIDENT 2
+pty_status pty_set_strategy(pty_ctx* ctx, int32_t strategy);
 
 /* Schedule of pty_loss_and_grad and pty_reconstruct_step: the group is taken
  * through the forward and adjoint passes in consecutive chunks of
@@ -197,6 +212,32 @@ typedef struct {
   double lr_object, lr_probe, lr_pos;   /* 0 freezes a variable */
   double beta1, beta2, eps;             /* Adam */
 } pty_optim;
+
+/* Regularization (Sec. 3.4), applied by pty_reconstruct_step and grouped
+ * steps of this context. Cost regularizers add lambda * R to the group loss
+ * and lambda * dR to the gradients before the optimiser:
+ *   obj_l2          sum |O - 1|^2 (distance from vacuum)
+ *   probe_l2        sum |P|^2
+ *   obj_l1          sum |O - 1|
+ *   obj_tikhonov    sum over slices of |D_y O|^2 + |D_x O|^2 (forward differences, no wrap)
+ *   obj_tv          sum over slices of phi(D_y O) + phi(D_x O), phi(z) = sqrt(|z|^2 + tv_delta^2)
+ *   layers_tikhonov sum |O_{i+1} - O_i|^2
+ *   layers_tv       sum phi(O_{i+1} - O_i)
+ * Constraint regularizers are applied to the state after the optimiser:
+ *   amp_clamp       object amplitude limited to [amp_min, amp_max] (phase kept)
+ *   probe_support   host [N][N] reciprocal-space mask (FFT order) or NULL: P <- F^-1(mask F(P))
+ *   layer_sigma     Gaussian blur along depth (sigma in slices, truncated at 3 sigma, normalised,
+ *                   real space; 0 = off; at most 64 slices)
+ * A NULL argument turns all regularization off. */
+typedef struct {
+  double obj_l2, probe_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta;
+  int32_t amp_clamp;
+  double amp_min, amp_max;
+  const uint8_t* probe_support;
+  double layer_sigma;
+} pty_regularizers;
+
+pty_status pty_set_regularizers(pty_ctx* ctx, const pty_regularizers* reg);
 
 /* One gradient step on one group (Sec. 2.2 engine loop, Sec. 3.2 solver):
  * loss and gradients of the group, then SGD (theta -= lr g) or Adam (per real

@@ -20,7 +20,8 @@ Readings fixed where the paper is silent:
 * F is the unitary 2D DFT (numpy ``norm="ortho"``); detector in FFT order.
 * Propagator H(u) = B(u) exp(-i pi lambda dz |q|^2), q = fftfreq(N)/dx in 1/A;
   B is a circular band limit k_y^2 + k_x^2 <= (f N / 2)^2 on signed integer
-  bins (inclusive), f = 2/3 by default, f <= 0 disables it.
+  bins (inclusive), f = 2/3 by default, f <= 0 disables it, or any mask the
+  caller gives. A beam tilt t multiplies H by exp(2 pi i dz q.tan(t)).
 * S slices have S-1 gaps, hence S-1 propagations and none after the last slice.
 * Positions X_j = (row, col) of the window's top-left corner in object pixels;
   n_j = floor(X_j + 0.5) is the integer window offset and d_j = X_j - n_j in
@@ -31,6 +32,7 @@ Readings fixed where the paper is silent:
 * Complex gradients are dL/dRe + i dL/dIm (= 2 dL/dconj(z)), the PyTorch
   convention; the paper's conj(dL/dz) differs by the positive factor 2.
 * Losses are sums over pixels and over the positions of the group.
+* Regularizers (Sec. 3.4): formulas fixed below, next to their code.
 
 Parity status: every function below is pinned by tests under ``tests/``
 (brute-force DFT, unitarity, closed-form Gaussian beam, strong-phase-object
@@ -40,7 +42,7 @@ tests, invariants, torch.optim.Adam).
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import Sequence
+from typing import Optional, Sequence
 
 import numpy as np
 
@@ -58,6 +60,12 @@ class Geometry:
     loss: str = "poisson"
     eps: float = 0.0
     sigma: float = 1.0
+    tilt: Sequence[float] = (0.0, 0.0)   # beam tilt (theta_y, theta_x) in radians
+    bandlimit_mask: Optional[np.ndarray] = None   # custom band-limit mask [N][N] (FFT order); overrides bandlimit
+
+    def props(self, S):
+        return [propagator(self.N, self.dx, self.wavelength, self.dz[i], self.bandlimit, self.tilt,
+                           self.bandlimit_mask) for i in range(S - 1)]
 
 
 # --------------------------------------------------------------------------
@@ -101,17 +109,22 @@ def bandlimit_mask(N, frac):
     return k2 <= r * r * (1.0 + 1e-9)
 
 
-def propagator(N, dx, wavelength, dz, frac):
-    """Fresnel free-space propagator in Fourier space (Sec. 3, p(dz)).
+def propagator(N, dx, wavelength, dz, frac, tilt=(0.0, 0.0), mask=None):
+    """Fresnel free-space propagator in Fourier space (Sec. 3, p(dz)), with
+    the propagator tilt of Sec. 1 and the customizable band limit of Sec. 3.
 
-    H(u) = B(u) exp(-i pi lambda dz (q_y^2 + q_x^2)), q = u / dx in 1/Angstrom.
-    Convolution with p(dz) in real space is multiplication by H after the
-    forward DFT.
+    H(u) = B(u) exp(-i pi lambda dz (q_y^2 + q_x^2) + 2 pi i dz (q_y tan t_y + q_x tan t_x)),
+    q = u / dx in 1/Angstrom. Convolution with p(dz) in real space is
+    multiplication by H after the forward DFT; the tilt term moves the wave by
+    -dz tan(t) per gap. B is `mask` when given (any shape, FFT order), else
+    the circular limit of `frac`.
     """
     q = freq(N) / dx
     q2 = q[:, None] ** 2 + q[None, :] ** 2
-    H = np.exp(-1j * np.pi * wavelength * dz * q2)
-    return H * bandlimit_mask(N, frac)
+    ramp = q[:, None] * np.tan(tilt[0]) + q[None, :] * np.tan(tilt[1])
+    H = np.exp(-1j * np.pi * wavelength * dz * q2 + 2j * np.pi * dz * ramp)
+    B = bandlimit_mask(N, frac) if mask is None else (np.asarray(mask) != 0)
+    return H * B
 
 
 def split_positions(X):
@@ -148,8 +161,7 @@ def forward_position(probe, obj, X, geom: Geometry, props=None):
     n, d = split_positions(X)
     check_window(n, N, obj.shape[1], obj.shape[2])
     if props is None:
-        props = [propagator(N, geom.dx, geom.wavelength, geom.dz[i], geom.bandlimit)
-                 for i in range(S - 1)]
+        props = geom.props(S)
     R = shift_ramp(N, d)
     psi = [ifft2u(fft2u(probe) * R)]                      # Psi_0 = P(r - X_j)
     for i in range(S):
@@ -167,8 +179,7 @@ def forward(probe, obj, positions, batch_idx, geom: Geometry):
     probe = np.asarray(probe, dtype=np.complex128)
     obj = np.asarray(obj, dtype=np.complex128)
     S = obj.shape[0]
-    props = [propagator(geom.N, geom.dx, geom.wavelength, geom.dz[i], geom.bandlimit)
-             for i in range(S - 1)]
+    props = geom.props(S)
     return np.stack([forward_position(probe, obj, positions[j], geom, props)[2]
                      for j in batch_idx])
 
@@ -234,8 +245,7 @@ def loss_and_grad(probe, obj, positions, patterns, batch_idx, geom: Geometry):
     N = geom.N
     M = probe.shape[0]
     S = obj.shape[0]
-    props = [propagator(N, geom.dx, geom.wavelength, geom.dz[i], geom.bandlimit)
-             for i in range(S - 1)]
+    props = geom.props(S)
     probe_hat = fft2u(probe)
     u = freq(N)
     g_obj = np.zeros_like(obj)
@@ -328,7 +338,9 @@ def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
 
     state: dict with probe, object, positions and, for Adam, m_/v_ moments
     per variable and the step counter t (number of steps already taken).
-    opt: dict(kind='sgd'|'adam', lr_object, lr_probe, lr_pos, beta1, beta2, eps).
+    opt: dict(kind='sgd'|'adam', lr_object, lr_probe, lr_pos, beta1, beta2, eps,
+    reg (cost regularizer weights, added to the loss and gradients),
+    con (constraints applied to the updated state)).
     Gradients of positions outside the group are zero; the update is applied
     to every element, as a dense optimiser on the whole variable does.
     Returns (new_state, loss).
@@ -339,11 +351,18 @@ def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
     for b, j in enumerate(batch_idx):
         g_pos[j] += r["g_pos"][b]
     grads = dict(object=r["g_object"], probe=r["g_probe"], positions=g_pos)
+    if opt.get("reg"):
+        cost, gO, gP = regularization(state["object"], state["probe"], opt["reg"])
+        r["loss"] += cost
+        grads["object"] = grads["object"] + gO
+        grads["probe"] = grads["probe"] + gP
     lrs = dict(object=opt["lr_object"], probe=opt["lr_probe"], positions=opt["lr_pos"])
     new = dict(state)
     if opt["kind"] == "sgd":
         for k in grads:
             new[k] = sgd_update(np.asarray(state[k]), grads[k], lrs[k])
+        if opt.get("con"):
+            new["object"], new["probe"] = apply_constraints(new["object"], new["probe"], opt["con"])
         return new, r["loss"]
     t = state.get("t", 0) + 1
     for k in grads:
@@ -356,4 +375,122 @@ def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
             np.asarray(state[k]), grads[k], m, v, t, lrs[k],
             opt.get("beta1", 0.9), opt.get("beta2", 0.999), opt.get("eps", 1e-8))
     new["t"] = t
+    if opt.get("con"):
+        new["object"], new["probe"] = apply_constraints(new["object"], new["probe"], opt["con"])
     return new, r["loss"]
+
+
+# --------------------------------------------------------------------------
+# Regularization (Sec. 3.4)
+# --------------------------------------------------------------------------
+#
+# Readings (the section names the regularizers without formulas):
+# cost regularizers are added to the detector loss of every group step with
+# weights lambda; "vacuum" is O = 1; finite differences are forward
+# differences inside the array (no wrap); TV uses the smoothed magnitude
+# phi(z) = sqrt(|z|^2 + delta^2) so that it is differentiable at 0.
+#   obj_l2:       sum |O - 1|^2                 probe_l2: sum |P|^2
+#   obj_l1:       sum |O - 1|  (gradient 0 where O = 1)
+#   obj_tikhonov: sum over slices of |D_y O|^2 + |D_x O|^2 (in-plane)
+#   obj_tv:       sum over slices of phi(D_y O) + phi(D_x O)
+#   layers_tikhonov: sum |O_{i+1} - O_i|^2      layers_tv: sum phi(O_{i+1} - O_i)
+# Constraint regularizers are applied to the state after each group step:
+#   amplitude range: O <- O * clip(|O|, a_min, a_max) / |O|
+#   probe support:   P <- F^-1(mask * F(P)) with a reciprocal-space mask
+#   layer blur:      O_i <- sum_j g(i - j) O_j / sum_j g(i - j), g Gaussian in
+#                    depth (sigma in slices), truncated at 3 sigma, real space
+#                    (no periodic wrap between the top and bottom slices).
+
+REG_KEYS = ("obj_l2", "probe_l2", "obj_l1", "obj_tikhonov", "obj_tv", "layers_tikhonov", "layers_tv")
+
+
+def _phi(z, delta):
+    return np.sqrt(np.abs(z) ** 2 + delta ** 2)
+
+
+def regularization(obj, probe, reg):
+    """Cost of the enabled cost regularizers and its gradients (dR/dRe + i dR/dIm).
+
+    reg: dict of weights (keys REG_KEYS, missing = 0) and `tv_delta`.
+    Returns (cost, g_object, g_probe).
+    """
+    O = np.asarray(obj, dtype=np.complex128)
+    P = np.asarray(probe, dtype=np.complex128)
+    d = reg.get("tv_delta", 1e-3)
+    cost = 0.0
+    gO = np.zeros_like(O)
+    gP = np.zeros_like(P)
+    w = reg.get("obj_l2", 0.0)
+    if w:
+        cost += w * np.sum(np.abs(O - 1) ** 2)
+        gO += w * 2 * (O - 1)
+    w = reg.get("probe_l2", 0.0)
+    if w:
+        cost += w * np.sum(np.abs(P) ** 2)
+        gP += w * 2 * P
+    w = reg.get("obj_l1", 0.0)
+    if w:
+        a = np.abs(O - 1)
+        cost += w * np.sum(a)
+        gO += w * np.where(a > 0, (O - 1) / np.where(a > 0, a, 1), 0)
+    for key, axis in (("obj_tikhonov", None), ("layers_tikhonov", 0)):
+        w = reg.get(key, 0.0)
+        if not w:
+            continue
+        for ax in ((1, 2) if axis is None else (0,)):
+            D = np.diff(O, axis=ax)                       # O[k+1] - O[k]
+            cost += w * np.sum(np.abs(D) ** 2)
+            g = np.zeros_like(O)
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[ax] = slice(0, -1)
+            hi[ax] = slice(1, None)
+            g[tuple(hi)] += 2 * D
+            g[tuple(lo)] -= 2 * D
+            gO += w * g
+    for key, axis in (("obj_tv", None), ("layers_tv", 0)):
+        w = reg.get(key, 0.0)
+        if not w:
+            continue
+        for ax in ((1, 2) if axis is None else (0,)):
+            D = np.diff(O, axis=ax)
+            cost += w * np.sum(_phi(D, d))
+            gd = D / _phi(D, d)
+            g = np.zeros_like(O)
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[ax] = slice(0, -1)
+            hi[ax] = slice(1, None)
+            g[tuple(hi)] += gd
+            g[tuple(lo)] -= gd
+            gO += w * g
+    return float(cost), gO, gP
+
+
+def apply_constraints(obj, probe, con):
+    """Constraint regularizers after a step (Sec. 3.4). con keys: amp_min,
+    amp_max (object amplitude range), probe_support (reciprocal-space mask
+    [N][N], FFT order), layer_sigma (Gaussian depth blur, slices)."""
+    O = np.array(obj, dtype=np.complex128)
+    P = np.array(probe, dtype=np.complex128)
+    if "amp_min" in con or "amp_max" in con:
+        a = np.abs(O)
+        c = np.clip(a, con.get("amp_min", 0.0), con.get("amp_max", np.inf))
+        O = np.where(a > 0, O * (c / np.where(a > 0, a, 1)), c)
+    if con.get("probe_support") is not None:
+        P = ifft2u(fft2u(P) * (np.asarray(con["probe_support"]) != 0))
+    s = con.get("layer_sigma", 0.0)
+    if s and O.shape[0] > 1:
+        S = O.shape[0]
+        r = int(np.ceil(3 * s))
+        out = np.zeros_like(O)
+        for i in range(S):
+            num = 0
+            den = 0.0
+            for j in range(max(0, i - r), min(S, i + r + 1)):
+                g = np.exp(-0.5 * ((i - j) / s) ** 2)
+                num = num + g * O[j]
+                den += g
+            out[i] = num / den
+        O = out
+    return O, P

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "PTY_OK", 1: "PTY_EINVAL", 2: "PTY_EBOUNDS", 3: "PTY_EUNSUPPO
                 5: "PTY_EHIP", 6: "PTY_ENONFINITE", 7: "PTY_ESTATE"}
 LOSS_IDS = {"amplitude": 0, "anscombe": 1, "poisson": 2, "gaussian": 3}
 OPT_SGD, OPT_ADAM = 0, 1
+STRATEGIES = {"auto": 0, "two_pass": 1, "resident": 2}
 PTY_ACCUMULATE = 1
 PTY_POS_DENSE = 2
 
@@ -26,6 +27,7 @@ EXPORTS = (
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
+    "pty_set_regularizers", "pty_set_strategy",
 )
 
 
@@ -35,12 +37,21 @@ class Geometry(C.Structure):
         ("obj_h", C.c_int32), ("obj_w", C.c_int32), ("n_positions", C.c_int32),
         ("dx", C.c_double), ("wavelength", C.c_double), ("dz", C.POINTER(C.c_double)),
         ("bandlimit", C.c_double), ("loss", C.c_int32), ("eps", C.c_double), ("sigma", C.c_double),
+        ("tilt_y", C.c_double), ("tilt_x", C.c_double), ("bandlimit_mask", C.POINTER(C.c_uint8)),
     ]
 
 
 class Options(C.Structure):
     _fields_ = [("max_batch", C.c_int32), ("checkpoint_every", C.c_int32), ("hbm_budget", C.c_size_t),
                 ("checkpoint_half", C.c_int32)]
+
+
+class Regularizers(C.Structure):
+    _fields_ = [("obj_l2", C.c_double), ("probe_l2", C.c_double), ("obj_l1", C.c_double),
+                ("obj_tikhonov", C.c_double), ("obj_tv", C.c_double), ("layers_tikhonov", C.c_double),
+                ("layers_tv", C.c_double), ("tv_delta", C.c_double), ("amp_clamp", C.c_int32),
+                ("amp_min", C.c_double), ("amp_max", C.c_double), ("probe_support", C.POINTER(C.c_uint8)),
+                ("layer_sigma", C.c_double)]
 
 
 class State(C.Structure):
@@ -101,6 +112,8 @@ def load():
         "pty_group_last_error": ([vp], C.c_char_p),
         "pty_group_destroy": ([vp], None),
         "pty_profile_enable": ([i32], None),
+        "pty_set_regularizers": ([vp, C.POINTER(Regularizers)], i32),
+        "pty_set_strategy": ([vp, i32], i32),
         "pty_profile_collect": ([C.c_char_p, sz, C.POINTER(f64), C.POINTER(i64), i32], i32),
     }
     for name, (args, res) in sig.items():

@@ -10,6 +10,7 @@ import ctypes as C
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -82,14 +83,22 @@ class ReconState:
                                                           self.v_pos) if t is not None)
 
 
-def _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma):
+def _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma, tilt=(0.0, 0.0),
+              bandlimit_mask=None):
     dz = list(dz) if dz is not None else []
     if len(dz) != max(S - 1, 0):
         raise ValueError(f"need {S - 1} slice gaps, got {len(dz)}")
     arr = (C.c_double * max(len(dz), 1))(*dz) if dz else None
+    mask = None
+    if bandlimit_mask is not None:
+        m = np.ascontiguousarray(np.asarray(bandlimit_mask) != 0, dtype=np.uint8)
+        if m.shape != (N, N):
+            raise ValueError(f"bandlimit_mask must be {N}x{N}")
+        mask = (C.c_uint8 * (N * N)).from_buffer_copy(m.tobytes())
     g = _lib.Geometry(N, M, S, H, W, J, dx, wavelength, C.cast(arr, C.POINTER(C.c_double)) if arr else None,
-                      bandlimit, _lib.LOSS_IDS[loss], eps, sigma)
-    return g, arr
+                      bandlimit, _lib.LOSS_IDS[loss], eps, sigma, float(tilt[0]), float(tilt[1]),
+                      C.cast(mask, C.POINTER(C.c_uint8)) if mask is not None else None)
+    return g, (arr, mask)
 
 
 def workspace_bytes(N, M, S, H, W, J, max_batch, checkpoint_every=1, dx=0.2, wavelength=0.019688,
@@ -111,12 +120,14 @@ class Problem:
     def __init__(self, N: int, M: int, S: int, H: int, W: int, J: int, dz: Sequence[float] = (),
                  dx: float = 0.2, wavelength: float = 0.019688, bandlimit: float = 2 / 3,
                  loss: str = "poisson", eps: float = 0.0, sigma: float = 1.0, max_batch: int = 256,
-                 checkpoint_every: int = 1, hbm_budget: int = 0, checkpoint_half: bool = False):
+                 checkpoint_every: int = 1, hbm_budget: int = 0, checkpoint_half: bool = False,
+                 tilt=(0.0, 0.0), bandlimit_mask=None):
         self.lib = _lib.load()
         self.N, self.M, self.S, self.H, self.W, self.J = N, M, S, H, W, J
         self.loss_kind = loss
         self.max_batch = max_batch
-        g, self._dz_keep = _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma)
+        g, self._dz_keep = _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma, tilt,
+                                     bandlimit_mask)
         self._g = g
         ctx = C.c_void_p()
         opt = _lib.Options(max_batch, checkpoint_every, hbm_budget, 1 if checkpoint_half else 0)
@@ -138,6 +149,30 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def set_regularizers(self, obj_l2=0.0, probe_l2=0.0, obj_l1=0.0, obj_tikhonov=0.0, obj_tv=0.0,
+                         layers_tikhonov=0.0, layers_tv=0.0, tv_delta=1e-3, amp_range=None, probe_support=None,
+                         layer_sigma=0.0):
+        """Cost and constraint regularizers applied by reconstruct_step (see include/pty.h)."""
+        mask = None
+        if probe_support is not None:
+            m = np.ascontiguousarray(np.asarray(probe_support) != 0, dtype=np.uint8)
+            if m.shape != (self.N, self.N):
+                raise ValueError(f"probe_support must be {self.N}x{self.N}")
+            mask = (C.c_uint8 * (self.N * self.N)).from_buffer_copy(m.tobytes())
+        lo, hi = amp_range if amp_range is not None else (0.0, 0.0)
+        r = _lib.Regularizers(obj_l2, probe_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta,
+                              1 if amp_range is not None else 0, lo, hi,
+                              C.cast(mask, C.POINTER(C.c_uint8)) if mask is not None else None, layer_sigma)
+        st = self.lib.pty_set_regularizers(self.ctx, C.byref(r))
+        if st:
+            self._err(st, "pty_set_regularizers")
+
+    def set_strategy(self, strategy: str):
+        """'auto', 'two_pass' or 'resident' (LDS-resident chains, N = 64 and 128)."""
+        st = self.lib.pty_set_strategy(self.ctx, _lib.STRATEGIES[strategy])
+        if st:
+            self._err(st, "pty_set_strategy")
 
     def set_chunk(self, positions: int):
         """Positions per launch in loss_and_grad / reconstruct_step (0: the whole group)."""

@@ -52,21 +52,25 @@ std::vector<float2> roots(int N) {
 }
 
 // Propagator for one gap, divided by N^2 (the normalisation of the unnormalised
-// forward and inverse 2D DFTs around it): H(u) = B(u) exp(-i pi lambda dz |q|^2),
-// q = f(u) / dx, B the circular band limit on signed integer bins.
-std::vector<float2> propagator(int N, double dx, double lam, double dz, double frac) {
+// forward and inverse 2D DFTs around it):
+// H(u) = B(u) exp(-i pi lambda dz |q|^2 + 2 pi i dz (q_y tan t_y + q_x tan t_x)),
+// q = f(u) / dx, B the circular band limit on signed integer bins or the mask.
+std::vector<float2> propagator(int N, double dx, double lam, double dz, double frac, double tilt_y,
+                               double tilt_x, const std::vector<uint8_t>& mask) {
   std::vector<float2> H((size_t)N * N);
   const double r = frac * N / 2.0;
   const double r2 = r * r * (1.0 + 1e-9);
   const double inv_n2 = 1.0 / ((double)N * (double)N);
+  const double ty = std::tan(tilt_y), tx = std::tan(tilt_x);
   for (int y = 0; y < N; ++y) {
     const int ky = y < (N + 1) / 2 ? y : y - N;
     const double qy = (double)ky / N / dx;
     for (int x = 0; x < N; ++x) {
       const int kx = x < (N + 1) / 2 ? x : x - N;
       const double qx = (double)kx / N / dx;
-      const bool keep = frac <= 0.0 || (double)(ky * ky + kx * kx) <= r2;
-      const double ph = -kPiD * lam * dz * (qy * qy + qx * qx);
+      const bool keep = mask.empty() ? (frac <= 0.0 || (double)(ky * ky + kx * kx) <= r2)
+                                     : mask[(size_t)y * N + x] != 0;
+      const double ph = -kPiD * lam * dz * (qy * qy + qx * qx) + 2.0 * kPiD * dz * (qy * ty + qx * tx);
       H[(size_t)y * N + x] = keep ? make_float2((float)(std::cos(ph) * inv_n2), (float)(std::sin(ph) * inv_n2))
                                   : make_float2(0.f, 0.f);
     }
@@ -120,6 +124,7 @@ pty_status validate_geometry(const pty_geometry* g, std::string& err) {
   if (g->n_slices > 1 && !g->dz) { err = "dz is NULL"; return PTY_EINVAL; }
   if (g->loss < PTY_LOSS_AMPLITUDE || g->loss > PTY_LOSS_GAUSSIAN) { err = "unknown loss kind"; return PTY_EINVAL; }
   if (!(g->dx > 0) || !(g->wavelength > 0)) { err = "dx and wavelength must be positive"; return PTY_EINVAL; }
+  if (!(std::fabs(g->tilt_y) < 1.5) || !(std::fabs(g->tilt_x) < 1.5)) { err = "tilt must be finite and below pi/2"; return PTY_EINVAL; }
   if (g->loss == PTY_LOSS_GAUSSIAN && !(g->sigma > 0)) { err = "sigma must be positive"; return PTY_EINVAL; }
   if ((size_t)g->n_slices * g->obj_h * g->obj_w > ((size_t)1 << 40)) { err = "object too large"; return PTY_EUNSUPPORTED; }
   return PTY_OK;
@@ -132,11 +137,13 @@ pty_status validate_geometry(const pty_geometry* g, std::string& err) {
 // returns total milliseconds and launch counts per class.
 enum ProfClass {
   P_ITEMS, P_COL_SHIFT, P_ROW_FWD, P_COL_PROP, P_FAR_LOSS, P_LOSS_REDUCE, P_ROW_ADJ, P_COL_PROP_ADJ,
-  P_COL_FINAL, P_PROBE_GRAD, P_POS_REDUCE, P_PLAIN2D, P_FILL, P_OPTIM, P_RECOMPUTE, P_NCLASS
+  P_COL_FINAL, P_PROBE_GRAD, P_POS_REDUCE, P_PLAIN2D, P_FILL, P_OPTIM, P_RECOMPUTE, P_REG, P_RES_FWD, P_RES_ADJ,
+  P_NCLASS
 };
 const char* kProfNames[P_NCLASS] = {"items", "col_shift", "row_fwd", "col_prop", "far_loss", "loss_reduce",
                                     "row_adj", "col_prop_adj", "col_final", "probe_grad", "pos_reduce",
-                                    "plain2d", "fill", "optimizer", "recompute"};
+                                    "plain2d", "fill", "optimizer", "recompute", "regularizers", "res_fwd",
+                                    "res_adj"};
 
 struct ProfRec { int cls; hipEvent_t a, b; };
 
@@ -180,6 +187,7 @@ struct pty_ctx {
   std::vector<double> dz;
   int max_batch = 0, ck_every = 1, n_ck = 1;
   int chunk = 0;              // positions per launch in fused loss-and-gradient calls (0: all)
+  int strategy = PTY_STRATEGY_AUTO;
   Sizes sz;
   float2 *tw = nullptr, *prop = nullptr, *phat = nullptr, *gphat = nullptr, *gprobe = nullptr, *gobj = nullptr;
   float* gpos = nullptr;
@@ -190,6 +198,16 @@ struct pty_ctx {
   Item* items = nullptr;
   float2* ramps = nullptr;
   float *loss_part = nullptr, *pos_part = nullptr;
+  // regularization
+  bool reg_on = false, con_on = false;
+  RegDev rg{};
+  float probe_l2 = 0.f;
+  int amp_clamp = 0;
+  float amp_min = 0.f, amp_max = 0.f;
+  uint8_t* support = nullptr;      // device [N][N] or null
+  float* blur = nullptr;           // device Gaussian weights [r + 1]
+  int blur_r = 0;
+  float* reg_part = nullptr;       // cost partial sums
   // tape of pty_forward_save
   bool tape_valid = false;
   LaunchCtx tape{};
@@ -216,6 +234,12 @@ namespace {
       return PTY_EHIP;                                                     \
     }                                                                      \
   } while (0)
+
+// LDS-resident chains: N <= 128 and every slice checkpointed.
+bool use_resident(int strategy, int N, int ck_every) {
+  if (!resident_supported(N) || ck_every != 1) return false;
+  return strategy != PTY_STRATEGY_TWO_PASS;
+}
 
 ReqDev base_req(pty_ctx* c) {
   ReqDev r{};
@@ -253,6 +277,7 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
   L.loss_part = c->loss_part;
   L.pos_part = c->pos_part;
   L.flags = c->flags;
+  L.resident = use_resident(c->strategy, c->g.N, c->ck_every) ? 1 : 0;
   return L;
 }
 
@@ -282,6 +307,14 @@ void run_prepare(const LaunchCtx& L, int N) {
 // entry-wave checkpoints and leave the detector-plane gradient seed (after
 // its inverse column DFT) in the workspace.
 void run_forward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<int>& far_steps, bool save) {
+  if (L.resident) {
+    { ProfScope p(P_RES_FWD, L.stream); launch_res_fwd(L, N, save); }
+    for (int i : far_steps) {
+      ProfScope p(P_FAR_LOSS, L.stream);
+      launch_far_loss(L, N, i, save);
+    }
+    return;
+  }
   { ProfScope p(P_COL_SHIFT, L.stream); launch_col(L, N, COL_SHIFT, 0); }
   PsiStore st{};
   st.mode = save ? 1 : 0;
@@ -305,6 +338,14 @@ void run_finish_forward(const LaunchCtx& L, int N) {
 // recomputed per segment); grouped launches store every slice.
 void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<int>& final_steps, float scale,
                         int k, float2* ws2, void* seg) {
+  if (L.resident) {
+    { ProfScope p(P_RES_ADJ, L.stream); launch_res_adj(L, N, scale); }
+    for (int t : final_steps) {
+      ProfScope p(P_COL_FINAL, L.stream);
+      launch_col(L, N, COL_FINAL, t);
+    }
+    return;
+  }
   int seg_lo = -1, seg_hi = -1;   // slices currently held in the segment buffer
   for (int t = 0; t < S_max; ++t) {
     const int i = S_max - 1 - t;   // single-request slice index (k > 1 only)
@@ -445,8 +486,11 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   }
   std::vector<float2> tw = roots(N);
   if (hipMemcpy(c->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return fail(PTY_EHIP);
+  std::vector<uint8_t> mask;
+  if (g->bandlimit_mask) mask.assign(g->bandlimit_mask, g->bandlimit_mask + N2);
+  c->g.bandlimit_mask = nullptr;   // copied above; the caller's array is not kept
   for (int i = 0; i < S - 1; ++i) {
-    std::vector<float2> H = propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit);
+    std::vector<float2> H = propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y, g->tilt_x, mask);
     if (hipMemcpy(c->prop + (size_t)i * N2, H.data(), N2 * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       return fail(PTY_EHIP);
   }
@@ -481,6 +525,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->tw); dfree(c->prop); dfree(c->phat); dfree(c->gphat); dfree(c->gprobe); dfree(c->gobj);
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
+  dfree(c->support); dfree(c->blur); dfree(c->reg_part);
   delete c;
 }
 
@@ -668,6 +713,87 @@ void apply_optimizer(pty_ctx* c, hipStream_t s, pty_state* st, const pty_optim* 
 
 }  // namespace
 
+namespace {
+
+// Cost regularizers: gradients into the dense gradients, cost added to *loss.
+void apply_cost_regularizers(pty_ctx* c, hipStream_t s, const pty_state* st, double* loss) {
+  if (!c->reg_on) return;
+  const pty_geometry& g = c->g;
+  int nb = 0;
+  if (c->rg.obj_l2 != 0.f || c->rg.obj_l1 != 0.f || c->rg.obj_tikhonov != 0.f || c->rg.obj_tv != 0.f ||
+      c->rg.layers_tikhonov != 0.f || c->rg.layers_tv != 0.f)
+    nb = launch_reg_object(s, (const float2*)st->object, c->gobj, g.n_slices, g.obj_h, g.obj_w, c->rg, c->reg_part);
+  int np = 0;
+  if (c->probe_l2 != 0.f)
+    np = launch_reg_probe(s, (const float2*)st->probe, c->gprobe, (size_t)g.n_modes * g.N * g.N, c->probe_l2,
+                          c->reg_part + 4096);
+  if (loss) {
+    if (nb) launch_add_cost(s, c->reg_part, nb, loss);
+    if (np) launch_add_cost(s, c->reg_part + 4096, np, loss);
+  }
+}
+
+// Constraint regularizers on the updated state.
+void apply_constraints(pty_ctx* c, hipStream_t s, pty_state* st) {
+  if (!c->con_on) return;
+  const pty_geometry& g = c->g;
+  const size_t HW = (size_t)g.obj_h * g.obj_w;
+  if (c->amp_clamp) launch_amp_clamp(s, (float2*)st->object, HW * g.n_slices, c->amp_min, c->amp_max);
+  if (c->blur) launch_layer_blur(s, (float2*)st->object, g.n_slices, HW, c->blur, c->blur_r);
+  if (c->support) {
+    const int N = g.N, M = g.n_modes;
+    launch_plain2d(N, s, c->tw, (const float2*)st->probe, c->gphat, M, false, 1.f / N, false);
+    launch_mask_tiles(s, c->gphat, c->support, (size_t)M * N * N, N * N);
+    launch_plain2d(N, s, c->tw, c->gphat, (float2*)st->probe, M, true, 1.f / N, false);
+  }
+}
+
+}  // namespace
+
+extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r) {
+  if (!c) return PTY_EINVAL;
+  dfree(c->support);
+  dfree(c->blur);
+  c->reg_on = c->con_on = false;
+  c->amp_clamp = 0;
+  c->blur_r = 0;
+  if (!r) return PTY_OK;
+  const double w[7] = {r->obj_l2, r->probe_l2, r->obj_l1, r->obj_tikhonov, r->obj_tv, r->layers_tikhonov, r->layers_tv};
+  for (double x : w)
+    if (!(x >= 0.0) || !std::isfinite(x)) { c->err = "regularizer weights must be finite and >= 0"; return PTY_EINVAL; }
+  if ((r->obj_tv > 0 || r->layers_tv > 0) && !(r->tv_delta > 0)) { c->err = "tv_delta must be > 0"; return PTY_EINVAL; }
+  if (r->amp_clamp && !(r->amp_min >= 0 && r->amp_max >= r->amp_min)) { c->err = "need 0 <= amp_min <= amp_max"; return PTY_EINVAL; }
+  if (r->layer_sigma < 0 || (r->layer_sigma > 0 && c->g.n_slices > kMaxBlurSlices)) {
+    c->err = "layer blur needs sigma >= 0 and at most 64 slices";
+    return PTY_EINVAL;
+  }
+  c->rg = RegDev{(float)r->obj_l2, (float)r->obj_l1, (float)r->obj_tikhonov, (float)r->obj_tv,
+                 (float)r->layers_tikhonov, (float)r->layers_tv, (float)r->tv_delta};
+  c->probe_l2 = (float)r->probe_l2;
+  for (double x : w) c->reg_on = c->reg_on || x > 0;
+  pty_status st;
+  if (!c->reg_part && (st = dmalloc(&c->reg_part, 8192, c->err))) return st;
+  c->amp_clamp = r->amp_clamp ? 1 : 0;
+  c->amp_min = (float)r->amp_min;
+  c->amp_max = (float)r->amp_max;
+  const size_t N2 = (size_t)c->g.N * c->g.N;
+  if (r->probe_support) {
+    if ((st = dmalloc(&c->support, N2, c->err))) return st;
+    std::vector<uint8_t> m(r->probe_support, r->probe_support + N2);
+    for (auto& v : m) v = v ? 1 : 0;
+    if (hipMemcpy(c->support, m.data(), N2, hipMemcpyHostToDevice) != hipSuccess) return PTY_EHIP;
+  }
+  if (r->layer_sigma > 0 && c->g.n_slices > 1) {
+    c->blur_r = (int)std::ceil(3.0 * r->layer_sigma);
+    std::vector<float> gw(c->blur_r + 1);
+    for (int k = 0; k <= c->blur_r; ++k) gw[k] = (float)std::exp(-0.5 * (k / r->layer_sigma) * (k / r->layer_sigma));
+    if ((st = dmalloc(&c->blur, gw.size(), c->err))) return st;
+    if (hipMemcpy(c->blur, gw.data(), gw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return PTY_EHIP;
+  }
+  c->con_on = c->amp_clamp || c->support || c->blur;
+  return PTY_OK;
+}
+
 extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* st, const float* patterns,
                                            const int32_t* batch_idx, int32_t B, const pty_optim* o, double* loss) {
   if (!c) return PTY_EINVAL;
@@ -698,7 +824,9 @@ extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* 
   }
   run_fused(c, L, 1.f);
   { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, g.n_modes, true, 1.f / N, false); }
+  { ProfScope p(P_REG, s); apply_cost_regularizers(c, s, st, loss); }
   apply_optimizer(c, s, st, o);
+  { ProfScope p(P_REG, s); apply_constraints(c, s, st); }
   HIPCHECK(c, hipGetLastError());
   return PTY_OK;
 }
@@ -784,6 +912,7 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   L.ws = G->ws;
   L.ck = G->ck;
   L.ck_half = 0;
+  L.resident = use_resident(items[0].ctx ? items[0].ctx->strategy : PTY_STRATEGY_AUTO, N, 1) ? 1 : 0;
   L.ramps = G->ramps;
   L.tw = G->tw;
   L.loss_part = G->loss_part;
@@ -846,7 +975,9 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   for (int q = 0; q < n; ++q) {
     pty_ctx* c = items[q].ctx;
     launch_plain2d(N, s, G->tw, c->gphat, c->gprobe, c->g.n_modes, true, 1.f / N, false);
+    apply_cost_regularizers(c, s, items[q].state, items[q].loss);
     apply_optimizer(c, s, items[q].state, items[q].opt);
+    apply_constraints(c, s, items[q].state);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { G->err = hipGetErrorString(e); return PTY_EHIP; }
@@ -900,5 +1031,15 @@ extern "C" int32_t pty_profile_collect(char* names, size_t names_len, double* to
 extern "C" pty_status pty_set_chunk(pty_ctx* c, int32_t positions) {
   if (!c || positions < 0) return PTY_EINVAL;
   c->chunk = positions;
+  return PTY_OK;
+}
+
+extern "C" pty_status pty_set_strategy(pty_ctx* c, int32_t strategy) {
+  if (!c || strategy < PTY_STRATEGY_AUTO || strategy > PTY_STRATEGY_RESIDENT) return PTY_EINVAL;
+  if (strategy == PTY_STRATEGY_RESIDENT && !resident_supported(c->g.N)) {
+    c->err = "the LDS-resident chain needs N = 64 or 128";
+    return PTY_EUNSUPPORTED;
+  }
+  c->strategy = strategy;
   return PTY_OK;
 }

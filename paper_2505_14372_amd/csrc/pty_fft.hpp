@@ -256,6 +256,48 @@ __device__ __forceinline__ void line_fft(float2 (&v)[Cfg<N>::E], int l, const fl
   (void)L;
 }
 
+// ---------------------------------------------------------------- LDS-resident tiles
+// Row pitch (float2) of an LDS-resident N x N tile and the workgroup size of
+// the resident chains; the pitch leaves room for the padded row exchange.
+template <int N> struct Res;
+template <> struct Res<64>  { static constexpr int P = 93,  THREADS = 512; };
+template <> struct Res<128> { static constexpr int P = 146, THREADS = 1024; };
+
+// Line transform with the line's slot s stored at base[s * STRIDE] (XP: slot
+// pitch of the exchange, L + 1 for rows, L for columns). Stages as in
+// line_fft_stage1/2, with the exchange written into the line's own storage.
+template <int N, bool INV, int XP, int STRIDE>
+__host__ __device__ __forceinline__ void res_stage1(float2 (&v)[Cfg<N>::E], int l, const float2* tw, float2* base) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
+  static_assert((E - 1) * XP + L <= (XP == L ? N : N + E), "exchange exceeds the line storage");
+  Dft<E, INV>::run(v);
+#pragma unroll
+  for (int k1 = 1; k1 < E; ++k1) {
+    float2 w = tw[l * k1];
+    if (INV) w.y = -w.y;
+    v[k1] = cmul(v[k1], w);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < E; ++k1) base[(k1 * XP + l) * STRIDE] = v[k1];
+}
+
+template <int N, bool INV, int XP, int STRIDE>
+__host__ __device__ __forceinline__ void res_stage2(float2 (&v)[Cfg<N>::E], int l, const float2* base) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E, C = E / L;
+  float2 u[E];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int ll = 0; ll < L; ++ll) u[c * L + ll] = base[((l + L * c) * XP + ll) * STRIDE];
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    Dft<L, INV>::run(&u[c * L]);
+#pragma unroll
+    for (int k2 = 0; k2 < L; ++k2) v[c + C * k2] = u[c * L + k2];
+  }
+}
+
 // Ordering of LDS accesses among the lanes of one wavefront.
 struct WaveSync {
   __device__ __forceinline__ void operator()() const {

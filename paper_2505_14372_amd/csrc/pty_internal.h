@@ -77,6 +77,7 @@ struct LaunchCtx {
   ReqTable reqs;
   int n_reqs, n_items, max_modes;
   int item_off;             // first item of this launch (chunked schedules)
+  int resident;             // use the LDS-resident chain kernels
   Item* items;
   float2* ws;               // tile workspace
   void* ck;                 // checkpoint buffer (float2, or __half2 when ck_half)
@@ -105,5 +106,24 @@ void launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, s
 int col_blocks(int N);
 
 enum ColOp { COL_SHIFT = 0, COL_PROP = 1, COL_PROP_ADJ = 2, COL_FINAL = 3 };
+
+// Cost-regularizer weights on the device side (float).
+struct RegDev {
+  float obj_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta;
+};
+constexpr int kMaxBlurSlices = 64;
+
+int launch_reg_object(hipStream_t s, const float2* O, float2* g, int S, int H, int W, const RegDev& rg,
+                      float* cost_part);
+int launch_reg_probe(hipStream_t s, const float2* P, float2* g, size_t n, float w, float* cost_part);
+void launch_add_cost(hipStream_t s, const float* part, int n, double* loss);
+void launch_amp_clamp(hipStream_t s, float2* O, size_t n, float lo, float hi);
+void launch_layer_blur(hipStream_t s, float2* O, int S, size_t HW, const float* g, int r);
+void launch_mask_tiles(hipStream_t s, float2* t, const uint8_t* mask, size_t n, int N2);
+
+// LDS-resident forward / adjoint chains (N = 64, 128; every slice checkpointed)
+bool resident_supported(int N);
+void launch_res_fwd(const LaunchCtx& L, int N, bool save);
+void launch_res_adj(const LaunchCtx& L, int N, float scale);
 
 }  // namespace pty

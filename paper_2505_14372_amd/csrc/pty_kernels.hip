@@ -48,6 +48,9 @@ __device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw_g
 #ifndef PTY_NT_CKPT
 #define PTY_NT_CKPT 0
 #endif
+#ifndef PTY_ROWADJ_RELOAD_O
+#define PTY_ROWADJ_RELOAD_O 0
+#endif
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // Entry-wave checkpoint storage: complex64 (float2) or two IEEE halves
@@ -192,8 +195,16 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 //   g = IDFT_x(tile row)                (gradient wrt phi_i, real space)
 //   grad O_i += sum_m conj(psi_i,m) g   (scatter-added into the object gradient)
 //   h = conj(O_i) g ; tile row = DFT_x(h)
+#ifndef PTY_ROWADJ_WAVES
+#define PTY_ROWADJ_WAVES 0
+#endif
+#if PTY_ROWADJ_WAVES
+#define PTY_ROWADJ_ATTR __attribute__((amdgpu_waves_per_eu(PTY_ROWADJ_WAVES, PTY_ROWADJ_WAVES)))
+#else
+#define PTY_ROWADJ_ATTR
+#endif
 template <int N, bool HALF>
-__global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ items,
+__global__ __launch_bounds__(kThreads) PTY_ROWADJ_ATTR void k_row_adj(const Item* __restrict__ items,
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, const void* __restrict__ ck_,
                                                       const float2* __restrict__ twg, int step,
@@ -212,11 +223,23 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   float2* sx = xch + line * Xch<N>::ROW_STRIDE;
   using CT = typename Ck<HALF>::T;
   const CT* ck = static_cast<const CT*>(ck_);
-  float2 o[E], acc[E];
+  float2 acc[E];
   const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
+#if !PTY_ROWADJ_RELOAD_O
+  float2 o[E];
 #pragma unroll
-  for (int a = 0; a < E; ++a) { o[a] = r.obj[orow + l + L * a]; acc[a] = make_float2(0.f, 0.f); }
+  for (int a = 0; a < E; ++a) o[a] = r.obj[orow + l + L * a];
+#endif
+#pragma unroll
+  for (int a = 0; a < E; ++a) acc[a] = make_float2(0.f, 0.f);
   for (int m = 0; m < r.M; ++m) {
+#if PTY_ROWADJ_RELOAD_O
+    // the object row is re-read for every mode (an L2 hit after the first)
+    // instead of being held in registers across the mode loop
+    float2 o[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) o[a] = r.obj[orow + l + L * a];
+#endif
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
 #pragma unroll
@@ -740,6 +763,397 @@ void launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, s
 }
 int col_blocks(int N) {
   return N == 256 ? ColPass<256>::NBLK : N == 192 ? ColPass<192>::NBLK : N == 128 ? ColPass<128>::NBLK : ColPass<64>::NBLK;
+}
+
+}  // namespace pty
+
+namespace pty {
+
+// ============================================================ regularization (Sec. 3.4)
+//
+// Cost regularizers on the object [S][H][W]: one thread per element adds the
+// gradient of every enabled term to g (dR/dRe + i dR/dIm) and accumulates
+// the cost of the forward differences it owns (to y+1, x+1, i+1), so that
+// each difference is counted once. phi(z) = sqrt(|z|^2 + delta^2).
+__device__ __forceinline__ float2 tv_grad(float2 z, float d2) {
+  return cscale(z, rsqrtf(cabs2(z) + d2));
+}
+
+__global__ void k_reg_object(const float2* __restrict__ O, float2* __restrict__ g, int S, int H, int W,
+                             RegDev rg, float* __restrict__ cost_part) {
+  __shared__ float red[kThreads / 64];
+  const size_t n = (size_t)S * H * W;
+  float cost = 0.f;
+  const float d2 = rg.tv_delta * rg.tv_delta;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(e % W);
+    const int y = (int)((e / W) % H);
+    const int i = (int)(e / ((size_t)W * H));
+    const float2 o = O[e];
+    float2 gr = make_float2(0.f, 0.f);
+    if (rg.obj_l2 != 0.f) {
+      float2 d = make_float2(o.x - 1.f, o.y);
+      gr = cadd(gr, cscale(d, 2.f * rg.obj_l2));
+      cost += rg.obj_l2 * cabs2(d);
+    }
+    if (rg.obj_l1 != 0.f) {
+      float2 d = make_float2(o.x - 1.f, o.y);
+      float a = sqrtf(cabs2(d));
+      if (a > 0.f) gr = cadd(gr, cscale(d, rg.obj_l1 / a));
+      cost += rg.obj_l1 * a;
+    }
+    const bool in_tik = rg.obj_tikhonov != 0.f, in_tv = rg.obj_tv != 0.f;
+    const bool z_tik = rg.layers_tikhonov != 0.f, z_tv = rg.layers_tv != 0.f;
+    // neighbours along each axis: (stride, has_prev, has_next, weight_tik, weight_tv)
+    const size_t strides[3] = {(size_t)W, (size_t)1, (size_t)W * H};
+    const bool prev[3] = {y > 0, x > 0, i > 0};
+    const bool next[3] = {y + 1 < H, x + 1 < W, i + 1 < S};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float wt = ax < 2 ? (in_tik ? rg.obj_tikhonov : 0.f) : (z_tik ? rg.layers_tikhonov : 0.f);
+      const float wv = ax < 2 ? (in_tv ? rg.obj_tv : 0.f) : (z_tv ? rg.layers_tv : 0.f);
+      if (wt == 0.f && wv == 0.f) continue;
+      if (prev[ax]) {           // difference D = o - O[prev] enters with +
+        float2 D = csub(o, O[e - strides[ax]]);
+        if (wt != 0.f) gr = cadd(gr, cscale(D, 2.f * wt));
+        if (wv != 0.f) gr = cadd(gr, cscale(tv_grad(D, d2), wv));
+      }
+      if (next[ax]) {           // difference D = O[next] - o enters with -
+        float2 D = csub(O[e + strides[ax]], o);
+        if (wt != 0.f) { gr = csub(gr, cscale(D, 2.f * wt)); cost += wt * cabs2(D); }
+        if (wv != 0.f) { gr = csub(gr, cscale(tv_grad(D, d2), wv)); cost += wv * sqrtf(cabs2(D) + d2); }
+      }
+    }
+    g[e] = cadd(g[e], gr);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cost;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+    cost_part[blockIdx.x] = t;
+  }
+}
+
+// Probe L2: g += 2 w P, cost w |P|^2.
+__global__ void k_reg_probe(const float2* __restrict__ P, float2* __restrict__ g, size_t n, float w,
+                            float* __restrict__ cost_part) {
+  __shared__ float red[kThreads / 64];
+  float cost = 0.f;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const float2 p = P[e];
+    g[e] = cadd(g[e], cscale(p, 2.f * w));
+    cost += w * cabs2(p);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cost;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int w2 = 0; w2 < kThreads / 64; ++w2) t += red[w2];
+    cost_part[blockIdx.x] = t;
+  }
+}
+
+// loss += sum of the cost partials (double), one block.
+__global__ void k_add_cost(const float* __restrict__ part, int n, double* __restrict__ loss) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) s += (double)part[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) *loss += red[0];
+}
+
+// Object amplitude range: O <- O * clip(|O|, lo, hi) / |O| (|O| = 0 -> lo).
+__global__ void k_amp_clamp(float2* __restrict__ O, size_t n, float lo, float hi) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    float2 o = O[e];
+    float a = sqrtf(cabs2(o));
+    float c = fminf(fmaxf(a, lo), hi);
+    O[e] = a > 0.f ? cscale(o, c / a) : make_float2(c, 0.f);
+  }
+}
+
+// Gaussian depth blur per pixel column, normalised, truncated at radius r.
+__global__ void k_layer_blur(float2* __restrict__ O, int S, size_t HW, const float* __restrict__ g, int r) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += (size_t)gridDim.x * blockDim.x) {
+    float2 col[kMaxBlurSlices];
+    for (int i = 0; i < S; ++i) col[i] = O[(size_t)i * HW + p];
+    for (int i = 0; i < S; ++i) {
+      float2 acc = make_float2(0.f, 0.f);
+      float den = 0.f;
+      const int j0 = i - r < 0 ? 0 : i - r, j1 = i + r + 1 > S ? S : i + r + 1;
+      for (int j = j0; j < j1; ++j) {
+        const float w = g[i - j < 0 ? j - i : i - j];
+        acc = cadd(acc, cscale(col[j], w));
+        den += w;
+      }
+      O[(size_t)i * HW + p] = cscale(acc, 1.f / den);
+    }
+  }
+}
+
+// t <- t * mask (elementwise over n_tiles tiles of N*N).
+__global__ void k_mask_tiles(float2* __restrict__ t, const uint8_t* __restrict__ mask, size_t n, int N2) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    if (!mask[e % N2]) t[e] = make_float2(0.f, 0.f);
+}
+
+static inline int reg_blocks(size_t n) {
+  size_t b = (n + kThreads - 1) / kThreads;
+  return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
+}
+
+int launch_reg_object(hipStream_t s, const float2* O, float2* g, int S, int H, int W, const RegDev& rg,
+                      float* cost_part) {
+  const int nb = reg_blocks((size_t)S * H * W);
+  hipLaunchKernelGGL(k_reg_object, dim3(nb), dim3(kThreads), 0, s, O, g, S, H, W, rg, cost_part);
+  return nb;
+}
+int launch_reg_probe(hipStream_t s, const float2* P, float2* g, size_t n, float w, float* cost_part) {
+  const int nb = reg_blocks(n);
+  hipLaunchKernelGGL(k_reg_probe, dim3(nb), dim3(kThreads), 0, s, P, g, n, w, cost_part);
+  return nb;
+}
+void launch_add_cost(hipStream_t s, const float* part, int n, double* loss) {
+  hipLaunchKernelGGL(k_add_cost, dim3(1), dim3(kThreads), 0, s, part, n, loss);
+}
+void launch_amp_clamp(hipStream_t s, float2* O, size_t n, float lo, float hi) {
+  hipLaunchKernelGGL(k_amp_clamp, dim3(reg_blocks(n)), dim3(kThreads), 0, s, O, n, lo, hi);
+}
+void launch_layer_blur(hipStream_t s, float2* O, int S, size_t HW, const float* g, int r) {
+  hipLaunchKernelGGL(k_layer_blur, dim3(reg_blocks(HW)), dim3(kThreads), 0, s, O, S, HW, g, r);
+}
+void launch_mask_tiles(hipStream_t s, float2* t, const uint8_t* mask, size_t n, int N2) {
+  hipLaunchKernelGGL(k_mask_tiles, dim3(reg_blocks(n)), dim3(kThreads), 0, s, t, mask, n, N2);
+}
+
+}  // namespace pty
+
+namespace pty {
+
+// ============================================================ LDS-resident chains (N <= 128)
+//
+// For N = 64 and 128 a whole tile (32 / 128 KiB of complex64) fits in LDS, so
+// one workgroup per (position, mode) runs every slice step of the forward (or
+// adjoint) model with the tile resident: rows and columns are transformed in
+// place, each line using its own storage as its exchange scratch (rows with a
+// padded exchange layout inside the padded row pitch, columns with the plain
+// one). Only the object rows, the propagator, the checkpoints and the
+// gradients are read from or written to memory. The pitch P was chosen so that
+// every exchange and line access of a wave hits any LDS bank at most 4 times.
+template <int N, bool INV, int XP, int STRIDE>
+__device__ __forceinline__ void res_line_fft(float2 (&v)[Cfg<N>::E], int l, const float2* tw, float2* base) {
+  WaveSync{}();           // earlier reads of this line's storage are done
+  res_stage1<N, INV, XP, STRIDE>(v, l, tw, base);
+  WaveSync{}();
+  res_stage2<N, INV, XP, STRIDE>(v, l, base);
+  WaveSync{}();           // exchange reads are done before the line is rewritten
+}
+
+template <int N>
+__device__ __forceinline__ void res_load_row(float2 (&v)[Cfg<N>::E], const float2* tile, int y, int l) {
+#pragma unroll
+  for (int a = 0; a < Cfg<N>::E; ++a) v[a] = tile[y * Res<N>::P + l + Cfg<N>::L * a];
+}
+template <int N>
+__device__ __forceinline__ void res_store_row(const float2 (&v)[Cfg<N>::E], float2* tile, int y, int l) {
+#pragma unroll
+  for (int a = 0; a < Cfg<N>::E; ++a) tile[y * Res<N>::P + l + Cfg<N>::L * a] = v[a];
+}
+
+// Column pass in LDS: tile column x <- IDFT_y(mult * DFT_y(column)), mult from a
+// global [N][N] table (conjugated if CONJ).
+template <int N, bool CONJ>
+__device__ __forceinline__ void res_col_prop(float2* tile, const float2* tw, const float2* __restrict__ Hm) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E, P = Res<N>::P, LINES = Res<N>::THREADS / L;
+  const int l = threadIdx.x % L;
+  for (int x = threadIdx.x / L; x < N; x += LINES) {
+    float2 v[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) v[a] = tile[(l + L * a) * P + x];
+    res_line_fft<N, false, L, P>(v, l, tw, tile + x);
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      const float2 h = Hm[(size_t)(l + L * a) * N + x];
+      v[a] = CONJ ? cjmul(h, v[a]) : cmul(v[a], h);
+    }
+    res_line_fft<N, true, L, P>(v, l, tw, tile + x);
+#pragma unroll
+    for (int a = 0; a < E; ++a) tile[(l + L * a) * P + x] = v[a];
+  }
+}
+
+// Forward chain of one (item, mode): shift, every slice, ending with the
+// forward row DFT of the last exit wave written to the global work tile
+// (the far-field kernel takes it from there). Entry waves are checkpointed.
+template <int N, bool HALF>
+__global__ __launch_bounds__(Res<N>::THREADS) void k_res_fwd(const Item* __restrict__ items, const ReqTable reqs,
+                                                             float2* __restrict__ ws, void* __restrict__ ck_,
+                                                             const float2* __restrict__ ramps,
+                                                             const float2* __restrict__ twg, int save, int item_off) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E, LINES = Res<N>::THREADS / L;
+  __shared__ float2 tile[N * Res<N>::P];
+  __shared__ float2 tw[N];
+  const int b = item_off + blockIdx.y, m = blockIdx.z;
+  const Item it = items[b];
+  const ReqDev& r = reqs.r[it.req];
+  if (!it.valid || m >= r.M) return;
+  using CT = typename Ck<HALF>::T;
+  CT* ck = static_cast<CT*>(ck_);
+  for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twg[k];
+  __syncthreads();
+  const int l = threadIdx.x % L;
+  const float inv = 1.f / (float)N;
+  // psi_0 = IDFT_2(phat R) / N : columns first (u_x fixed per column)
+  {
+    const float2* ry = ramps + (size_t)b * 2 * N;
+    const float2* ph = r.phat + (size_t)m * N * N;
+    for (int x = threadIdx.x / L; x < N; x += LINES) {
+      const float2 rx = ramps[(size_t)b * 2 * N + N + x];
+      float2 v[E];
+#pragma unroll
+      for (int a = 0; a < E; ++a) {
+        const int uy = l + L * a;
+        v[a] = cscale(cmul(cmul(ph[(size_t)uy * N + x], ry[uy]), rx), inv);
+      }
+      res_line_fft<N, true, L, Res<N>::P>(v, l, tw, tile + x);
+#pragma unroll
+      for (int a = 0; a < E; ++a) tile[(l + L * a) * Res<N>::P + x] = v[a];
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < r.S; ++i) {
+    for (int y = threadIdx.x / L; y < N; y += LINES) {
+      float2 v[E];
+      res_load_row<N>(v, tile, y, l);
+      res_line_fft<N, true, L + 1, 1>(v, l, tw, tile + y * Res<N>::P);       // entry wave psi_i
+      if (save && (i % r.ck_every) == 0) {
+        CT* dst = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i / r.ck_every) * N + y) * N;
+#pragma unroll
+        for (int a = 0; a < E; ++a) Ck<HALF>::store(dst + l + L * a, v[a]);
+      }
+      const float2* orow = r.obj + ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
+#pragma unroll
+      for (int a = 0; a < E; ++a) v[a] = cmul(v[a], orow[l + L * a]);
+      res_line_fft<N, false, L + 1, 1>(v, l, tw, tile + y * Res<N>::P);
+      if (i == r.S - 1) {
+        float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
+#pragma unroll
+        for (int a = 0; a < E; ++a) trow[l + L * a] = v[a];
+      } else {
+        res_store_row<N>(v, tile, y, l);
+      }
+    }
+    __syncthreads();
+    if (i < r.S - 1) {
+      res_col_prop<N, false>(tile, tw, r.prop + (size_t)i * N * N);
+      __syncthreads();
+    }
+  }
+}
+
+// Adjoint chain of one (item, mode): from the detector seed in the global work
+// tile (after its inverse column DFT) back through every slice; the object
+// gradient of this mode is scatter-added per slice; the forward row DFT of the
+// gradient with respect to psi_0 is written back to the work tile for the
+// final column pass.
+template <int N, bool HALF>
+__global__ __launch_bounds__(Res<N>::THREADS) void k_res_adj(const Item* __restrict__ items, const ReqTable reqs,
+                                                             float2* __restrict__ ws, const void* __restrict__ ck_,
+                                                             const float2* __restrict__ twg, float scale,
+                                                             int item_off) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E, LINES = Res<N>::THREADS / L;
+  __shared__ float2 tile[N * Res<N>::P];
+  __shared__ float2 tw[N];
+  const int b = item_off + blockIdx.y, m = blockIdx.z;
+  const Item it = items[b];
+  const ReqDev& r = reqs.r[it.req];
+  if (!it.valid || m >= r.M) return;
+  using CT = typename Ck<HALF>::T;
+  const CT* ck = static_cast<const CT*>(ck_);
+  for (int k = threadIdx.x; k < N; k += blockDim.x) tw[k] = twg[k];
+  __syncthreads();
+  const int l = threadIdx.x % L;
+  float2* wtile = ws + (size_t)(it.tile0 + m) * N * N;
+  for (int i = r.S - 1; i >= 0; --i) {
+    for (int y = threadIdx.x / L; y < N; y += LINES) {
+      float2 v[E];
+      if (i == r.S - 1) {
+#pragma unroll
+        for (int a = 0; a < E; ++a) v[a] = wtile[(size_t)y * N + l + L * a];
+      } else {
+        res_load_row<N>(v, tile, y, l);
+      }
+      res_line_fft<N, true, L + 1, 1>(v, l, tw, tile + y * Res<N>::P);       // gradient wrt phi_i
+      const CT* prow = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i) * N + y) * N;
+      const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
+      float* g = r.gobj ? reinterpret_cast<float*>(r.gobj + orow) : nullptr;
+#pragma unroll
+      for (int a = 0; a < E; ++a) {
+        const float2 p = Ck<HALF>::load(prow + l + L * a);
+        const float2 o = r.obj[orow + l + L * a];
+        if (g) {
+          const float2 d = cjmul(p, v[a]);
+          unsafeAtomicAdd(g + 2 * (l + L * a), scale * d.x);
+          unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * d.y);
+        }
+        v[a] = cjmul(o, v[a]);
+      }
+      res_line_fft<N, false, L + 1, 1>(v, l, tw, tile + y * Res<N>::P);
+      if (i == 0) {
+#pragma unroll
+        for (int a = 0; a < E; ++a) wtile[(size_t)y * N + l + L * a] = v[a];
+      } else {
+        res_store_row<N>(v, tile, y, l);
+      }
+    }
+    __syncthreads();
+    if (i > 0) {
+      res_col_prop<N, true>(tile, tw, r.prop + (size_t)(i - 1) * N * N);
+      __syncthreads();
+    }
+  }
+}
+
+template <int N>
+static void res_fwd_n(const LaunchCtx& L, bool save) {
+  dim3 g(1, L.n_items, L.max_modes);
+  if (L.ck_half)
+    hipLaunchKernelGGL((k_res_fwd<N, true>), g, dim3(Res<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ck,
+                       L.ramps, L.tw, save ? 1 : 0, L.item_off);
+  else
+    hipLaunchKernelGGL((k_res_fwd<N, false>), g, dim3(Res<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ck,
+                       L.ramps, L.tw, save ? 1 : 0, L.item_off);
+}
+template <int N>
+static void res_adj_n(const LaunchCtx& L, float scale) {
+  dim3 g(1, L.n_items, L.max_modes);
+  if (L.ck_half)
+    hipLaunchKernelGGL((k_res_adj<N, true>), g, dim3(Res<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ck,
+                       L.tw, scale, L.item_off);
+  else
+    hipLaunchKernelGGL((k_res_adj<N, false>), g, dim3(Res<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ck,
+                       L.tw, scale, L.item_off);
+}
+
+bool resident_supported(int N) { return N == 64 || N == 128; }
+
+void launch_res_fwd(const LaunchCtx& L, int N, bool save) {
+  if (N == 64) res_fwd_n<64>(L, save);
+  else res_fwd_n<128>(L, save);
+}
+void launch_res_adj(const LaunchCtx& L, int N, float scale) {
+  if (N == 64) res_adj_n<64>(L, scale);
+  else res_adj_n<128>(L, scale);
 }
 
 }  // namespace pty

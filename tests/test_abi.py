@@ -77,12 +77,14 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.pty_last_error(None) == b"NULL context"
 
 
-def test_host_fft_emulation(tmp_path):
-    """The cross-lane line FFT of the kernels, emulated lane by lane on the
-    host, matches a double-precision DFT for every supported N."""
+@pytest.mark.parametrize("prog", ["line_fft_check", "resident_check"])
+def test_host_fft_emulation(tmp_path, prog):
+    """The cross-lane line FFT of the kernels (and the in-place 2D transform of
+    the LDS-resident tile), emulated lane by lane on the host, match a
+    double-precision DFT for every supported N."""
     from paper_2505_14372_amd import build_lib
-    exe = tmp_path / "line_fft_check"
-    src = os.path.join(ROOT, "tests", "host", "line_fft_check.cpp")
+    exe = tmp_path / prog
+    src = os.path.join(ROOT, "tests", "host", prog + ".cpp")
     r = subprocess.run([build_lib.hipcc(), "-std=c++17", "-O1", "-I", build_lib.CSRC, "-I", build_lib.INCLUDE,
                         src, "-o", str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]

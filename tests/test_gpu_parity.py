@@ -36,6 +36,14 @@ def _case(name):
     if name == "n256_ms_gaussian":
         return Case(synth.make_small(N=256, M=2, S=3, scan=3, step=8, seed=4, loss="gaussian", eps=0.0,
                                      phi_max=0.1, dose=1e3, dz=1.0))
+    if name == "n128_tilt_mask_dz":     # propagator tilt, a square band-limit mask, non-uniform gaps
+        wl = synth.make_small(N=128, M=2, S=4, scan=3, step=8, seed=6, loss="poisson", eps=0.8, phi_max=0.2,
+                              dose=1e5)
+        wl.dz = [1.0, 3.5, 2.0]
+        wl.tilt = (0.003, -0.005)
+        k = np.fft.fftfreq(128) * 128
+        wl.bandlimit_mask = (np.abs(k)[:, None] <= 40) & (np.abs(k)[None, :] <= 40)
+        return Case(wl)
     if name == "n64_amp_eps_nobl":
         return Case(synth.make_small(N=64, M=2, S=3, scan=3, step=5, seed=5, loss="amplitude", eps=0.5,
                                      bandlimit=0.0, amp_noise=0.1))
@@ -43,7 +51,7 @@ def _case(name):
 
 
 CASES = ["n64_spoa_amp", "n64_ms_poisson", "n128_ms_poisson", "n192_ms_anscombe", "n256_ms_gaussian",
-         "n64_amp_eps_nobl"]
+         "n64_amp_eps_nobl", "n128_tilt_mask_dz"]
 
 
 @pytest.fixture(scope="module")
@@ -309,3 +317,58 @@ def test_half_checkpoints_parity(cache, name, k):
                 pos=rel_l2(_np(gX), ref["g_pos"]))
     print(errs)
     assert all(e < TOL_G for e in errs.values()), errs
+
+
+def test_regularized_step_matches_oracle():
+    """reconstruct_step with every cost regularizer and every constraint (Sec. 3.4)."""
+    from paper_2505_14372_amd import api
+    c = Case(synth.make_small(N=64, M=2, S=4, scan=3, step=4, seed=30, loss="poisson", eps=0.8, amp_noise=0.3))
+    d = c.device()
+    prob = c.problem(max_batch=9)
+    k = np.fft.fftfreq(64) * 64
+    support = (k[:, None] ** 2 + k[None, :] ** 2) <= 20 ** 2
+    reg = dict(obj_l2=3.0, probe_l2=0.02, obj_l1=2.0, obj_tikhonov=5.0, obj_tv=4.0, layers_tikhonov=6.0,
+               layers_tv=3.0, tv_delta=0.05)
+    con = dict(amp_min=0.75, amp_max=0.98, probe_support=support, layer_sigma=0.8)
+    prob.set_regularizers(**reg, amp_range=(con["amp_min"], con["amp_max"]), probe_support=support,
+                          layer_sigma=con["layer_sigma"])
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    lr = dict(object=2e-4, probe=1e-4, pos=1e-4)
+    opt = api.Optimizer(kind="sgd", lr_object=lr["object"], lr_probe=lr["probe"], lr_pos=lr["pos"])
+    P0, O0, X0 = c.o_args()
+    ost = dict(probe=P0, object=O0, positions=X0)
+    oopt = dict(kind="sgd", lr_object=lr["object"], lr_probe=lr["probe"], lr_pos=lr["pos"], reg=reg, con=con)
+    for b in ([0, 3, 5, 8], [1, 2, 4, 6, 7]):
+        loss = prob.reconstruct_step(st, d["pats"], torch.tensor(b, dtype=torch.int32, device="cuda"), opt)
+        prob.check()
+        ost, oloss = orc.reconstruct_step(ost, c.pats.astype(np.float64), b, c.geom, oopt)
+        assert abs(loss.item() - oloss) < 1e-4 * abs(oloss), (loss.item(), oloss)
+    for key, got in (("object", st.object), ("probe", st.probe), ("positions", st.positions)):
+        g = _np(got).astype(np.complex128 if key != "positions" else np.float64)
+        assert rel_l2(g, ost[key]) < 1e-5, (key, rel_l2(g, ost[key]))
+    # the constraints hold on the GPU state
+    a = np.abs(_np(st.object))
+    assert a.min() >= 0.75 - 1e-5 and a.max() <= 0.98 + 1e-5
+    spec = np.fft.fft2(_np(st.probe))
+    assert np.max(np.abs(spec[:, ~support])) < 1e-4 * np.max(np.abs(spec))
+
+
+@pytest.mark.parametrize("strategy", ["two_pass", "resident"])
+@pytest.mark.parametrize("name", ["n64_spoa_amp", "n64_ms_poisson", "n128_ms_poisson", "n128_tilt_mask_dz"])
+def test_both_strategies_match_oracle(cache, name, strategy):
+    """N = 64, 128: the two-pass kernels and the LDS-resident chains both match
+    the oracle (intensities, loss, gradients), also with half checkpoints."""
+    c, ref = _get(cache, name)
+    d = c.device()
+    for half in (False, True):
+        prob = c.problem(checkpoint_half=half)
+        prob.set_strategy(strategy)
+        I, lf = prob.forward(d["probe"], d["obj"], d["pos"], d["batch"], patterns=d["pats"])
+        loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+        prob.check()
+        assert rel_l2(_np(I), ref["I"]) < TOL_I
+        assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+        errs = dict(obj=rel_l2(_np(gO), ref["g_object"]), probe=rel_l2(_np(gP), ref["g_probe"]),
+                    pos=rel_l2(_np(gX), ref["g_pos"]))
+        print(strategy, half, errs)
+        assert all(e < TOL_G for e in errs.values()), errs

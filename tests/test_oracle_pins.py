@@ -110,6 +110,38 @@ def test_propagator_gaussian_beam_closed_form():
     assert np.max(np.abs(psiz - bad)) > 1e-2
 
 
+def test_tilted_propagator_moves_the_gaussian_beam():
+    """With a beam tilt t the Fresnel step also moves the wave by -dz tan(t):
+    the closed-form beam of the untilted case, evaluated at r + dz tan(t)."""
+    N, dx, lam, z, w0 = 256, 0.2, 0.019688, 300.0, 3.0
+    tilt = (0.004, -0.007)                # radians
+    r = (np.arange(N) - N // 2) * dx
+    ry, rx = np.meshgrid(r, r, indexing="ij")
+    psi0 = np.exp(-(ry ** 2 + rx ** 2) / w0 ** 2)
+    H = orc.propagator(N, dx, lam, z, 0, tilt=tilt)
+    psiz = orc.ifft2u(H * orc.fft2u(psi0))
+    a = np.pi * w0 ** 2 + 1j * lam * z
+    dy, dxs = z * np.tan(tilt[0]), z * np.tan(tilt[1])
+    ref = (np.pi * w0 ** 2 / a) * np.exp(-np.pi * ((ry + dy) ** 2 + (rx + dxs) ** 2) / a)
+    assert np.max(np.abs(psiz - ref)) < 1e-10
+    # tilt is a phase: unitarity and the semigroup property still hold
+    assert np.allclose(np.abs(H), 1)
+    assert np.allclose(orc.propagator(N, dx, lam, 100.0, 0, tilt=tilt) * orc.propagator(N, dx, lam, 200.0, 0, tilt=tilt),
+                       H, atol=1e-12)
+
+
+def test_custom_bandlimit_mask():
+    N = 64
+    d = orc.propagator(N, 0.2, 0.02, 5.0, 2 / 3)
+    assert np.array_equal(orc.propagator(N, 0.2, 0.02, 5.0, 0.3, mask=orc.bandlimit_mask(N, 2 / 3)), d)
+    assert np.array_equal(orc.propagator(N, 0.2, 0.02, 5.0, 2 / 3, mask=np.ones((N, N), np.uint8)),
+                          orc.propagator(N, 0.2, 0.02, 5.0, 0))
+    k = orc.signed_bins(N)
+    square = (np.abs(k)[:, None] <= N // 3) & (np.abs(k)[None, :] <= N // 3)
+    H = orc.propagator(N, 0.2, 0.02, 5.0, 2 / 3, mask=square)
+    assert np.array_equal(H != 0, square)
+
+
 # ---------------------------------------------------------------- shift
 
 def test_shift_integer_is_roll_and_composes():
@@ -268,7 +300,7 @@ def test_poisson_weight_at_truth_with_eps():
 
 # ---------------------------------------------------------------- adjoint
 
-def _fd_problem(kind, eps, frac=2 / 3, seed=21):
+def _fd_problem(kind, eps, frac=2 / 3, seed=21, tilt=(0.0, 0.0), mask=None, dz=(3.0, 3.0)):
     rng = np.random.default_rng(seed)
     N, M, S = 8, 2, 3
     P = crandn(rng, M, N, N) * 0.7
@@ -276,13 +308,20 @@ def _fd_problem(kind, eps, frac=2 / 3, seed=21):
     X = np.array([[2.3, 3.8], [4.1, 1.7], [3.0, 4.35]])
     pats = 1.0 + 4 * rng.random((3, N, N))
     geom = _geom(N, S, loss=kind, eps=eps, frac=frac, dz=3.0)
+    geom.dz = list(dz)
+    geom.tilt = tilt
+    geom.bandlimit_mask = mask
     return P, O, X, pats, geom
 
 
-@pytest.mark.parametrize("kind,eps", [("gaussian", 0.0), ("poisson", 0.8), ("amplitude", 0.0),
-                                      ("anscombe", 0.0)])
-def test_gradients_match_central_finite_differences(kind, eps):
-    P, O, X, pats, geom = _fd_problem(kind, eps)
+FD_CASES = [("gaussian", 0.0, {}), ("poisson", 0.8, {}), ("amplitude", 0.0, {}), ("anscombe", 0.0, {}),
+            ("poisson", 0.8, dict(tilt=(0.02, -0.03), dz=(2.0, 5.0),
+                                  mask=np.random.default_rng(0).random((8, 8)) < 0.7))]
+
+
+@pytest.mark.parametrize("kind,eps,extra", FD_CASES)
+def test_gradients_match_central_finite_differences(kind, eps, extra):
+    P, O, X, pats, geom = _fd_problem(kind, eps, **extra)
     idx = [0, 1, 2]
     r = orc.loss_and_grad(P, O, X, pats, idx, geom)
     L = lambda P_, O_, X_: orc.total_loss(P_, O_, X_, pats, idx, geom)  # noqa: E731

@@ -1,0 +1,116 @@
+"""Pins of the oracle's regularizers (Sec. 3.4): central finite differences of
+each cost against its gradient, closed forms on special objects, and the
+constraints' defining properties."""
+import numpy as np
+import pytest
+
+import oracle as orc
+
+
+def crandn(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("key", orc.REG_KEYS)
+def test_regularizer_gradient_matches_finite_differences(key):
+    rng = np.random.default_rng(hash(key) % 1000)
+    O = 1 + 0.3 * crandn(rng, 3, 6, 7)
+    P = crandn(rng, 2, 5, 5)
+    reg = {key: 0.7, "tv_delta": 0.05}
+    _, gO, gP = orc.regularization(O, P, reg)
+    h = 1e-6
+    for _ in range(12):
+        if key == "probe_l2":
+            idx = (rng.integers(2), rng.integers(5), rng.integers(5))
+            base, g = P, gP
+        else:
+            idx = (rng.integers(3), rng.integers(6), rng.integers(7))
+            base, g = O, gO
+        for part in (1, 1j):
+            a, b = base.copy(), base.copy()
+            a[idx] += h * part
+            b[idx] -= h * part
+            if key == "probe_l2":
+                fd = (orc.regularization(O, a, reg)[0] - orc.regularization(O, b, reg)[0]) / (2 * h)
+            else:
+                fd = (orc.regularization(a, P, reg)[0] - orc.regularization(b, P, reg)[0]) / (2 * h)
+            an = g[idx].real if part == 1 else g[idx].imag
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (key, idx, fd, an)
+
+
+def test_vacuum_and_closed_forms():
+    S, H, W = 3, 8, 9
+    vac = np.ones((S, H, W), complex)
+    P = np.zeros((1, 4, 4), complex)
+    for key in orc.REG_KEYS:
+        if key in ("obj_tv", "layers_tv"):
+            continue
+        c, gO, gP = orc.regularization(vac, P, {key: 1.0})
+        assert c == 0 and np.all(gO == 0) and np.all(gP == 0)
+    # smoothed TV of a constant object: delta per difference
+    d = 0.01
+    c, gO, _ = orc.regularization(vac, P, {"obj_tv": 1.0, "tv_delta": d})
+    assert abs(c - d * S * ((H - 1) * W + H * (W - 1))) < 1e-12 and np.all(gO == 0)
+    c, _, _ = orc.regularization(vac, P, {"layers_tv": 1.0, "tv_delta": d})
+    assert abs(c - d * (S - 1) * H * W) < 1e-12
+    # Tikhonov of a phase ramp along y: |e^{ia} - 1|^2 = 2 - 2 cos a per difference
+    a = 0.3
+    y = np.arange(H)[None, :, None]
+    ramp = np.exp(1j * a * y) * np.ones((S, H, W))
+    c, _, _ = orc.regularization(ramp, P, {"obj_tikhonov": 1.0})
+    assert abs(c - S * (H - 1) * W * (2 - 2 * np.cos(a))) < 1e-10
+    # layers Tikhonov of a depth ramp
+    z = np.arange(S)[:, None, None]
+    c, _, _ = orc.regularization(np.exp(1j * a * z) * np.ones((S, H, W)), P, {"layers_tikhonov": 1.0})
+    assert abs(c - (S - 1) * H * W * (2 - 2 * np.cos(a))) < 1e-10
+    # L2 of the probe is its power
+    P = crandn(np.random.default_rng(1), 2, 4, 4)
+    assert abs(orc.regularization(vac, P, {"probe_l2": 1.0})[0] - np.sum(np.abs(P) ** 2)) < 1e-12
+
+
+def test_constraints():
+    rng = np.random.default_rng(2)
+    O = (0.2 + 2 * rng.random((4, 5, 6))) * np.exp(1j * rng.random((4, 5, 6)))
+    P = crandn(rng, 2, 8, 8)
+    O2, P2 = orc.apply_constraints(O, P, {"amp_min": 0.5, "amp_max": 1.5})
+    assert np.all(np.abs(O2) >= 0.5 - 1e-12) and np.all(np.abs(O2) <= 1.5 + 1e-12)
+    assert np.allclose(np.angle(O2), np.angle(O))
+    inside = (np.abs(O) >= 0.5) & (np.abs(O) <= 1.5)
+    assert np.array_equal(O2[inside], O[inside]) and np.array_equal(P2, P)
+    # probe support: all-ones mask is the identity, a mask zeroes the spectrum outside
+    _, P3 = orc.apply_constraints(O, P, {"probe_support": np.ones((8, 8))})
+    assert np.allclose(P3, P)
+    m = np.zeros((8, 8))
+    m[:3, :3] = 1
+    _, P4 = orc.apply_constraints(O, P, {"probe_support": m})
+    assert np.allclose(orc.fft2u(P4) * (1 - m), 0) and np.allclose(orc.fft2u(P4) * m, orc.fft2u(P) * m)
+    # layer blur: identical slices unchanged; one bright slice spreads as normalised Gaussian weights
+    same = np.repeat(O[:1], 4, axis=0)
+    assert np.allclose(orc.apply_constraints(same, P, {"layer_sigma": 1.3})[0], same)
+    spike = np.zeros((5, 1, 1), complex)
+    spike[2] = 1
+    out = orc.apply_constraints(spike, P, {"layer_sigma": 1.0})[0][:, 0, 0]
+    g = np.exp(-0.5 * np.arange(-4, 5) ** 2)
+    for i in range(5):
+        js = range(max(0, i - 3), min(5, i + 4))
+        assert abs(out[i] - (np.exp(-0.5 * (i - 2) ** 2) if abs(i - 2) <= 3 else 0)
+                   / sum(np.exp(-0.5 * (i - j) ** 2) for j in js)) < 1e-12
+    assert g.sum() > 0
+
+
+def test_reconstruct_step_adds_regularizer_gradient():
+    rng = np.random.default_rng(3)
+    N = 8
+    P = crandn(rng, 1, N, N) * 0.5
+    O = np.exp(1j * rng.random((2, 12, 12)))
+    X = np.array([[1.2, 2.3], [3.1, 0.8]])
+    pats = 1 + 3 * rng.random((2, N, N))
+    geom = orc.Geometry(N=N, dz=[2.0], loss="gaussian")
+    reg = {"obj_l2": 0.3, "obj_tikhonov": 0.2, "layers_tikhonov": 0.5, "probe_l2": 0.1}
+    opt = dict(kind="sgd", lr_object=1e-3, lr_probe=1e-4, lr_pos=0.0, reg=reg)
+    new, loss = orc.reconstruct_step(dict(probe=P, object=O, positions=X), pats, [0, 1], geom, opt)
+    r = orc.loss_and_grad(P, O, X, pats, [0, 1], geom)
+    c, gO, gP = orc.regularization(O, P, reg)
+    assert abs(loss - (r["loss"] + c)) < 1e-12
+    assert np.allclose(new["object"], O - 1e-3 * (r["g_object"] + gO))
+    assert np.allclose(new["probe"], P - 1e-4 * (r["g_probe"] + gP))
