@@ -228,6 +228,13 @@ typedef struct {
  *   probe_support   host [N][N] reciprocal-space mask (FFT order) or NULL: P <- F^-1(mask F(P))
  *   layer_sigma     Gaussian blur along depth (sigma in slices, truncated at 3 sigma, normalised,
  *                   real space; 0 = off; at most 64 slices)
+ *   obj_lowpass_sigma  in-plane Gaussian low pass of every slice (sigma in pixels, at most 64; taps
+ *                   t = -r..r with r = ceil(3 sigma), weights exp(-t^2 / 2 sigma^2) normalised;
+ *                   separable, x then y, periodic boundaries; 0 = off)
+ *   phase_deramp    nonzero: per slice, remove the affine phase theta_0 + theta_y y + theta_x x,
+ *                   theta_x = arg sum O(y, x+1) conj O(y, x), theta_y likewise along y, theta_0 =
+ *                   arg of the sum of the de-ramped slice
+ * Order: amplitude range, depth blur, low pass, deramp (object); support (probe).
  * A NULL argument turns all regularization off. */
 typedef struct {
   double obj_l2, probe_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta;
@@ -235,6 +242,8 @@ typedef struct {
   double amp_min, amp_max;
   const uint8_t* probe_support;
   double layer_sigma;
+  double obj_lowpass_sigma;
+  int32_t phase_deramp;
 } pty_regularizers;
 
 pty_status pty_set_regularizers(pty_ctx* ctx, const pty_regularizers* reg);

@@ -467,18 +467,61 @@ def regularization(obj, probe, reg):
     return float(cost), gO, gP
 
 
+def gaussian_taps(sigma):
+    """Offsets t = -r..r, r = ceil(3 sigma), and the normalised weights
+    exp(-t^2 / (2 sigma^2)) / sum."""
+    r = int(np.ceil(3 * sigma))
+    t = np.arange(-r, r + 1)
+    w = np.exp(-0.5 * (t / sigma) ** 2)
+    return t, w / w.sum()
+
+
+def lowpass_object(obj, sigma):
+    """Object low pass (Sec. 3.4): every slice convolved in the plane with a
+    sampled Gaussian (taps above), separably along x then y, with periodic
+    boundaries, as a filter applied in reciprocal space would have."""
+    t, w = gaussian_taps(sigma)
+    out = np.asarray(obj, dtype=np.complex128)
+    for axis in (2, 1):
+        acc = np.zeros_like(out)
+        for tk, wk in zip(t, w):
+            acc += wk * np.roll(out, -tk, axis=axis)       # out[.., x + tk] (periodic)
+        out = acc
+    return out
+
+
+def deramp_object(obj):
+    """Object phase deramp (Sec. 3.4), per slice: the affine phase
+    theta_0 + theta_y y + theta_x x is removed, with theta_x the angle of
+    sum O(y, x+1) conj(O(y, x)) over horizontally adjacent pairs, theta_y
+    likewise for vertical pairs, and theta_0 the angle of the sum of the
+    de-ramped slice (amplitude-weighted estimates of the mean phase gradient
+    and the mean phase)."""
+    O = np.asarray(obj, dtype=np.complex128)
+    out = np.empty_like(O)
+    H, W = O.shape[1:]
+    y = np.arange(H)[:, None]
+    x = np.arange(W)[None, :]
+    for i, Oi in enumerate(O):
+        tx = np.angle(np.sum(Oi[:, 1:] * np.conj(Oi[:, :-1])))
+        ty = np.angle(np.sum(Oi[1:, :] * np.conj(Oi[:-1, :])))
+        D = Oi * np.exp(-1j * (ty * y + tx * x))
+        out[i] = D * np.exp(-1j * np.angle(np.sum(D)))
+    return out
+
+
 def apply_constraints(obj, probe, con):
-    """Constraint regularizers after a step (Sec. 3.4). con keys: amp_min,
-    amp_max (object amplitude range), probe_support (reciprocal-space mask
-    [N][N], FFT order), layer_sigma (Gaussian depth blur, slices)."""
+    """Constraint regularizers after a step (Sec. 3.4), in this order:
+    object amplitude range (amp_min, amp_max), Gaussian depth blur
+    (layer_sigma, slices), in-plane Gaussian low pass (obj_lowpass_sigma,
+    pixels), phase deramp (phase_deramp), probe support (probe_support,
+    reciprocal-space mask [N][N] in FFT order)."""
     O = np.array(obj, dtype=np.complex128)
     P = np.array(probe, dtype=np.complex128)
     if "amp_min" in con or "amp_max" in con:
         a = np.abs(O)
         c = np.clip(a, con.get("amp_min", 0.0), con.get("amp_max", np.inf))
         O = np.where(a > 0, O * (c / np.where(a > 0, a, 1)), c)
-    if con.get("probe_support") is not None:
-        P = ifft2u(fft2u(P) * (np.asarray(con["probe_support"]) != 0))
     s = con.get("layer_sigma", 0.0)
     if s and O.shape[0] > 1:
         S = O.shape[0]
@@ -493,4 +536,11 @@ def apply_constraints(obj, probe, con):
                 den += g
             out[i] = num / den
         O = out
+    s = con.get("obj_lowpass_sigma", 0.0)
+    if s:
+        O = lowpass_object(O, s)
+    if con.get("phase_deramp"):
+        O = deramp_object(O)
+    if con.get("probe_support") is not None:
+        P = ifft2u(fft2u(P) * (np.asarray(con["probe_support"]) != 0))
     return O, P

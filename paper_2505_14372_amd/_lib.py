@@ -51,7 +51,7 @@ class Regularizers(C.Structure):
                 ("obj_tikhonov", C.c_double), ("obj_tv", C.c_double), ("layers_tikhonov", C.c_double),
                 ("layers_tv", C.c_double), ("tv_delta", C.c_double), ("amp_clamp", C.c_int32),
                 ("amp_min", C.c_double), ("amp_max", C.c_double), ("probe_support", C.POINTER(C.c_uint8)),
-                ("layer_sigma", C.c_double)]
+                ("layer_sigma", C.c_double), ("obj_lowpass_sigma", C.c_double), ("phase_deramp", C.c_int32)]
 
 
 class State(C.Structure):

@@ -152,7 +152,7 @@ class Problem:
 
     def set_regularizers(self, obj_l2=0.0, probe_l2=0.0, obj_l1=0.0, obj_tikhonov=0.0, obj_tv=0.0,
                          layers_tikhonov=0.0, layers_tv=0.0, tv_delta=1e-3, amp_range=None, probe_support=None,
-                         layer_sigma=0.0):
+                         layer_sigma=0.0, obj_lowpass_sigma=0.0, phase_deramp=False):
         """Cost and constraint regularizers applied by reconstruct_step (see include/pty.h)."""
         mask = None
         if probe_support is not None:
@@ -163,7 +163,8 @@ class Problem:
         lo, hi = amp_range if amp_range is not None else (0.0, 0.0)
         r = _lib.Regularizers(obj_l2, probe_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta,
                               1 if amp_range is not None else 0, lo, hi,
-                              C.cast(mask, C.POINTER(C.c_uint8)) if mask is not None else None, layer_sigma)
+                              C.cast(mask, C.POINTER(C.c_uint8)) if mask is not None else None, layer_sigma,
+                              obj_lowpass_sigma, 1 if phase_deramp else 0)
         st = self.lib.pty_set_regularizers(self.ctx, C.byref(r))
         if st:
             self._err(st, "pty_set_regularizers")

@@ -207,6 +207,9 @@ struct pty_ctx {
   uint8_t* support = nullptr;      // device [N][N] or null
   float* blur = nullptr;           // device Gaussian weights [r + 1]
   int blur_r = 0;
+  float* lowpass = nullptr;        // device in-plane Gaussian weights [r + 1], normalised over 2r + 1 taps
+  int lowpass_r = 0;
+  double* deramp = nullptr;        // device [S][3] angles, then [S][deramp_blocks][4] partial sums
   float* reg_part = nullptr;       // cost partial sums
   // tape of pty_forward_save
   bool tape_valid = false;
@@ -525,7 +528,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->tw); dfree(c->prop); dfree(c->phat); dfree(c->gphat); dfree(c->gprobe); dfree(c->gobj);
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
-  dfree(c->support); dfree(c->blur); dfree(c->reg_part);
+  dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part);
   delete c;
 }
 
@@ -740,6 +743,10 @@ void apply_constraints(pty_ctx* c, hipStream_t s, pty_state* st) {
   const size_t HW = (size_t)g.obj_h * g.obj_w;
   if (c->amp_clamp) launch_amp_clamp(s, (float2*)st->object, HW * g.n_slices, c->amp_min, c->amp_max);
   if (c->blur) launch_layer_blur(s, (float2*)st->object, g.n_slices, HW, c->blur, c->blur_r);
+  // the object gradient buffer is free once the optimiser has run
+  if (c->lowpass) launch_lowpass(s, (float2*)st->object, c->gobj, g.n_slices, g.obj_h, g.obj_w, c->lowpass, c->lowpass_r);
+  if (c->deramp)
+    launch_deramp(s, (float2*)st->object, g.n_slices, g.obj_h, g.obj_w, c->deramp, c->deramp + 3 * g.n_slices);
   if (c->support) {
     const int N = g.N, M = g.n_modes;
     launch_plain2d(N, s, c->tw, (const float2*)st->probe, c->gphat, M, false, 1.f / N, false);
@@ -754,9 +761,11 @@ extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r
   if (!c) return PTY_EINVAL;
   dfree(c->support);
   dfree(c->blur);
+  dfree(c->lowpass);
+  dfree(c->deramp);
   c->reg_on = c->con_on = false;
   c->amp_clamp = 0;
-  c->blur_r = 0;
+  c->blur_r = c->lowpass_r = 0;
   if (!r) return PTY_OK;
   const double w[7] = {r->obj_l2, r->probe_l2, r->obj_l1, r->obj_tikhonov, r->obj_tv, r->layers_tikhonov, r->layers_tv};
   for (double x : w)
@@ -765,6 +774,10 @@ extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r
   if (r->amp_clamp && !(r->amp_min >= 0 && r->amp_max >= r->amp_min)) { c->err = "need 0 <= amp_min <= amp_max"; return PTY_EINVAL; }
   if (r->layer_sigma < 0 || (r->layer_sigma > 0 && c->g.n_slices > kMaxBlurSlices)) {
     c->err = "layer blur needs sigma >= 0 and at most 64 slices";
+    return PTY_EINVAL;
+  }
+  if (!(r->obj_lowpass_sigma >= 0 && r->obj_lowpass_sigma <= 64)) {
+    c->err = "object low pass needs 0 <= sigma <= 64 pixels";
     return PTY_EINVAL;
   }
   c->rg = RegDev{(float)r->obj_l2, (float)r->obj_l1, (float)r->obj_tikhonov, (float)r->obj_tv,
@@ -790,7 +803,25 @@ extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r
     if ((st = dmalloc(&c->blur, gw.size(), c->err))) return st;
     if (hipMemcpy(c->blur, gw.data(), gw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return PTY_EHIP;
   }
-  c->con_on = c->amp_clamp || c->support || c->blur;
+  if (r->obj_lowpass_sigma > 0) {
+    const double sg = r->obj_lowpass_sigma;
+    c->lowpass_r = (int)std::ceil(3.0 * sg);
+    std::vector<double> gd(c->lowpass_r + 1);
+    double tot = 0.0;
+    for (int t = 0; t <= c->lowpass_r; ++t) {
+      gd[t] = std::exp(-0.5 * (t / sg) * (t / sg));
+      tot += t ? 2 * gd[t] : gd[t];
+    }
+    std::vector<float> gw(gd.size());
+    for (size_t t = 0; t < gd.size(); ++t) gw[t] = (float)(gd[t] / tot);
+    if ((st = dmalloc(&c->lowpass, gw.size(), c->err))) return st;
+    if (hipMemcpy(c->lowpass, gw.data(), gw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return PTY_EHIP;
+  }
+  if (r->phase_deramp) {
+    const size_t n = 3 * (size_t)c->g.n_slices + (size_t)c->g.n_slices * deramp_blocks(c->g.obj_h, c->g.obj_w) * 4;
+    if ((st = dmalloc(&c->deramp, n, c->err))) return st;
+  }
+  c->con_on = c->amp_clamp || c->support || c->blur || c->lowpass || c->deramp;
   return PTY_OK;
 }
 

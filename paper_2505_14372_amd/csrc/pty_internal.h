@@ -120,6 +120,12 @@ void launch_add_cost(hipStream_t s, const float* part, int n, double* loss);
 void launch_amp_clamp(hipStream_t s, float2* O, size_t n, float lo, float hi);
 void launch_layer_blur(hipStream_t s, float2* O, int S, size_t HW, const float* g, int r);
 void launch_mask_tiles(hipStream_t s, float2* t, const uint8_t* mask, size_t n, int N2);
+// In-plane periodic Gaussian low pass of every slice; tmp holds S*H*W values.
+void launch_lowpass(hipStream_t s, float2* O, float2* tmp, int S, int H, int W, const float* w, int r);
+// Blocks per slice of the deramp sums (the partials buffer holds S * this * 4 doubles).
+int deramp_blocks(int H, int W);
+// Affine phase removal per slice; theta: S * 3 doubles, part: see deramp_blocks.
+void launch_deramp(hipStream_t s, float2* O, int S, int H, int W, double* theta, double* part);
 
 // LDS-resident forward / adjoint chains (N = 64, 128; every slice checkpointed)
 bool resident_supported(int N);

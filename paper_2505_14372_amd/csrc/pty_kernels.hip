@@ -311,6 +311,32 @@ template <int N> struct ColPass {
   static constexpr int NBLK = N / CB;
 };
 
+// Thread -> (column, lane) mapping of the column passes.
+// Block-wide (default): column c = t % CB, lane l = t / CB, so a load of
+// register a reads CB consecutive values of one row per lane group; a
+// column's lanes span several waves and exchange through LDS with block
+// barriers. Wave-local (PTY_COL_WAVE_LOCAL): each wave owns 64 / L whole
+// columns (column fastest within the wave), so the exchange needs no block
+// barrier; a load instruction then covers 64 / L consecutive values of L rows.
+#ifndef PTY_COL_WAVE_LOCAL
+#define PTY_COL_WAVE_LOCAL 0
+#endif
+template <int N> struct ColMap {
+  static constexpr int L = Cfg<N>::L, CB = ColPass<N>::CB, CPW = 64 / L;
+#if PTY_COL_WAVE_LOCAL
+  // exchange stride per column: searched for two bank cycles per access
+  static constexpr int STRIDE = N == 64 ? 72 : N == 128 ? 148 : N == 192 ? 216 : 272;
+  __device__ __forceinline__ static int col() { return (threadIdx.x >> 6) * CPW + (threadIdx.x & 63) % CPW; }
+  __device__ __forceinline__ static int lane() { return (threadIdx.x & 63) / CPW; }
+  using Sync = WaveSync;
+#else
+  static constexpr int STRIDE = Xch<N>::COL_STRIDE;
+  __device__ __forceinline__ static int col() { return threadIdx.x % CB; }
+  __device__ __forceinline__ static int lane() { return threadIdx.x / CB; }
+  using Sync = BlockSync;
+#endif
+};
+
 // Column passes over (item, mode) tiles:
 //   COL_SHIFT    tile = IDFT_y(phat_m * R_j) / N         (start of the forward model)
 //   COL_PROP     tile = IDFT_y(H_i * DFT_y(tile))        (forward, slice i = step < S-1)
@@ -325,7 +351,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
                                                   float* __restrict__ pos_part, int item_off) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[CB * Xch<N>::COL_STRIDE];
+  __shared__ float2 xch[CB * ColMap<N>::STRIDE];
   __shared__ float red[2][ColPass<N>::THREADS / 64];
   const int b = item_off + blockIdx.y, m = blockIdx.z;
   const Item it = items[b];
@@ -337,9 +363,9 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   if constexpr (OP == COL_FINAL) { if (r.S - 1 - step != 0) return; }
   load_twiddles<N>(tw, twg);
   __syncthreads();
-  const int c = threadIdx.x % CB, l = threadIdx.x / CB;
+  const int c = ColMap<N>::col(), l = ColMap<N>::lane();
   const int ux = blockIdx.x * CB + c;
-  float2* sx = xch + c * Xch<N>::COL_STRIDE;
+  float2* sx = xch + c * ColMap<N>::STRIDE;
   float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
   float2 v[E];
   if constexpr (OP == COL_SHIFT) {
@@ -352,11 +378,11 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
       int uy = l + L * a;
       v[a] = cscale(cmul(cmul(ph[(size_t)uy * N + ux], ry[uy]), rx), inv);
     }
-    line_fft<N, true>(v, l, tw, sx, BlockSync{});
+    line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
   } else {
 #pragma unroll
     for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
-    line_fft<N, false>(v, l, tw, sx, BlockSync{});
+    line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
     if constexpr (OP == COL_PROP || OP == COL_PROP_ADJ) {
       const float2* H = r.prop + (size_t)(OP == COL_PROP ? i : i - 1) * N * N;
 #pragma unroll
@@ -364,7 +390,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
         float2 h = H[(size_t)(l + L * a) * N + ux];
         v[a] = (OP == COL_PROP) ? cmul(v[a], h) : cjmul(h, v[a]);
       }
-      line_fft<N, true>(v, l, tw, sx, BlockSync{});
+      line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
     } else {  // COL_FINAL
       const float inv = 1.f / (float)N;
       const float2* ry = ramps + (size_t)b * 2 * N;
@@ -409,16 +435,16 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col_plain(float2* __res
                                                         float scale) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[CB * Xch<N>::COL_STRIDE];
+  __shared__ float2 xch[CB * ColMap<N>::STRIDE];
   load_twiddles<N>(tw, twg);
   __syncthreads();
-  const int c = threadIdx.x % CB, l = threadIdx.x / CB;
+  const int c = ColMap<N>::col(), l = ColMap<N>::lane();
   const int ux = blockIdx.x * CB + c;
   float2* tile = t + (size_t)blockIdx.y * N * N;
   float2 v[E];
 #pragma unroll
   for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
-  line_fft<N, INV>(v, l, tw, xch + c * Xch<N>::COL_STRIDE, BlockSync{});
+  line_fft<N, INV>(v, l, tw, xch + c * ColMap<N>::STRIDE, typename ColMap<N>::Sync{});
 #pragma unroll
   for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = cscale(v[a], scale);
 }
@@ -465,13 +491,13 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __
                                                        int item_off) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
   __shared__ float2 tw[N];
-  __shared__ float2 xch[CB * Xch<N>::COL_STRIDE];
+  __shared__ float2 xch[CB * ColMap<N>::STRIDE];
   __shared__ float red[ColPass<N>::THREADS / 64];
   const int b = item_off + blockIdx.y;
   const Item it = items[b];
   const ReqDev& r = reqs.r[it.req];
   if (step != r.S - 1) return;
-  const int c = threadIdx.x % CB, l = threadIdx.x / CB;
+  const int c = ColMap<N>::col(), l = ColMap<N>::lane();
   const int ux = blockIdx.x * CB + c;
   if (!it.valid) {
     if (r.I_out) {
@@ -484,7 +510,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __
   }
   load_twiddles<N>(tw, twg);
   __syncthreads();
-  float2* sx = xch + c * Xch<N>::COL_STRIDE;
+  float2* sx = xch + c * ColMap<N>::STRIDE;
   const float inv = 1.f / (float)N;
   float I[E];
 #pragma unroll
@@ -494,7 +520,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __
     float2 v[E];
 #pragma unroll
     for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
-    line_fft<N, false>(v, l, tw, sx, BlockSync{});
+    line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
 #pragma unroll
     for (int a = 0; a < E; ++a) {
       v[a] = cscale(v[a], inv);
@@ -536,7 +562,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __
       float2 v[E];
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = cscale(tile[(size_t)(l + L * a) * N + ux], wgt[a] * inv);
-      line_fft<N, true>(v, l, tw, sx, BlockSync{});
+      line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
 #pragma unroll
       for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = v[a];
     }
@@ -901,6 +927,129 @@ __global__ void k_layer_blur(float2* __restrict__ O, int S, size_t HW, const flo
   }
 }
 
+// In-plane Gaussian low pass, one axis at a time (AXIS 0: along x, AXIS 1:
+// along y) with periodic boundaries: dst[s][y][x] = sum_{t=-r..r} w[|t|] *
+// src[s][y][x + t] (or src[s][y + t][x]), indices wrapped. w is normalised
+// over the 2r + 1 taps.
+template <int AXIS>
+__global__ void k_lowpass(const float2* __restrict__ src, float2* __restrict__ dst, int S, int H, int W,
+                          const float* __restrict__ w, int r) {
+  const size_t n = (size_t)S * H * W;
+  const int len = AXIS == 0 ? W : H;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(e % W);
+    const size_t row = e / W;                      // s * H + y
+    const int y = (int)(row % H);
+    const int at = AXIS == 0 ? x : y;
+    int q = (at - r) % len;
+    if (q < 0) q += len;
+    const float2* base = AXIS == 0 ? src + row * W : src + (row - y) * W + x;
+    const size_t step = AXIS == 0 ? 1 : (size_t)W;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int t = -r; t <= r; ++t) {
+      acc = cadd(acc, cscale(base[q * step], w[t < 0 ? -t : t]));
+      if (++q == len) q = 0;
+    }
+    dst[e] = acc;
+  }
+}
+
+// Phase deramp sums of one slice per blockIdx.y, reduced in double.
+// PHASE 0: part = (sum O(y,x+1) conj O(y,x), sum O(y+1,x) conj O(y,x)) as
+// (re, im, re, im); PHASE 1: part = sum O(y,x) exp(-i(ty y + tx x)) with
+// (ty, tx) = theta[s][1..2].
+template <int PHASE>
+__global__ __launch_bounds__(kThreads) void k_deramp_sums(const float2* __restrict__ O, int H, int W,
+                                                           const double* __restrict__ theta,
+                                                           double* __restrict__ part) {
+  const int s = blockIdx.y;
+  const size_t HW = (size_t)H * W;
+  const float2* Os = O + s * HW;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  const double ty = PHASE ? theta[s * 3 + 1] : 0.0, tx = PHASE ? theta[s * 3 + 2] : 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < HW; e += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(e % W), y = (int)(e / W);
+    const float2 o = Os[e];
+    if (PHASE == 0) {
+      if (x + 1 < W) {
+        const float2 q = Os[e + 1];
+        a[0] += (double)q.x * o.x + (double)q.y * o.y;
+        a[1] += (double)q.y * o.x - (double)q.x * o.y;
+      }
+      if (y + 1 < H) {
+        const float2 q = Os[e + W];
+        a[2] += (double)q.x * o.x + (double)q.y * o.y;
+        a[3] += (double)q.y * o.x - (double)q.x * o.y;
+      }
+    } else {
+      double ph = ty * y + tx * x;
+      ph -= 6.283185307179586 * rint(ph * 0.15915494309189535);
+      float sn, cs;
+      sincosf((float)ph, &sn, &cs);
+      a[0] += (double)o.x * cs + (double)o.y * sn;     // o * exp(-i ph)
+      a[1] += (double)o.y * cs - (double)o.x * sn;
+    }
+  }
+  __shared__ double red[4][kThreads / 64];
+  for (int c = 0; c < 4; ++c) {
+    double v = a[c];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) t += red[threadIdx.x][w];
+    part[((size_t)s * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = t;
+  }
+}
+
+// One block per slice: sum the partials of k_deramp_sums and store the
+// angles: PHASE 0 theta[s][1] = arg(vertical pair sum), theta[s][2] =
+// arg(horizontal pair sum); PHASE 1 theta[s][0] = arg(de-ramped slice sum).
+template <int PHASE>
+__global__ __launch_bounds__(kThreads) void k_deramp_angles(const double* __restrict__ part, int nblk,
+                                                             double* __restrict__ theta) {
+  const int s = blockIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kThreads)
+    for (int c = 0; c < 4; ++c) a[c] += part[((size_t)s * nblk + b) * 4 + c];
+  __shared__ double red[4][kThreads / 64];
+  for (int c = 0; c < 4; ++c) {
+    double v = a[c];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 4; ++c)
+      for (int w = 0; w < kThreads / 64; ++w) t[c] += red[c][w];
+    if (PHASE == 0) {
+      theta[s * 3 + 1] = atan2(t[3], t[2]);
+      theta[s * 3 + 2] = atan2(t[1], t[0]);
+    } else {
+      theta[s * 3 + 0] = atan2(t[1], t[0]);
+    }
+  }
+}
+
+// O[s][y][x] *= exp(-i (theta0 + ty y + tx x)).
+__global__ void k_deramp_apply(float2* __restrict__ O, int S, int H, int W, const double* __restrict__ theta) {
+  const size_t HW = (size_t)H * W, n = HW * S;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(e / HW);
+    const size_t p = e % HW;
+    const int x = (int)(p % W), y = (int)(p / W);
+    double ph = theta[s * 3] + theta[s * 3 + 1] * y + theta[s * 3 + 2] * x;
+    ph -= 6.283185307179586 * rint(ph * 0.15915494309189535);
+    float sn, cs;
+    sincosf((float)ph, &sn, &cs);
+    const float2 o = O[e];
+    O[e] = make_float2(o.x * cs + o.y * sn, o.y * cs - o.x * sn);
+  }
+}
+
 // t <- t * mask (elementwise over n_tiles tiles of N*N).
 __global__ void k_mask_tiles(float2* __restrict__ t, const uint8_t* __restrict__ mask, size_t n, int N2) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
@@ -931,6 +1080,23 @@ void launch_amp_clamp(hipStream_t s, float2* O, size_t n, float lo, float hi) {
 }
 void launch_layer_blur(hipStream_t s, float2* O, int S, size_t HW, const float* g, int r) {
   hipLaunchKernelGGL(k_layer_blur, dim3(reg_blocks(HW)), dim3(kThreads), 0, s, O, S, HW, g, r);
+}
+void launch_lowpass(hipStream_t s, float2* O, float2* tmp, int S, int H, int W, const float* w, int r) {
+  const size_t n = (size_t)S * H * W;
+  hipLaunchKernelGGL(k_lowpass<0>, dim3(reg_blocks(n)), dim3(kThreads), 0, s, O, tmp, S, H, W, w, r);
+  hipLaunchKernelGGL(k_lowpass<1>, dim3(reg_blocks(n)), dim3(kThreads), 0, s, tmp, O, S, H, W, w, r);
+}
+int deramp_blocks(int H, int W) {
+  const size_t b = ((size_t)H * W + kThreads - 1) / kThreads;
+  return (int)(b > 256 ? 256 : b);
+}
+void launch_deramp(hipStream_t s, float2* O, int S, int H, int W, double* theta, double* part) {
+  const int nb = deramp_blocks(H, W);
+  hipLaunchKernelGGL(k_deramp_sums<0>, dim3(nb, S), dim3(kThreads), 0, s, O, H, W, theta, part);
+  hipLaunchKernelGGL(k_deramp_angles<0>, dim3(S), dim3(kThreads), 0, s, part, nb, theta);
+  hipLaunchKernelGGL(k_deramp_sums<1>, dim3(nb, S), dim3(kThreads), 0, s, O, H, W, theta, part);
+  hipLaunchKernelGGL(k_deramp_angles<1>, dim3(S), dim3(kThreads), 0, s, part, nb, theta);
+  hipLaunchKernelGGL(k_deramp_apply, dim3(reg_blocks((size_t)S * H * W)), dim3(kThreads), 0, s, O, S, H, W, theta);
 }
 void launch_mask_tiles(hipStream_t s, float2* t, const uint8_t* mask, size_t n, int N2) {
   hipLaunchKernelGGL(k_mask_tiles, dim3(reg_blocks(n)), dim3(kThreads), 0, s, t, mask, n, N2);

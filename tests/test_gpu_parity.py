@@ -353,6 +353,40 @@ def test_regularized_step_matches_oracle():
     assert np.max(np.abs(spec[:, ~support])) < 1e-4 * np.max(np.abs(spec))
 
 
+def test_lowpass_and_deramp_constraints_match_oracle():
+    """reconstruct_step with the object low pass and the phase deramp (Sec. 3.4)
+    on an odd-sized object that carries an affine phase ramp per slice."""
+    from paper_2505_14372_amd import api
+    wl = synth.make_small(N=64, M=2, S=3, scan=5, step=5, seed=31, loss="amplitude", amp_noise=0.2)
+    S, H, W = wl.obj.shape
+    y, x = np.mgrid[:H, :W]
+    wl.obj = wl.obj * np.exp(1j * (0.3 + 0.02 * np.arange(1, S + 1)[:, None, None] * y
+                                  - 0.03 * np.arange(1, S + 1)[:, None, None] * x))
+    c = Case(wl)
+    d = c.device()
+    prob = c.problem(max_batch=len(c.batch))
+    con = dict(layer_sigma=0.7, obj_lowpass_sigma=1.5, phase_deramp=1)
+    prob.set_regularizers(layer_sigma=0.7, obj_lowpass_sigma=1.5, phase_deramp=True)
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    opt = api.Optimizer(kind="sgd", lr_object=1e-4, lr_probe=1e-5, lr_pos=0.0)
+    P0, O0, X0 = c.o_args()
+    ost = dict(probe=P0, object=O0, positions=X0)
+    oopt = dict(kind="sgd", lr_object=1e-4, lr_probe=1e-5, lr_pos=0.0, con=con)
+    for b in ([0, 7, 12, 20], list(range(1, 25, 2))):
+        loss = prob.reconstruct_step(st, d["pats"], torch.tensor(b, dtype=torch.int32, device="cuda"), opt)
+        prob.check()
+        ost, oloss = orc.reconstruct_step(ost, c.pats.astype(np.float64), b, c.geom, oopt)
+        assert abs(loss.item() - oloss) < 1e-4 * abs(oloss), (loss.item(), oloss)
+        for key, got in (("object", st.object), ("probe", st.probe)):
+            e = rel_l2(_np(got).astype(np.complex128), ost[key])
+            assert e < 1e-5, (key, e)
+    # the ramp is gone: the pair sums of every slice are real and positive
+    Og = _np(st.object).astype(np.complex128)
+    for Oi in Og:
+        z = np.sum(Oi[:, 1:] * np.conj(Oi[:, :-1]))
+        assert abs(np.angle(z)) < 1e-5
+
+
 @pytest.mark.parametrize("strategy", ["two_pass", "resident"])
 @pytest.mark.parametrize("name", ["n64_spoa_amp", "n64_ms_poisson", "n128_ms_poisson", "n128_tilt_mask_dz"])
 def test_both_strategies_match_oracle(cache, name, strategy):

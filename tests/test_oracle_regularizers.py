@@ -114,3 +114,70 @@ def test_reconstruct_step_adds_regularizer_gradient():
     assert abs(loss - (r["loss"] + c)) < 1e-12
     assert np.allclose(new["object"], O - 1e-3 * (r["g_object"] + gO))
     assert np.allclose(new["probe"], P - 1e-4 * (r["g_probe"] + gP))
+
+
+def test_object_lowpass_matches_scipy_and_fourier_modes():
+    """In-plane low pass: agrees with scipy.ndimage's periodic Gaussian filter
+    (the library routine for a sampled, normalised, truncated Gaussian), keeps
+    constants and the slice sums, and scales a Fourier mode by the closed-form
+    response sum_t w_t cos(2 pi k t / W)."""
+    from scipy import ndimage
+    rng = np.random.default_rng(5)
+    O = crandn(rng, 2, 11, 13)
+    for sigma in (0.7, 1.0, 2.3):
+        r = int(np.ceil(3 * sigma))
+        out = orc.lowpass_object(O, sigma)
+
+        def filt(a):
+            a = ndimage.gaussian_filter1d(a, sigma, axis=2, mode="wrap", truncate=r / sigma)
+            return ndimage.gaussian_filter1d(a, sigma, axis=1, mode="wrap", truncate=r / sigma)
+        ref = filt(O.real) + 1j * filt(O.imag)
+        assert np.max(np.abs(out - ref)) < 1e-12
+        assert np.allclose(out.sum(axis=(1, 2)), O.sum(axis=(1, 2)), atol=1e-12)
+        assert np.allclose(orc.lowpass_object(np.full((1, 5, 7), 2 - 1j), sigma), 2 - 1j)
+        H, W, ky, kx = 11, 13, 3, 5
+        y, x = np.mgrid[:H, :W]
+        mode = np.exp(2j * np.pi * (ky * y / H + kx * x / W))[None]
+        t = np.arange(-r, r + 1)
+        w = np.exp(-0.5 * (t / sigma) ** 2)
+        w /= w.sum()
+        lam = np.sum(w * np.cos(2 * np.pi * kx * t / W)) * np.sum(w * np.cos(2 * np.pi * ky * t / H))
+        assert np.max(np.abs(orc.lowpass_object(mode, sigma) - lam * mode)) < 1e-12
+
+
+def test_phase_deramp():
+    """Phase deramp: a pure affine phase is removed exactly (sign and axes),
+    the result is invariant to any added affine phase, deramping twice
+    changes nothing, and amplitudes are untouched."""
+    rng = np.random.default_rng(6)
+    S, H, W = 3, 9, 14
+    y, x = np.mgrid[:H, :W]
+    amp = 0.5 + rng.random((S, H, W))
+    c = rng.uniform(-1.0, 1.0, (S, 3))
+    ramp = np.exp(1j * (c[:, 0, None, None] + c[:, 1, None, None] * y + c[:, 2, None, None] * x))
+    pure = orc.deramp_object(1.7 * ramp)
+    assert np.max(np.abs(pure - 1.7)) < 1e-12
+    O = amp * np.exp(1j * 0.4 * rng.standard_normal((S, H, W)))
+    d = orc.deramp_object(O)
+    assert np.max(np.abs(orc.deramp_object(O * ramp) - d)) < 1e-10
+    assert np.max(np.abs(orc.deramp_object(d) - d)) < 1e-10
+    assert np.allclose(np.abs(d), amp)
+    # after deramping, the horizontal and vertical pair sums and the slice sum are real and positive
+    for di in d:
+        for z in (np.sum(di[:, 1:] * np.conj(di[:, :-1])), np.sum(di[1:] * np.conj(di[:-1])), np.sum(di)):
+            assert z.real > 0 and abs(z.imag) < 1e-9 * abs(z)
+
+
+def test_constraint_order():
+    """Constraints run as amplitude range, depth blur, low pass, deramp on the
+    object; the probe support acts on the probe alone."""
+    rng = np.random.default_rng(7)
+    O = (0.2 + 2 * rng.random((3, 8, 9))) * np.exp(1j * rng.random((3, 8, 9)))
+    P = crandn(rng, 1, 8, 8)
+    con = {"amp_min": 0.5, "amp_max": 1.5, "layer_sigma": 0.8, "obj_lowpass_sigma": 0.9, "phase_deramp": 1}
+    O2, P2 = orc.apply_constraints(O, P, con)
+    a = np.abs(O)
+    step = O * np.clip(a, 0.5, 1.5) / a
+    step = orc.apply_constraints(step, P, {"layer_sigma": 0.8})[0]
+    step = orc.deramp_object(orc.lowpass_object(step, 0.9))
+    assert np.max(np.abs(O2 - step)) < 1e-12 and np.array_equal(P2, P)
