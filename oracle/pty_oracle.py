@@ -333,6 +333,68 @@ def adam_update(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return _from_real(th, theta), m, v
 
 
+# --------------------------------------------------------------------------
+# Conventional engine: ePIE / 3PIE (Sec. 3.3)
+# --------------------------------------------------------------------------
+#
+# Readings of the section (its slice equations are garbled):
+# * the detector update is the generalized-amplitude one the section gives,
+#   chi_hat = (sqrt(Ie + c) / (eps + sqrt(I + c)) - 1) Psi_hat for every mode,
+#   with c = 3/8 for the Anscombe model and 0 otherwise, for every noise
+#   model (for amplitude, Poisson and Gaussian likelihoods the per-pixel
+#   minimiser along the gradient is this same modulus projection at eps = 0);
+#   chi_hat = 0 where eps + sqrt(I + c) = 0;
+# * the wave that multiplies conj(.) in the object update is the entry wave
+#   psi_i of slice i, and the update of the entry wave is carried to the exit
+#   wave of slice i - 1 by the adjoint propagator F^-1 conj(H) F;
+# * the normalisers are per position and slice: max over the window of
+#   sum_m |psi_i,m|^2 (mixed-state form) for the object, and max over the
+#   window of |O_i|^2 for the wave; a zero maximum gives a zero update;
+# * the group is evaluated at the current state (all positions in parallel),
+#   the object update is summed over positions and modes, the probe update
+#   (the entry-wave update of slice 0, shifted back by -delta_j) is averaged
+#   over the positions of the group; positions are not refined.
+
+def epie_update(probe, obj, positions, patterns, batch_idx, geom: Geometry):
+    """Summed ePIE updates of one group at the current state.
+
+    Returns dict(loss (noise-model loss of the current state), dO (sum over
+    positions and modes, shape of obj), dP (sum over positions, shape of
+    probe), a, b ([B][S] object and wave normalisers 1 / max)).
+    """
+    probe = np.asarray(probe, dtype=np.complex128)
+    obj = np.asarray(obj, dtype=np.complex128)
+    N = geom.N
+    S = obj.shape[0]
+    props = geom.props(S)
+    c = 0.375 if geom.loss == "anscombe" else 0.0
+    dO = np.zeros_like(obj)
+    dP_hat = np.zeros_like(probe)
+    A = np.zeros((len(batch_idx), S))
+    Bn = np.zeros((len(batch_idx), S))
+    loss = 0.0
+    for b, j in enumerate(batch_idx):
+        n, d = split_positions(positions[j])
+        psi, far, I = forward_position(probe, obj, positions[j], geom, props)
+        Ie = np.asarray(patterns[j], dtype=np.float64)
+        loss += float(loss_and_weight(I, Ie, geom.loss, geom.eps, geom.sigma)[0].sum())
+        den = geom.eps + np.sqrt(I + c)
+        factor = np.where(den > 0, np.sqrt(Ie + c) / np.where(den > 0, den, 1.0) - 1.0, 0.0)
+        chi = ifft2u(factor * far)                       # update of the last exit wave
+        for i in range(S - 1, -1, -1):
+            patch = obj[i, n[0]:n[0] + N, n[1]:n[1] + N]
+            mp = np.max(np.sum(np.abs(psi[i]) ** 2, axis=0))
+            mo = np.max(np.abs(patch) ** 2)
+            A[b, i] = 1.0 / mp if mp > 0 else 0.0
+            Bn[b, i] = 1.0 / mo if mo > 0 else 0.0
+            dO[i, n[0]:n[0] + N, n[1]:n[1] + N] += A[b, i] * np.sum(np.conj(psi[i]) * chi, axis=0)
+            dpsi = Bn[b, i] * np.conj(patch) * chi       # update of the entry wave psi_i
+            if i > 0:
+                chi = ifft2u(np.conj(props[i - 1]) * fft2u(dpsi))
+        dP_hat += fft2u(dpsi) * np.conj(shift_ramp(N, d))
+    return dict(loss=loss, dO=dO, dP=ifft2u(dP_hat), a=A, b=Bn)
+
+
 def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
     """One gradient step on one group (Sec. 2.2 engine loop, Sec. 3.2 solver).
 
@@ -343,8 +405,20 @@ def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
     con (constraints applied to the updated state)).
     Gradients of positions outside the group are zero; the update is applied
     to every element, as a dense optimiser on the whole variable does.
+    kind='epie' takes the ePIE step instead: object += lr_object * dO,
+    probe += lr_probe * dP / B (beta_object, beta_probe), positions kept,
+    no cost regularizers (they belong to the gradient engine), constraints
+    applied.
     Returns (new_state, loss).
     """
+    if opt["kind"] == "epie":
+        e = epie_update(state["probe"], state["object"], state["positions"], patterns, batch_idx, geom)
+        new = dict(state)
+        new["object"] = np.asarray(state["object"]) + opt["lr_object"] * e["dO"]
+        new["probe"] = np.asarray(state["probe"]) + opt["lr_probe"] / len(batch_idx) * e["dP"]
+        if opt.get("con"):
+            new["object"], new["probe"] = apply_constraints(new["object"], new["probe"], opt["con"])
+        return new, e["loss"]
     r = loss_and_grad(state["probe"], state["object"], state["positions"],
                       patterns, batch_idx, geom)
     g_pos = np.zeros_like(np.asarray(state["positions"], dtype=np.float64))
