@@ -205,7 +205,21 @@ typedef struct {
   int64_t step;
 } pty_state;
 
-typedef enum { PTY_OPT_SGD = 0, PTY_OPT_ADAM = 1 } pty_opt_kind;
+/* PTY_OPT_EPIE is the conventional ePIE / 3PIE engine (Sec. 3.3) rather than
+ * an optimiser: every position of the group is evaluated at the current
+ * state; at the detector chi = (sqrt(Ie + c) / (eps + sqrt(I + c)) - 1) Psi
+ * per mode (c = 3/8 for the Anscombe model, else 0; 0 where eps + sqrt(I + c)
+ * is 0); per slice i from the last down, dO_i += a conj(psi_i) chi (summed over
+ * modes) and the entry-wave update b conj(O_i) chi is carried back to slice
+ * i - 1 through F^-1 conj(H) F, with a = 1 / max over the window of
+ * sum_m |psi_i,m|^2 and b = 1 / max over the window of |O_i|^2 (0 when the
+ * maximum is 0); the slice-0 entry-wave update, shifted back by -delta_j,
+ * is the probe update. Then O += lr_object * sum dO (beta_object) and
+ * P += lr_probe * (sum dP) / B (beta_probe). Positions are not refined, the
+ * Adam fields and moments are ignored, cost regularizers do not apply, the
+ * constraints do. The loss written is the configured noise model's loss at
+ * the state before the step. */
+typedef enum { PTY_OPT_SGD = 0, PTY_OPT_ADAM = 1, PTY_OPT_EPIE = 2 } pty_opt_kind;
 
 typedef struct {
   int32_t kind;          /* pty_opt_kind */

@@ -15,7 +15,8 @@ PTY_OK, PTY_EINVAL, PTY_EBOUNDS, PTY_EUNSUPPORTED, PTY_ENOMEM, PTY_EHIP, PTY_ENO
 STATUS_NAMES = {0: "PTY_OK", 1: "PTY_EINVAL", 2: "PTY_EBOUNDS", 3: "PTY_EUNSUPPORTED", 4: "PTY_ENOMEM",
                 5: "PTY_EHIP", 6: "PTY_ENONFINITE", 7: "PTY_ESTATE"}
 LOSS_IDS = {"amplitude": 0, "anscombe": 1, "poisson": 2, "gaussian": 3}
-OPT_SGD, OPT_ADAM = 0, 1
+OPT_SGD, OPT_ADAM, OPT_EPIE = 0, 1, 2
+OPT_KINDS = {"sgd": OPT_SGD, "adam": OPT_ADAM, "epie": OPT_EPIE}
 STRATEGIES = {"auto": 0, "two_pass": 1, "resident": 2}
 PTY_ACCUMULATE = 1
 PTY_POS_DENSE = 2

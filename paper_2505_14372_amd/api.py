@@ -41,7 +41,9 @@ def _need(t, dtype, shape, name):
 
 @dataclass
 class Optimizer:
-    """SGD or Adam settings of pty_reconstruct_step (learning rate 0 freezes a variable)."""
+    """Settings of pty_reconstruct_step: 'sgd', 'adam' (learning rate 0 freezes a
+    variable) or 'epie', the conventional ePIE / 3PIE engine with
+    lr_object = beta_object and lr_probe = beta_probe (positions fixed)."""
     kind: str = "adam"
     lr_object: float = 1e-3
     lr_probe: float = 1e-3
@@ -51,7 +53,9 @@ class Optimizer:
     eps: float = 1e-8
 
     def c(self):
-        return _lib.Optim(_lib.OPT_ADAM if self.kind == "adam" else _lib.OPT_SGD, self.lr_object, self.lr_probe,
+        if self.kind not in _lib.OPT_KINDS:
+            raise ValueError(f"unknown optimiser {self.kind!r}")
+        return _lib.Optim(_lib.OPT_KINDS[self.kind], self.lr_object, self.lr_probe,
                           self.lr_pos, self.beta1, self.beta2, self.eps)
 
 

@@ -111,6 +111,7 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8) {
     b += align256((size_t)max_batch * 2 * g->N * sizeof(float2));
     b += align256((size_t)max_batch * nblk * sizeof(float));
     b += align256((size_t)max_batch * M * nblk * 2 * sizeof(float));
+    b += align256((size_t)max_batch * S * 2 * sizeof(float));          // ePIE window maxima
   }
   s.bytes = b;
   return s;
@@ -211,6 +212,7 @@ struct pty_ctx {
   int lowpass_r = 0;
   double* deramp = nullptr;        // device [S][3] angles, then [S][deramp_blocks][4] partial sums
   float* reg_part = nullptr;       // cost partial sums
+  float* emax = nullptr;           // ePIE window maxima [max_batch][S][2]
   // tape of pty_forward_save
   bool tape_valid = false;
   LaunchCtx tape{};
@@ -365,6 +367,7 @@ void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<
         st.mode = 0;
         st.src = L.ck;
         st.src_slot = i0 / k;
+        R.emax = 0;
         launch_rows_fwd(R, N, i0, st, true);
         for (int s = i0 + 1; s <= i1; ++s) {
           launch_col(R, N, COL_PROP, s - 1);
@@ -483,6 +486,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
     if ((st = dmalloc(&c->ws, c->sz.tiles * N2, e)) || (st = dmalloc(&c->ck, c->sz.ck_tiles * N2 * ck_elem, e)) ||
         (st = dmalloc(&c->seg, c->sz.seg_tiles * N2 * ck_elem, e)) || (st = dmalloc(&c->ws2, c->sz.ws2_tiles * N2, e)) ||
         (st = dmalloc(&c->items, (size_t)max_batch, e)) || (st = dmalloc(&c->ramps, (size_t)max_batch * 2 * N, e)) ||
+        (st = dmalloc(&c->emax, (size_t)max_batch * S * 2, e)) ||
         (st = dmalloc(&c->loss_part, (size_t)max_batch * nblk, e)) ||
         (st = dmalloc(&c->pos_part, (size_t)max_batch * M * nblk * 2, e)))
       return fail(st);
@@ -528,7 +532,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->tw); dfree(c->prop); dfree(c->phat); dfree(c->gphat); dfree(c->gprobe); dfree(c->gobj);
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
-  dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part);
+  dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax);
   delete c;
 }
 
@@ -690,7 +694,10 @@ void opt_update(hipStream_t s, const pty_optim* o, int64_t t, float* th, const f
 
 pty_status check_state(pty_ctx* c, const pty_state* st, const pty_optim* o) {
   if (!st || !o || !st->probe || !st->object || !st->positions) { c->err = "NULL state"; return PTY_EINVAL; }
-  if (o->kind != PTY_OPT_SGD && o->kind != PTY_OPT_ADAM) { c->err = "unknown optimiser"; return PTY_EINVAL; }
+  if (o->kind != PTY_OPT_SGD && o->kind != PTY_OPT_ADAM && o->kind != PTY_OPT_EPIE) {
+    c->err = "unknown optimiser";
+    return PTY_EINVAL;
+  }
   if (o->kind == PTY_OPT_ADAM) {
     if ((o->lr_object != 0 && (!st->m_object || !st->v_object)) || (o->lr_probe != 0 && (!st->m_probe || !st->v_probe)) ||
         (o->lr_pos != 0 && (!st->m_pos || !st->v_pos))) {
@@ -847,14 +854,36 @@ extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* 
   r.gobj = c->gobj;
   r.gpos_dense = c->gpos;
   r.gphat = c->gphat;
+  const bool epie = o->kind == PTY_OPT_EPIE;
+  if (epie) {
+    // ePIE / 3PIE: the same chain with the modulus update at the detector and
+    // per-(position, slice) normalisers recorded by the first forward pass
+    r.emax = c->emax;
+    r.modulus = 1;
+  }
   LaunchCtx L = ctx_launch(c, s, r, B);
+  if (epie) {
+    L.emax = 1;
+    L.resident = 0;
+  }
   {
     ProfScope p(P_FILL, s);
     launch_fill(s, (float*)c->gobj, (size_t)S * g.obj_h * g.obj_w * 2, 0.f);
     launch_fill(s, c->gpos, (size_t)g.n_positions * 2, 0.f);
+    if (epie) launch_fill(s, c->emax, (size_t)B * S * 2, 0.f);
   }
   run_fused(c, L, 1.f);
   { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, g.n_modes, true, 1.f / N, false); }
+  if (epie) {
+    // the chain produced minus the summed updates: O += beta_O dO, P += beta_P dP / B
+    ProfScope p(P_OPTIM, s);
+    const size_t nO = (size_t)S * g.obj_h * g.obj_w * 2, nP = (size_t)g.n_modes * N * N * 2;
+    if (o->lr_object != 0) launch_sgd(s, (float*)st->object, (const float*)c->gobj, nO, (float)o->lr_object);
+    if (o->lr_probe != 0) launch_sgd(s, (float*)st->probe, (const float*)c->gprobe, nP, (float)(o->lr_probe / B));
+    { ProfScope q(P_REG, s); apply_constraints(c, s, st); }
+    HIPCHECK(c, hipGetLastError());
+    return PTY_OK;
+  }
   { ProfScope p(P_REG, s); apply_cost_regularizers(c, s, st, loss); }
   apply_optimizer(c, s, st, o);
   { ProfScope p(P_REG, s); apply_constraints(c, s, st); }
@@ -958,6 +987,7 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
     if (!c || c->g.N != N) { G->err = "item context missing or of another N"; return PTY_EINVAL; }
     pty_status st0 = check_state(c, it.state, it.opt);
     if (st0 != PTY_OK) { G->err = c->err; return st0; }
+    if (it.opt->kind == PTY_OPT_EPIE) { G->err = "grouped steps take SGD or Adam"; return PTY_EUNSUPPORTED; }
     if (!it.patterns || !it.batch_idx || it.batch < 1) { G->err = "item needs patterns and a batch"; return PTY_EINVAL; }
     const int M = c->g.n_modes, S = c->g.n_slices;
     ReqDev r = base_req(c);

@@ -49,6 +49,8 @@ struct ReqDev {
   long long ck_base;        // first checkpoint tile of this request
   int ck_every, n_ck;       // checkpoint interval and stored slices per mode
   int accumulate;           // add into gpos instead of overwriting
+  float* emax;              // [n_items][S][2] window maxima of sum_m |psi_i|^2 and |O_i|^2 (ePIE) or null
+  int modulus;              // far-field weight: 0 loss gradient, 1 ePIE modulus update
 };
 
 struct ReqTable {
@@ -87,6 +89,7 @@ struct LaunchCtx {
   float* loss_part;         // [n_items][col blocks]
   float* pos_part;          // [tiles][col blocks][2] (tile = item tile0 + mode)
   int* flags;
+  int emax;                 // the first forward records the window maxima (ePIE)
 };
 
 void launch_items(const LaunchCtx& L, int N);

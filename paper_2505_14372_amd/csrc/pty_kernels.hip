@@ -134,8 +134,11 @@ __global__ void k_items(const ReqTable reqs, int n_reqs, Item* __restrict__ item
 // Slice step of the forward model, row part (slice i = step):
 //   psi = IDFT_x(tile row) ; [checkpoint psi] ; phi = psi * O_i ; tile row = DFT_x(phi)
 // With FROM_REAL the entry wave is read from a real-space buffer (the start
-// of a recomputed segment) instead of inverse-transforming the tile.
-template <int N, bool FROM_REAL, bool HALF>
+// of a recomputed segment) instead of inverse-transforming the tile. With
+// EMAX the maxima over the window of sum_m |psi_i,m|^2 and of |O_i|^2 are
+// max-accumulated into r.emax[item][i] (non-negative floats order like their
+// bit patterns, so an unsigned atomic max is exact).
+template <int N, bool FROM_REAL, bool HALF, bool EMAX = false>
 __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ items,
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, void* __restrict__ ck_,
@@ -161,6 +164,11 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 #pragma unroll
   for (int a = 0; a < E; ++a) o[a] = orow[l + L * a];
   const int n_ck = r.n_ck;
+  float pw[EMAX ? E : 1];
+  if constexpr (EMAX) {
+#pragma unroll
+    for (int a = 0; a < E; ++a) pw[a] = 0.f;
+  }
   for (int m = 0; m < r.M; ++m) {
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
@@ -182,12 +190,34 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 #pragma unroll
       for (int a = 0; a < E; ++a) Ck<HALF>::store(dst + l + L * a, v[a]);
     }
+    if constexpr (EMAX) {
+#pragma unroll
+      for (int a = 0; a < E; ++a) pw[a] += cabs2(v[a]);
+    }
     if (store.stop_after_store) continue;
 #pragma unroll
     for (int a = 0; a < E; ++a) v[a] = cmul(v[a], o[a]);
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
 #pragma unroll
     for (int a = 0; a < E; ++a) trow[l + L * a] = v[a];
+  }
+  if constexpr (EMAX) {
+    float mp = 0.f, mo = 0.f;
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      mp = fmaxf(mp, pw[a]);
+      mo = fmaxf(mo, cabs2(o[a]));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      mp = fmaxf(mp, __shfl_xor(mp, off));
+      mo = fmaxf(mo, __shfl_xor(mo, off));
+    }
+    if ((threadIdx.x & 63) == 0 && r.emax) {
+      unsigned* e = reinterpret_cast<unsigned*>(r.emax + ((size_t)(item_off + blockIdx.y - r.item0) * r.S + i) * 2);
+      atomicMax(e, __float_as_uint(mp));
+      atomicMax(e + 1, __float_as_uint(mo));
+    }
   }
 }
 
@@ -225,10 +255,17 @@ __global__ __launch_bounds__(kThreads) PTY_ROWADJ_ATTR void k_row_adj(const Item
   const CT* ck = static_cast<const CT*>(ck_);
   float2 acc[E];
   const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
+  // ePIE: object step divided by max sum_m |psi_i|^2, wave step by max |O_i|^2
+  float sa = 1.f, sb = 1.f;
+  if (r.emax) {
+    const float* e = r.emax + ((size_t)(item_off + blockIdx.y - r.item0) * r.S + i) * 2;
+    sa = e[0] > 0.f ? 1.f / e[0] : 0.f;
+    sb = e[1] > 0.f ? 1.f / e[1] : 0.f;
+  }
 #if !PTY_ROWADJ_RELOAD_O
   float2 o[E];
 #pragma unroll
-  for (int a = 0; a < E; ++a) o[a] = r.obj[orow + l + L * a];
+  for (int a = 0; a < E; ++a) o[a] = cscale(r.obj[orow + l + L * a], sb);
 #endif
 #pragma unroll
   for (int a = 0; a < E; ++a) acc[a] = make_float2(0.f, 0.f);
@@ -238,7 +275,7 @@ __global__ __launch_bounds__(kThreads) PTY_ROWADJ_ATTR void k_row_adj(const Item
     // instead of being held in registers across the mode loop
     float2 o[E];
 #pragma unroll
-    for (int a = 0; a < E; ++a) o[a] = r.obj[orow + l + L * a];
+    for (int a = 0; a < E; ++a) o[a] = cscale(r.obj[orow + l + L * a], sb);
 #endif
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
@@ -262,8 +299,8 @@ __global__ __launch_bounds__(kThreads) PTY_ROWADJ_ATTR void k_row_adj(const Item
     float* g = reinterpret_cast<float*>(r.gobj + orow);
 #pragma unroll
     for (int a = 0; a < E; ++a) {
-      unsafeAtomicAdd(g + 2 * (l + L * a), scale * acc[a].x);
-      unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * acc[a].y);
+      unsafeAtomicAdd(g + 2 * (l + L * a), scale * sa * acc[a].x);
+      unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * sa * acc[a].y);
     }
   }
 }
@@ -536,7 +573,15 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __
   for (int a = 0; a < E; ++a) {
     size_t p = (size_t)(l + L * a) * N + ux;
     float ell = 0.f, w = 0.f;
-    if (pat) loss_weight(r.loss, I[a], pat[p], r.eps, r.inv_sigma2, ell, w);
+    if (pat) {
+      loss_weight(r.loss, I[a], pat[p], r.eps, r.inv_sigma2, ell, w);
+      // ePIE: (1 - sqrt(Ie + c) / (eps + sqrt(I + c))) Psi is minus the modulus update
+      if (r.modulus) {
+        float ell_amp;
+        loss_weight(r.loss == PTY_LOSS_ANSCOMBE ? PTY_LOSS_ANSCOMBE : PTY_LOSS_AMPLITUDE, I[a], pat[p], r.eps,
+                    r.inv_sigma2, ell_amp, w);
+      }
+    }
     wgt[a] = w;
     lsum += ell;
     bad |= !isfinite(ell) || !isfinite(w);
@@ -690,6 +735,8 @@ struct Launch {
     dim3 g(Pass<N>::NBLK, L.n_items);
     if (from_real)
       hipLaunchKernelGGL((k_row_fwd<N, true, HALF>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
+    else if (L.emax)
+      hipLaunchKernelGGL((k_row_fwd<N, false, HALF, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
     else
       hipLaunchKernelGGL((k_row_fwd<N, false, HALF>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, st, L.item_off);
   }
