@@ -3,7 +3,7 @@ gradient iteration (forward model, noise-model loss, exact adjoint to object,
 probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 512]
-                    [--no-cpu-baseline] [--cpu-positions 8]
+                    [--no-cpu-baseline] [--cpu-positions 16]
 
 A step is one reconstruct_step over one group of `batch` positions drawn
 from a seeded permutation of the 128 x 128 scan (16384 positions = 32 groups
@@ -38,7 +38,7 @@ def parse():
     p.add_argument("--batch", type=int, default=0, help="positions per group (0: the workload's)")
     p.add_argument("--workload", default="cfg3_ms256")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-positions", type=int, default=8)
+    p.add_argument("--cpu-positions", type=int, default=16)
     p.add_argument("--checkpoint-every", type=int, default=1)
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--strategy", default="auto", choices=["auto", "two_pass", "resident"])

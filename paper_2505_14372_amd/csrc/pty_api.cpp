@@ -243,7 +243,7 @@ namespace {
 // LDS-resident chains: N <= 128 and every slice checkpointed.
 bool use_resident(int strategy, int N, int ck_every) {
   if (!resident_supported(N) || ck_every != 1) return false;
-  return strategy != PTY_STRATEGY_TWO_PASS;
+  return strategy == PTY_STRATEGY_RESIDENT;
 }
 
 ReqDev base_req(pty_ctx* c) {

@@ -48,9 +48,6 @@ __device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw_g
 #ifndef PTY_NT_CKPT
 #define PTY_NT_CKPT 0
 #endif
-#ifndef PTY_ROWADJ_RELOAD_O
-#define PTY_ROWADJ_RELOAD_O 0
-#endif
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // Entry-wave checkpoint storage: complex64 (float2) or two IEEE halves
@@ -225,16 +222,8 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 //   g = IDFT_x(tile row)                (gradient wrt phi_i, real space)
 //   grad O_i += sum_m conj(psi_i,m) g   (scatter-added into the object gradient)
 //   h = conj(O_i) g ; tile row = DFT_x(h)
-#ifndef PTY_ROWADJ_WAVES
-#define PTY_ROWADJ_WAVES 0
-#endif
-#if PTY_ROWADJ_WAVES
-#define PTY_ROWADJ_ATTR __attribute__((amdgpu_waves_per_eu(PTY_ROWADJ_WAVES, PTY_ROWADJ_WAVES)))
-#else
-#define PTY_ROWADJ_ATTR
-#endif
 template <int N, bool HALF>
-__global__ __launch_bounds__(kThreads) PTY_ROWADJ_ATTR void k_row_adj(const Item* __restrict__ items,
+__global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ items,
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, const void* __restrict__ ck_,
                                                       const float2* __restrict__ twg, int step,
@@ -262,21 +251,12 @@ __global__ __launch_bounds__(kThreads) PTY_ROWADJ_ATTR void k_row_adj(const Item
     sa = e[0] > 0.f ? 1.f / e[0] : 0.f;
     sb = e[1] > 0.f ? 1.f / e[1] : 0.f;
   }
-#if !PTY_ROWADJ_RELOAD_O
   float2 o[E];
 #pragma unroll
   for (int a = 0; a < E; ++a) o[a] = cscale(r.obj[orow + l + L * a], sb);
-#endif
 #pragma unroll
   for (int a = 0; a < E; ++a) acc[a] = make_float2(0.f, 0.f);
   for (int m = 0; m < r.M; ++m) {
-#if PTY_ROWADJ_RELOAD_O
-    // the object row is re-read for every mode (an L2 hit after the first)
-    // instead of being held in registers across the mode loop
-    float2 o[E];
-#pragma unroll
-    for (int a = 0; a < E; ++a) o[a] = cscale(r.obj[orow + l + L * a], sb);
-#endif
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
 #pragma unroll
@@ -348,30 +328,18 @@ template <int N> struct ColPass {
   static constexpr int NBLK = N / CB;
 };
 
-// Thread -> (column, lane) mapping of the column passes.
-// Block-wide (default): column c = t % CB, lane l = t / CB, so a load of
-// register a reads CB consecutive values of one row per lane group; a
-// column's lanes span several waves and exchange through LDS with block
-// barriers. Wave-local (PTY_COL_WAVE_LOCAL): each wave owns 64 / L whole
-// columns (column fastest within the wave), so the exchange needs no block
-// barrier; a load instruction then covers 64 / L consecutive values of L rows.
-#ifndef PTY_COL_WAVE_LOCAL
-#define PTY_COL_WAVE_LOCAL 0
-#endif
+// Thread -> (column, lane) mapping of the column passes: column c = t % CB,
+// lane l = t / CB, so a load of register a reads CB consecutive values of
+// one row per lane group; a column's lanes span several waves and exchange
+// through LDS with block barriers. (Keeping each column inside one wave, with
+// no block barrier, measured slower: the loads then cover 64 / L values per
+// row.)
 template <int N> struct ColMap {
-  static constexpr int L = Cfg<N>::L, CB = ColPass<N>::CB, CPW = 64 / L;
-#if PTY_COL_WAVE_LOCAL
-  // exchange stride per column: searched for two bank cycles per access
-  static constexpr int STRIDE = N == 64 ? 72 : N == 128 ? 148 : N == 192 ? 216 : 272;
-  __device__ __forceinline__ static int col() { return (threadIdx.x >> 6) * CPW + (threadIdx.x & 63) % CPW; }
-  __device__ __forceinline__ static int lane() { return (threadIdx.x & 63) / CPW; }
-  using Sync = WaveSync;
-#else
+  static constexpr int CB = ColPass<N>::CB;
   static constexpr int STRIDE = Xch<N>::COL_STRIDE;
   __device__ __forceinline__ static int col() { return threadIdx.x % CB; }
   __device__ __forceinline__ static int lane() { return threadIdx.x / CB; }
   using Sync = BlockSync;
-#endif
 };
 
 // Column passes over (item, mode) tiles:
