@@ -395,6 +395,99 @@ def epie_update(probe, obj, positions, patterns, batch_idx, geom: Geometry):
     return dict(loss=loss, dO=dO, dP=ifft2u(dP_hat), a=A, b=Bn)
 
 
+# --------------------------------------------------------------------------
+# Conventional engine: LSQML (Sec. 3.3)
+# --------------------------------------------------------------------------
+#
+# Readings of the section:
+# * detector update chi_hat as for ePIE above; no normalisers in the chain:
+#   the illumination update direction conj(O_i) chi_i is carried to slice
+#   i - 1 by F^-1 conj(H) F;
+# * object, per slice i: the direction summed over the group and the modes,
+#   D_i = sum_j sum_m chi_i,m conj(psi_i,m) (scattered into object
+#   coordinates), normalised by the illumination sum A_i:
+#   dO_hat_i = D_i / (A_i + delta_O);
+# * the step is computed per group (one per slice), the least-squares fit of
+#   dO_hat_i psi to chi over the group:
+#   alpha_i = Re <dO_hat_i, D_i> / (<|dO_hat_i|^2, W_i> + gamma) with
+#   W_i = sum_j sum_m |psi_i,m|^2 (scattered), so the section's
+#   illumination-weighted average of the steps over the group is alpha_i
+#   itself: O_i += beta_O alpha_i dO_hat_i;
+# * probe, at slice 0: the direction is the entry-wave update conj(O_0) chi_0
+#   shifted back by -delta_j, summed over the group, per mode: dP_m;
+#   dP_hat_m = dP_m / (B + delta_P); the illumination of the probe is the
+#   object's transparency T_j = prod_i |O_i|^2 over window j (probe view,
+#   integer window offset), so alpha_P = Re sum_m <dP_hat_m, dP_m> /
+#   (sum_m <|dP_hat_m|^2, sum_j T_j> + gamma) and P += beta_P alpha_P dP_hat;
+# * A (object view, per slice) and B (probe view) are illumination sums over
+#   a whole iteration: a step uses the previous iteration's sums and adds its
+#   own group's W_i and sum_j T_j to the running sums of the current
+#   iteration; in the first iteration, which has no previous sums, the
+#   running sums (this group included) are used;
+# * positions are not refined; the loss reported is the noise model's at the
+#   state before the step.
+
+def lsqml_step(state, illum, patterns, batch_idx, geom: Geometry, beta_object=1.0, beta_probe=1.0,
+               delta_object=1e-3, delta_probe=1e-3, gamma=0.0):
+    """One LSQML group step.
+
+    illum: dict(obj_prev [S][H][W], obj_cur [S][H][W], probe_prev [N][N],
+    probe_cur [N][N], first (bool)); the *_cur sums are updated in place.
+    Returns (new_state, loss, info) with info = dict(alpha [S], alpha_probe).
+    """
+    P = np.asarray(state["probe"], dtype=np.complex128)
+    O = np.asarray(state["object"], dtype=np.complex128)
+    X = state["positions"]
+    N = geom.N
+    S = O.shape[0]
+    props = geom.props(S)
+    c = 0.375 if geom.loss == "anscombe" else 0.0
+    D = np.zeros_like(O)
+    W = np.zeros(O.shape)
+    dP_hat_spec = np.zeros_like(P)
+    T_sum = np.zeros((N, N))
+    loss = 0.0
+    for j in batch_idx:
+        n, d = split_positions(X[j])
+        win = (slice(n[0], n[0] + N), slice(n[1], n[1] + N))
+        psi, far, I = forward_position(P, O, X[j], geom, props)
+        Ie = np.asarray(patterns[j], dtype=np.float64)
+        loss += float(loss_and_weight(I, Ie, geom.loss, geom.eps, geom.sigma)[0].sum())
+        den = geom.eps + np.sqrt(I + c)
+        factor = np.where(den > 0, np.sqrt(Ie + c) / np.where(den > 0, den, 1.0) - 1.0, 0.0)
+        chi = ifft2u(factor * far)                       # update of the last exit wave
+        T = np.ones((N, N))
+        for i in range(S):
+            T = T * np.abs(O[i][win]) ** 2
+        T_sum += T
+        for i in range(S - 1, -1, -1):
+            D[i][win] += np.sum(chi * np.conj(psi[i]), axis=0)
+            W[i][win] += np.sum(np.abs(psi[i]) ** 2, axis=0)
+            dpsi = chi * np.conj(O[i][win])              # update of the entry wave psi_i
+            if i > 0:
+                chi = ifft2u(np.conj(props[i - 1]) * fft2u(dpsi))
+        dP_hat_spec += fft2u(dpsi) * np.conj(shift_ramp(N, d))
+    illum["obj_cur"] += W
+    illum["probe_cur"] += T_sum
+    A = illum["obj_cur"] if illum["first"] else illum["obj_prev"]
+    Bp = illum["probe_cur"] if illum["first"] else illum["probe_prev"]
+    new = dict(state)
+    dO_hat = D / (A + delta_object)
+    alpha = np.zeros(S)
+    for i in range(S):
+        num = np.real(np.vdot(dO_hat[i], D[i]))
+        den = np.sum(np.abs(dO_hat[i]) ** 2 * W[i]) + gamma
+        alpha[i] = num / den if den > 0 else 0.0
+    new["object"] = O + beta_object * alpha[:, None, None] * dO_hat
+    dP = ifft2u(dP_hat_spec)
+    dP_hat = dP / (Bp + delta_probe)
+    num = np.real(np.vdot(dP_hat, dP))
+    den = np.sum(np.abs(dP_hat) ** 2 * T_sum[None]) + gamma
+    alpha_p = num / den if den > 0 else 0.0
+    new["probe"] = P + beta_probe * alpha_p * dP_hat
+    return new, loss, dict(alpha=alpha, alpha_probe=alpha_p)
+
+
 def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
     """One gradient step on one group (Sec. 2.2 engine loop, Sec. 3.2 solver).
 
