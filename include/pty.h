@@ -73,7 +73,8 @@ typedef enum {
   PTY_ENOMEM = 4,        /* device allocation failed at create */
   PTY_EHIP = 5,          /* a HIP runtime call failed */
   PTY_ENONFINITE = 6,    /* non-finite loss or detector weight (device flag) */
-  PTY_ESTATE = 7         /* pty_backward without a preceding pty_forward_save */
+  PTY_ESTATE = 7         /* pty_backward without a preceding pty_forward_save; pty_lsqml_step
+                            on a context created without its scratch */
 } pty_status;
 
 /* Noise models of Sec. 3.1. */
@@ -127,6 +128,8 @@ typedef struct {
   int32_t checkpoint_half;   /* 1: store entry-wave checkpoints as pairs of IEEE
                                 half floats (round to nearest), halving their HBM
                                 traffic; only the object gradient reads them */
+  int32_t lsqml;             /* 1: also allocate the scratch of pty_lsqml_step
+                                (S*H*W + 33*N*N floats and a few sums) */
 } pty_options;
 
 /* pty_create with the options above; pty_create(g, b, k, budget, out) equals
@@ -271,6 +274,49 @@ pty_status pty_set_regularizers(pty_ctx* ctx, const pty_regularizers* reg);
 pty_status pty_reconstruct_step(pty_ctx* ctx, void* stream, pty_state* st, const float* patterns,
                                 const int32_t* batch_idx, int32_t batch, const pty_optim* opt,
                                 double* loss);
+
+/* LSQML engine (Sec. 3.3). Illumination sums over an iteration, caller-owned
+ * float device arrays: obj_* [S][H][W] (object view, sum over positions and
+ * modes of |psi_i|^2 per slice), probe_* [N][N] (probe view, sum over
+ * positions of prod_i |O_i|^2 over the window). A step reads the *_prev sums
+ * of the previous iteration, or, when both *_prev are NULL (the first
+ * iteration), the *_cur sums with its own group included; it always adds its
+ * group's sums to *_cur. At the end of an iteration the caller moves *_cur to
+ * *_prev and zeroes *_cur. */
+typedef struct {
+  const float* obj_prev;
+  float* obj_cur;
+  const float* probe_prev;
+  float* probe_cur;
+} pty_illum;
+
+typedef struct {
+  double beta_object, beta_probe;   /* step scales (0 freezes) */
+  double delta_object, delta_probe; /* added to the illumination sums (> 0) */
+  double gamma;                     /* added to the step-size denominators (>= 0) */
+} pty_lsqml;
+
+/* One LSQML step on one group, every position at the current state. At the
+ * detector chi = (sqrt(Ie + c) / (eps + sqrt(I + c)) - 1) Psi per mode (as for
+ * PTY_OPT_EPIE); per slice i from the last the entry-wave update conj(O_i) chi_i
+ * is carried to slice i - 1 by F^-1 conj(H) F (no normalisers). With
+ * D_i = sum_j sum_m chi_i conj(psi_i) and W_i = sum_j sum_m |psi_i|^2 scattered
+ * into object coordinates, A_i the object-view illumination sum:
+ *   dO_i = D_i / (A_i + delta_object),
+ *   alpha_i = Re <dO_i, D_i> / (<|dO_i|^2, W_i> + gamma)   (0 if that is 0),
+ *   O_i += beta_object alpha_i dO_i.
+ * Probe: dP_m = sum_j (slice-0 entry-wave update shifted back by -delta_j),
+ * T = sum_j prod_i |O_i|^2 over window j, Bp the probe-view sum:
+ *   dP'_m = dP_m / (Bp + delta_probe),
+ *   alpha_P = Re sum_m <dP'_m, dP_m> / (sum_m <|dP'_m|^2, T> + gamma),
+ *   P += beta_probe alpha_P dP'.
+ * Positions are kept; the constraints of pty_set_regularizers apply, the cost
+ * regularizers do not; the loss written is the noise model's at the state
+ * before the step. Needs a context created with pty_options.lsqml = 1
+ * (PTY_ESTATE otherwise); always runs the two-pass kernels. */
+pty_status pty_lsqml_step(pty_ctx* ctx, void* stream, pty_state* st, const pty_illum* illum,
+                          const float* patterns, const int32_t* batch_idx, int32_t batch,
+                          const pty_lsqml* opt, double* loss);
 
 /* Synchronise the stream, return PTY_EBOUNDS / PTY_ENONFINITE if a device
  * flag was raised since the last check (then clear it), else PTY_OK. */

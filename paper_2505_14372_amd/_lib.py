@@ -28,7 +28,7 @@ EXPORTS = (
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
-    "pty_set_regularizers", "pty_set_strategy",
+    "pty_set_regularizers", "pty_set_strategy", "pty_lsqml_step",
 )
 
 
@@ -44,7 +44,7 @@ class Geometry(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("max_batch", C.c_int32), ("checkpoint_every", C.c_int32), ("hbm_budget", C.c_size_t),
-                ("checkpoint_half", C.c_int32)]
+                ("checkpoint_half", C.c_int32), ("lsqml", C.c_int32)]
 
 
 class Regularizers(C.Structure):
@@ -53,6 +53,16 @@ class Regularizers(C.Structure):
                 ("layers_tv", C.c_double), ("tv_delta", C.c_double), ("amp_clamp", C.c_int32),
                 ("amp_min", C.c_double), ("amp_max", C.c_double), ("probe_support", C.POINTER(C.c_uint8)),
                 ("layer_sigma", C.c_double), ("obj_lowpass_sigma", C.c_double), ("phase_deramp", C.c_int32)]
+
+
+class Illum(C.Structure):
+    _fields_ = [("obj_prev", C.c_void_p), ("obj_cur", C.c_void_p), ("probe_prev", C.c_void_p),
+                ("probe_cur", C.c_void_p)]
+
+
+class Lsqml(C.Structure):
+    _fields_ = [("beta_object", C.c_double), ("beta_probe", C.c_double), ("delta_object", C.c_double),
+                ("delta_probe", C.c_double), ("gamma", C.c_double)]
 
 
 class State(C.Structure):
@@ -115,6 +125,7 @@ def load():
         "pty_profile_enable": ([i32], None),
         "pty_set_regularizers": ([vp, C.POINTER(Regularizers)], i32),
         "pty_set_strategy": ([vp, i32], i32),
+        "pty_lsqml_step": ([vp, vp, C.POINTER(State), C.POINTER(Illum), vp, vp, i32, C.POINTER(Lsqml), vp], i32),
         "pty_profile_collect": ([C.c_char_p, sz, C.POINTER(f64), C.POINTER(i64), i32], i32),
     }
     for name, (args, res) in sig.items():

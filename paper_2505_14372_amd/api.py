@@ -106,12 +106,13 @@ def _geometry(N, M, S, H, W, J, dx, wavelength, dz, bandlimit, loss, eps, sigma,
 
 
 def workspace_bytes(N, M, S, H, W, J, max_batch, checkpoint_every=1, dx=0.2, wavelength=0.019688,
-                    dz=None, bandlimit=2 / 3, loss="poisson", eps=0.0, sigma=1.0, checkpoint_half=False):
+                    dz=None, bandlimit=2 / 3, loss="poisson", eps=0.0, sigma=1.0, checkpoint_half=False,
+                    lsqml=False):
     lib = _lib.load()
     g, _keep = _geometry(N, M, S, H, W, J, dx, wavelength, dz if dz is not None else [1.0] * (S - 1),
                          bandlimit, loss, eps, sigma)
     out = C.c_size_t()
-    opt = _lib.Options(max_batch, checkpoint_every, 0, 1 if checkpoint_half else 0)
+    opt = _lib.Options(max_batch, checkpoint_every, 0, 1 if checkpoint_half else 0, 1 if lsqml else 0)
     st = lib.pty_workspace_bytes_ex(C.byref(g), C.byref(opt), C.byref(out))
     if st:
         raise PtyError(st, "pty_workspace_bytes")
@@ -125,7 +126,7 @@ class Problem:
                  dx: float = 0.2, wavelength: float = 0.019688, bandlimit: float = 2 / 3,
                  loss: str = "poisson", eps: float = 0.0, sigma: float = 1.0, max_batch: int = 256,
                  checkpoint_every: int = 1, hbm_budget: int = 0, checkpoint_half: bool = False,
-                 tilt=(0.0, 0.0), bandlimit_mask=None):
+                 tilt=(0.0, 0.0), bandlimit_mask=None, lsqml: bool = False):
         self.lib = _lib.load()
         self.N, self.M, self.S, self.H, self.W, self.J = N, M, S, H, W, J
         self.loss_kind = loss
@@ -134,7 +135,7 @@ class Problem:
                                      bandlimit_mask)
         self._g = g
         ctx = C.c_void_p()
-        opt = _lib.Options(max_batch, checkpoint_every, hbm_budget, 1 if checkpoint_half else 0)
+        opt = _lib.Options(max_batch, checkpoint_every, hbm_budget, 1 if checkpoint_half else 0, 1 if lsqml else 0)
         st = self.lib.pty_create_ex(C.byref(g), C.byref(opt), C.byref(ctx))
         if st:
             raise PtyError(st, "pty_create")
@@ -263,11 +264,56 @@ class Problem:
         state.step = cs.step
         return loss
 
+    def lsqml_step(self, state: ReconState, illum: "IllumSums", patterns, batch_idx, beta_object=1.0,
+                   beta_probe=1.0, delta_object=1e-3, delta_probe=1e-3, gamma=0.0, loss=None):
+        """One LSQML group step (pty_lsqml_step); needs Problem(..., lsqml=True)."""
+        B = self._check_inputs(state.probe, state.object, state.positions, batch_idx, patterns)
+        for t, shape, name in ((illum.obj_cur, (self.S, self.H, self.W), "obj_cur"),
+                               (illum.obj_prev, (self.S, self.H, self.W), "obj_prev"),
+                               (illum.probe_cur, (self.N, self.N), "probe_cur"),
+                               (illum.probe_prev, (self.N, self.N), "probe_prev")):
+            if t is not None or name.endswith("cur"):
+                _need(t, torch.float32, shape, name)
+                if not t.is_contiguous():
+                    raise ValueError(f"{name} must be contiguous")
+        if loss is None:
+            loss = torch.zeros(1, dtype=torch.float64, device=state.probe.device)
+        cs = state.c()
+        co = _lib.Lsqml(beta_object, beta_probe, delta_object, delta_probe, gamma)
+        ci = illum.c()
+        st = self.lib.pty_lsqml_step(self.ctx, _stream(), C.byref(cs), C.byref(ci), _ptr(patterns), _ptr(batch_idx),
+                                     B, C.byref(co), _ptr(loss))
+        if st:
+            self._err(st, "pty_lsqml_step")
+        return loss
+
     def check(self):
         """Synchronise and raise on a device-side flag (window out of bounds, non-finite loss)."""
         st = self.lib.pty_check(self.ctx, _stream())
         if st:
             self._err(st, "pty_check")
+
+
+class IllumSums:
+    """Illumination sums of the LSQML engine over an iteration (object view
+    [S][H][W], probe view [N][N]): the running sums of the current iteration
+    and, after the first, those of the previous one."""
+
+    def __init__(self, S: int, H: int, W: int, N: int, device="cuda"):
+        f = dict(dtype=torch.float32, device=device)
+        self.obj_cur = torch.zeros((S, H, W), **f)
+        self.probe_cur = torch.zeros((N, N), **f)
+        self.obj_prev = None
+        self.probe_prev = None
+
+    def end_iteration(self):
+        """The running sums become the previous iteration's; new running sums start at zero."""
+        self.obj_prev, self.probe_prev = self.obj_cur, self.probe_cur
+        self.obj_cur = torch.zeros_like(self.obj_prev)
+        self.probe_cur = torch.zeros_like(self.probe_prev)
+
+    def c(self):
+        return _lib.Illum(_ptr(self.obj_prev), _ptr(self.obj_cur), _ptr(self.probe_prev), _ptr(self.probe_cur))
 
 
 class Group:

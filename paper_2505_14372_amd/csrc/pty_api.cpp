@@ -87,7 +87,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Device bytes of one context (fixed part + batch workspace); checkpoints and
 // segment buffers hold ck_elem bytes per complex value.
-Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8) {
+Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8, bool lsqml = false) {
   Sizes s;
   const size_t N2 = (size_t)g->N * g->N;
   const int S = g->n_slices, M = g->n_modes;
@@ -112,6 +112,12 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8) {
     b += align256((size_t)max_batch * nblk * sizeof(float));
     b += align256((size_t)max_batch * M * nblk * 2 * sizeof(float));
     b += align256((size_t)max_batch * S * 2 * sizeof(float));          // ePIE window maxima
+  }
+  if (lsqml) {
+    const size_t HW = (size_t)g->obj_h * g->obj_w;
+    b += align256((size_t)S * HW * sizeof(float));                     // illumination scatter
+    b += align256((size_t)(kLsqSplit + 1) * N2 * sizeof(float));       // transparency partials + sum
+    b += align256(((size_t)S * lsq_blocks(HW) * 2 + S + 1) * sizeof(double));
   }
   s.bytes = b;
   return s;
@@ -213,6 +219,12 @@ struct pty_ctx {
   double* deramp = nullptr;        // device [S][3] angles, then [S][deramp_blocks][4] partial sums
   float* reg_part = nullptr;       // cost partial sums
   float* emax = nullptr;           // ePIE window maxima [max_batch][S][2]
+  // LSQML scratch (pty_options.lsqml): illumination scatter [S][H][W],
+  // transparency partials [kLsqSplit][N][N] and sum [N][N], step sums
+  float* lsq_w = nullptr;
+  float* lsq_part = nullptr;
+  float* lsq_wp = nullptr;
+  double* lsq_sums = nullptr;
   // tape of pty_forward_save
   bool tape_valid = false;
   LaunchCtx tape{};
@@ -457,7 +469,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   if (k == 0) {
     k = 1;
     if (hbm_budget > 0) {
-      while (k <= S && ctx_sizes(g, max_batch, k, ck_elem).bytes > hbm_budget) ++k;
+      while (k <= S && ctx_sizes(g, max_batch, k, ck_elem, o->lsqml != 0).bytes > hbm_budget) ++k;
       if (k > S) return PTY_ENOMEM;
     }
   }
@@ -470,7 +482,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   c->ck_every = k;
   c->n_ck = (S + k - 1) / k;
   c->ck_half = o->checkpoint_half ? 1 : 0;
-  c->sz = ctx_sizes(g, max_batch, k, ck_elem);
+  c->sz = ctx_sizes(g, max_batch, k, ck_elem, o->lsqml != 0);
   const int N = g->N, M = g->n_modes;
   const size_t N2 = (size_t)N * N;
   std::string& e = c->err;
@@ -481,6 +493,13 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
       (st = dmalloc(&c->gobj, (size_t)S * g->obj_h * g->obj_w, e)) ||
       (st = dmalloc(&c->gpos, (size_t)g->n_positions * 2, e)) || (st = dmalloc(&c->flags, 4, e)))
     return fail(st);
+  if (o->lsqml) {
+    const size_t HW = (size_t)g->obj_h * g->obj_w;
+    if ((st = dmalloc(&c->lsq_w, (size_t)S * HW, e)) || (st = dmalloc(&c->lsq_part, (size_t)kLsqSplit * N2, e)) ||
+        (st = dmalloc(&c->lsq_wp, N2, e)) ||
+        (st = dmalloc(&c->lsq_sums, (size_t)S * lsq_blocks(HW) * 2 + S + 1, e)))
+      return fail(st);
+  }
   if (max_batch > 0) {
     const int nblk = col_blocks(N);
     if ((st = dmalloc(&c->ws, c->sz.tiles * N2, e)) || (st = dmalloc(&c->ck, c->sz.ck_tiles * N2 * ck_elem, e)) ||
@@ -513,6 +532,7 @@ pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoi
   o.checkpoint_every = checkpoint_every;
   o.hbm_budget = hbm_budget;
   o.checkpoint_half = 0;
+  o.lsqml = 0;
   return pty_create_ex(g, &o, out);
 }
 
@@ -521,7 +541,8 @@ pty_status pty_workspace_bytes_ex(const pty_geometry* g, const pty_options* o, s
   pty_status st = validate_geometry(g, err);
   if (st != PTY_OK) return st;
   if (!bytes || !o || o->max_batch < 0 || o->checkpoint_every < 1) return PTY_EINVAL;
-  *bytes = ctx_sizes(g, o->max_batch, std::min<int>(o->checkpoint_every, g->n_slices), o->checkpoint_half ? 4 : 8).bytes;
+  *bytes = ctx_sizes(g, o->max_batch, std::min<int>(o->checkpoint_every, g->n_slices), o->checkpoint_half ? 4 : 8,
+                     o->lsqml != 0).bytes;
   return PTY_OK;
 }
 
@@ -533,6 +554,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
   dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax);
+  dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums);
   delete c;
 }
 
@@ -886,6 +908,68 @@ extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* 
   }
   { ProfScope p(P_REG, s); apply_cost_regularizers(c, s, st, loss); }
   apply_optimizer(c, s, st, o);
+  { ProfScope p(P_REG, s); apply_constraints(c, s, st); }
+  HIPCHECK(c, hipGetLastError());
+  return PTY_OK;
+}
+
+extern "C" pty_status pty_lsqml_step(pty_ctx* c, void* stream, pty_state* st, const pty_illum* il,
+                                     const float* patterns, const int32_t* batch_idx, int32_t B, const pty_lsqml* o,
+                                     double* loss) {
+  if (!c) return PTY_EINVAL;
+  if (!st || !il || !o || !st->probe || !st->object || !st->positions) { c->err = "NULL argument"; return PTY_EINVAL; }
+  if (!c->lsq_w) { c->err = "context created without the LSQML scratch (pty_options.lsqml = 0)"; return PTY_ESTATE; }
+  if (!il->obj_cur || !il->probe_cur || (il->obj_prev == nullptr) != (il->probe_prev == nullptr)) {
+    c->err = "illumination sums: obj_cur and probe_cur are required, obj_prev and probe_prev both or neither";
+    return PTY_EINVAL;
+  }
+  const float dO = (float)o->delta_object, dP = (float)o->delta_probe;
+  if (!std::isfinite(o->beta_object) || !std::isfinite(o->beta_probe) || !(dO > 0.f) || !(dP > 0.f) ||
+      !std::isfinite(o->delta_object) || !std::isfinite(o->delta_probe) || !(o->gamma >= 0.0) ||
+      !std::isfinite(o->gamma)) {
+    c->err = "LSQML needs finite betas, deltas > 0 (in float) and gamma >= 0";
+    return PTY_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  pty_status s0 = check_call(c, st->probe, st->object, st->positions, batch_idx, B);
+  if (s0 != PTY_OK) return s0;
+  if (!patterns) { c->err = "patterns are required"; return PTY_EINVAL; }
+  c->tape_valid = false;
+  const pty_geometry& g = c->g;
+  const int N = g.N, S = g.n_slices, M = g.n_modes;
+  const size_t HW = (size_t)g.obj_h * g.obj_w;
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, (const float2*)st->probe, c->phat, M, false, 1.f / N, false); }
+  ReqDev r = base_req(c);
+  r.obj = (const float2*)st->object;
+  r.positions = st->positions;
+  r.batch_idx = batch_idx;
+  r.patterns = patterns;
+  r.loss_out = loss;
+  r.gobj = c->gobj;
+  r.gpos_dense = c->gpos;
+  r.gphat = c->gphat;
+  r.modulus = 1;
+  r.wsum = c->lsq_w;
+  LaunchCtx L = ctx_launch(c, s, r, B);
+  L.resident = 0;
+  L.wsum = 1;
+  {
+    ProfScope p(P_FILL, s);
+    launch_fill(s, (float*)c->gobj, (size_t)S * HW * 2, 0.f);
+    launch_fill(s, c->gpos, (size_t)g.n_positions * 2, 0.f);
+    launch_fill(s, c->lsq_w, (size_t)S * HW, 0.f);
+  }
+  // the chain accumulates minus the summed directions: gobj = -D, gphat -> gprobe = -dP
+  run_fused(c, L, 1.f);
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, M, true, 1.f / N, false); }
+  {
+    ProfScope p(P_OPTIM, s);
+    launch_lsq_transparency(s, c->items, B, (const float2*)st->object, S, g.obj_h, g.obj_w, N, c->lsq_part, c->lsq_wp);
+    launch_lsq_object(s, (float2*)st->object, c->gobj, c->lsq_w, il->obj_cur, il->obj_prev, S, HW, dO, o->gamma,
+                      (float)o->beta_object, c->lsq_sums, c->lsq_sums + (size_t)S * lsq_blocks(HW) * 2);
+    launch_lsq_probe(s, (float2*)st->probe, c->gprobe, c->lsq_wp, il->probe_cur, il->probe_prev, M, N * N, dP,
+                     o->gamma, (float)o->beta_probe, c->lsq_sums + (size_t)S * lsq_blocks(HW) * 2 + S);
+  }
   { ProfScope p(P_REG, s); apply_constraints(c, s, st); }
   HIPCHECK(c, hipGetLastError());
   return PTY_OK;

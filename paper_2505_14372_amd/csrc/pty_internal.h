@@ -50,7 +50,8 @@ struct ReqDev {
   int ck_every, n_ck;       // checkpoint interval and stored slices per mode
   int accumulate;           // add into gpos instead of overwriting
   float* emax;              // [n_items][S][2] window maxima of sum_m |psi_i|^2 and |O_i|^2 (ePIE) or null
-  int modulus;              // far-field weight: 0 loss gradient, 1 ePIE modulus update
+  int modulus;              // far-field weight: 0 loss gradient, 1 modulus update (ePIE, LSQML)
+  float* wsum;              // [S][H][W] scatter of sum_m |psi_i|^2 (LSQML) or null
 };
 
 struct ReqTable {
@@ -90,6 +91,7 @@ struct LaunchCtx {
   float* pos_part;          // [tiles][col blocks][2] (tile = item tile0 + mode)
   int* flags;
   int emax;                 // the first forward records the window maxima (ePIE)
+  int wsum;                 // the adjoint row pass scatters the illumination (LSQML)
 };
 
 void launch_items(const LaunchCtx& L, int N);
@@ -129,6 +131,23 @@ void launch_lowpass(hipStream_t s, float2* O, float2* tmp, int S, int H, int W, 
 int deramp_blocks(int H, int W);
 // Affine phase removal per slice; theta: S * 3 doubles, part: see deramp_blocks.
 void launch_deramp(hipStream_t s, float2* O, int S, int H, int W, double* theta, double* part);
+
+// LSQML (Sec. 3.3) after the adjoint chain. Transparency sum over the group's
+// valid items (first n_items of items): wp[r] = sum_j prod_i |O_i(n_j + r)|^2,
+// part holds kLsqSplit * N * N floats.
+constexpr int kLsqSplit = 32;
+void launch_lsq_transparency(hipStream_t s, const Item* items, int n_items, const float2* O, int S, int H,
+                             int W, int N, float* part, float* wp);
+// Object step: D = -g (g the chain's object accumulator), A = prev or cur + w,
+// alpha_i from double sums (part: S * lsq_blocks(H * W) * 2 doubles, alpha: S
+// doubles), O -= beta alpha_i g / (A + delta), cur += w.
+int lsq_blocks(size_t n);
+void launch_lsq_object(hipStream_t s, float2* O, const float2* g, const float* w, float* cur, const float* prev,
+                       int S, size_t HW, float delta, double gamma, float beta, double* part, double* alpha);
+// Probe step, likewise with the probe accumulator g [M][N][N], the
+// transparency sum wp [N][N] and one alpha.
+void launch_lsq_probe(hipStream_t s, float2* P, const float2* g, const float* wp, float* cur, const float* prev,
+                      int M, int N2, float delta, double gamma, float beta, double* alpha);
 
 // LDS-resident forward / adjoint chains (N = 64, 128; every slice checkpointed)
 bool resident_supported(int N);

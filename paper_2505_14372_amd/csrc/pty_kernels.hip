@@ -222,7 +222,9 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 //   g = IDFT_x(tile row)                (gradient wrt phi_i, real space)
 //   grad O_i += sum_m conj(psi_i,m) g   (scatter-added into the object gradient)
 //   h = conj(O_i) g ; tile row = DFT_x(h)
-template <int N, bool HALF>
+// With WSUM the illumination sum_m |psi_i,m|^2 of the window is also scattered
+// into r.wsum (LSQML).
+template <int N, bool HALF, bool WSUM = false>
 __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ items,
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, const void* __restrict__ ck_,
@@ -256,6 +258,11 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   for (int a = 0; a < E; ++a) o[a] = cscale(r.obj[orow + l + L * a], sb);
 #pragma unroll
   for (int a = 0; a < E; ++a) acc[a] = make_float2(0.f, 0.f);
+  float pw[WSUM ? E : 1];
+  if constexpr (WSUM) {
+#pragma unroll
+    for (int a = 0; a < E; ++a) pw[a] = 0.f;
+  }
   for (int m = 0; m < r.M; ++m) {
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
@@ -268,6 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) {
       float2 p = Ck<HALF>::load(prow + l + L * a);
+      if constexpr (WSUM) pw[a] += cabs2(p);
       acc[a] = cadd(acc[a], cjmul(p, v[a]));
       v[a] = cjmul(o[a], v[a]);
     }
@@ -281,6 +289,12 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     for (int a = 0; a < E; ++a) {
       unsafeAtomicAdd(g + 2 * (l + L * a), scale * sa * acc[a].x);
       unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * sa * acc[a].y);
+    }
+  }
+  if constexpr (WSUM) {
+    if (r.wsum) {
+#pragma unroll
+      for (int a = 0; a < E; ++a) unsafeAtomicAdd(r.wsum + orow + l + L * a, pw[a]);
     }
   }
 }
@@ -714,10 +728,16 @@ struct Launch {
   }
   static void rows_adj(const LaunchCtx& L, int step, PsiLoad psi, float scale) {
     dim3 g(Pass<N>::NBLK, L.n_items);
-    if (L.ck_half)
+    if (L.wsum) {
+      if (L.ck_half)
+        hipLaunchKernelGGL((k_row_adj<N, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+      else
+        hipLaunchKernelGGL((k_row_adj<N, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+    } else if (L.ck_half) {
       hipLaunchKernelGGL((k_row_adj<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
-    else
+    } else {
       hipLaunchKernelGGL((k_row_adj<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+    }
   }
   static void col(const LaunchCtx& L, int op, int step) {
     dim3 g(ColPass<N>::NBLK, L.n_items, L.max_modes);
@@ -1065,6 +1085,160 @@ __global__ void k_deramp_apply(float2* __restrict__ O, int S, int H, int W, cons
   }
 }
 
+// ------------------------------------------------------------ LSQML (Sec. 3.3)
+
+// Transparency of the object stack in the probe view, partial sums over the
+// items b = split, split + kLsqSplit, ...: part[split][r] = sum_b prod_i |O_i(n_b + r)|^2.
+__global__ __launch_bounds__(kThreads) void k_lsq_transp(const Item* __restrict__ items, int n_items,
+                                                          const float2* __restrict__ O, int S, int H, int W,
+                                                          int N, float* __restrict__ part) {
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  if (r >= N * N) return;
+  const int ry = r / N, rx = r % N;
+  float acc = 0.f;
+  for (int b = blockIdx.y; b < n_items; b += kLsqSplit) {
+    const Item it = items[b];
+    if (!it.valid) continue;
+    const float2* o = O + (size_t)(it.ny + ry) * W + it.nx + rx;
+    float t = 1.f;
+    for (int i = 0; i < S; ++i) t *= cabs2(o[(size_t)i * H * W]);
+    acc += t;
+  }
+  part[(size_t)blockIdx.y * N * N + r] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_lsq_transp_sum(const float* __restrict__ part, int N2,
+                                                              float* __restrict__ wp) {
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  if (r >= N2) return;
+  float acc = 0.f;
+  for (int q = 0; q < kLsqSplit; ++q) acc += part[(size_t)q * N2 + r];
+  wp[r] = acc;
+}
+
+// Object step sums per slice (blockIdx.y), with D = -g and
+// A = prev or cur + w: part = (sum |D|^2 / (A + delta), sum |D|^2 w / (A + delta)^2).
+__global__ __launch_bounds__(kThreads) void k_lsq_obj_sums(const float2* __restrict__ g, const float* __restrict__ w,
+                                                            const float* __restrict__ cur,
+                                                            const float* __restrict__ prev, size_t HW, float delta,
+                                                            double* __restrict__ part) {
+  const size_t base = (size_t)blockIdx.y * HW;
+  double num = 0.0, den = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < HW; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = base + e;
+    const double A = (prev ? (double)prev[q] : (double)cur[q] + (double)w[q]) + delta;
+    const double d2 = (double)cabs2(g[q]);
+    num += d2 / A;
+    den += d2 * (double)w[q] / (A * A);
+  }
+  __shared__ double red[2][kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_xor(num, off);
+    den += __shfl_xor(den, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = num;
+    red[1][threadIdx.x >> 6] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int v = 0; v < kThreads / 64; ++v) t += red[threadIdx.x][v];
+    part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2 + threadIdx.x] = t;
+  }
+}
+
+// alpha[s] = num / (den + gamma) from the partials of slice s (0 when the
+// denominator is 0). One block per slice.
+__global__ __launch_bounds__(kThreads) void k_lsq_alpha(const double* __restrict__ part, int nblk, double gamma,
+                                                         double* __restrict__ alpha) {
+  double num = 0.0, den = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    num += part[((size_t)blockIdx.x * nblk + b) * 2];
+    den += part[((size_t)blockIdx.x * nblk + b) * 2 + 1];
+  }
+  __shared__ double red[2][kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_xor(num, off);
+    den += __shfl_xor(den, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = num;
+    red[1][threadIdx.x >> 6] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double n = 0.0, d = gamma;
+    for (int v = 0; v < kThreads / 64; ++v) {
+      n += red[0][v];
+      d += red[1][v];
+    }
+    alpha[blockIdx.x] = d > 0.0 ? n / d : 0.0;
+  }
+}
+
+// O -= beta alpha_s g / (A + delta) (that is, O += beta alpha_s dO), then cur += w.
+__global__ void k_lsq_obj_update(float2* __restrict__ O, const float2* __restrict__ g, const float* __restrict__ w,
+                                 float* __restrict__ cur, const float* __restrict__ prev, int S, size_t HW,
+                                 float delta, float beta, const double* __restrict__ alpha) {
+  const size_t n = (size_t)S * HW;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const float ws = w[e];
+    const float A = (prev ? prev[e] : cur[e] + ws) + delta;
+    const float f = beta * (float)alpha[e / HW] / A;
+    O[e] = csub(O[e], cscale(g[e], f));
+    cur[e] += ws;
+  }
+}
+
+// Probe step size: one block reduces over M * N2 values (D = -g, A = prev or
+// cur + wp per pixel) and writes alpha = num / (den + gamma).
+__global__ __launch_bounds__(1024) void k_lsq_probe_alpha(const float2* __restrict__ g, const float* __restrict__ wp,
+                                                           const float* __restrict__ cur,
+                                                           const float* __restrict__ prev, int M, int N2,
+                                                           float delta, double gamma, double* __restrict__ alpha) {
+  double num = 0.0, den = 0.0;
+  for (int e = threadIdx.x; e < M * N2; e += blockDim.x) {
+    const int r = e % N2;
+    const double A = (prev ? (double)prev[r] : (double)cur[r] + (double)wp[r]) + delta;
+    const double d2 = (double)cabs2(g[e]);
+    num += d2 / A;
+    den += d2 * (double)wp[r] / (A * A);
+  }
+  __shared__ double red[2][16];
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_xor(num, off);
+    den += __shfl_xor(den, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = num;
+    red[1][threadIdx.x >> 6] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double n = 0.0, d = gamma;
+    for (int v = 0; v < (int)(blockDim.x >> 6); ++v) {
+      n += red[0][v];
+      d += red[1][v];
+    }
+    *alpha = d > 0.0 ? n / d : 0.0;
+  }
+}
+
+__global__ void k_lsq_probe_update(float2* __restrict__ P, const float2* __restrict__ g, const float* __restrict__ wp,
+                                   const float* __restrict__ cur, const float* __restrict__ prev, int M, int N2,
+                                   float delta, float beta, const double* __restrict__ alpha) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < M * N2; e += gridDim.x * blockDim.x) {
+    const int r = e % N2;
+    const float A = (prev ? prev[r] : cur[r] + wp[r]) + delta;
+    P[e] = csub(P[e], cscale(g[e], beta * (float)(*alpha) / A));
+  }
+}
+
+__global__ void k_add_inplace(float* __restrict__ a, const float* __restrict__ b, int n) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) a[e] += b[e];
+}
+
 // t <- t * mask (elementwise over n_tiles tiles of N*N).
 __global__ void k_mask_tiles(float2* __restrict__ t, const uint8_t* __restrict__ mask, size_t n, int N2) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
@@ -1112,6 +1286,32 @@ void launch_deramp(hipStream_t s, float2* O, int S, int H, int W, double* theta,
   hipLaunchKernelGGL(k_deramp_sums<1>, dim3(nb, S), dim3(kThreads), 0, s, O, H, W, theta, part);
   hipLaunchKernelGGL(k_deramp_angles<1>, dim3(S), dim3(kThreads), 0, s, part, nb, theta);
   hipLaunchKernelGGL(k_deramp_apply, dim3(reg_blocks((size_t)S * H * W)), dim3(kThreads), 0, s, O, S, H, W, theta);
+}
+void launch_lsq_transparency(hipStream_t s, const Item* items, int n_items, const float2* O, int S, int H,
+                             int W, int N, float* part, float* wp) {
+  const int N2 = N * N;
+  hipLaunchKernelGGL(k_lsq_transp, dim3((N2 + kThreads - 1) / kThreads, kLsqSplit), dim3(kThreads), 0, s, items,
+                     n_items, O, S, H, W, N, part);
+  hipLaunchKernelGGL(k_lsq_transp_sum, dim3((N2 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, part, N2, wp);
+}
+int lsq_blocks(size_t n) {
+  const size_t b = (n + kThreads - 1) / kThreads;
+  return (int)(b > 256 ? 256 : b);
+}
+void launch_lsq_object(hipStream_t s, float2* O, const float2* g, const float* w, float* cur, const float* prev,
+                       int S, size_t HW, float delta, double gamma, float beta, double* part, double* alpha) {
+  const int nb = lsq_blocks(HW);
+  hipLaunchKernelGGL(k_lsq_obj_sums, dim3(nb, S), dim3(kThreads), 0, s, g, w, cur, prev, HW, delta, part);
+  hipLaunchKernelGGL(k_lsq_alpha, dim3(S), dim3(kThreads), 0, s, part, nb, gamma, alpha);
+  hipLaunchKernelGGL(k_lsq_obj_update, dim3(reg_blocks((size_t)S * HW)), dim3(kThreads), 0, s, O, g, w, cur, prev,
+                     S, HW, delta, beta, alpha);
+}
+void launch_lsq_probe(hipStream_t s, float2* P, const float2* g, const float* wp, float* cur, const float* prev,
+                      int M, int N2, float delta, double gamma, float beta, double* alpha) {
+  hipLaunchKernelGGL(k_lsq_probe_alpha, dim3(1), dim3(1024), 0, s, g, wp, cur, prev, M, N2, delta, gamma, alpha);
+  hipLaunchKernelGGL(k_lsq_probe_update, dim3(reg_blocks((size_t)M * N2)), dim3(kThreads), 0, s, P, g, wp, cur,
+                     prev, M, N2, delta, beta, alpha);
+  hipLaunchKernelGGL(k_add_inplace, dim3(reg_blocks((size_t)N2)), dim3(kThreads), 0, s, cur, wp, N2);
 }
 void launch_mask_tiles(hipStream_t s, float2* t, const uint8_t* mask, size_t n, int N2) {
   hipLaunchKernelGGL(k_mask_tiles, dim3(reg_blocks(n)), dim3(kThreads), 0, s, t, mask, n, N2);

@@ -444,3 +444,54 @@ def test_epie_step_matches_oracle(N, loss, eps, ck_every):
     assert rel_l2(_np(st.object).astype(np.complex128), ost["object"]) < 1e-5
     assert rel_l2(_np(st.probe).astype(np.complex128), ost["probe"]) < 1e-5
     assert np.array_equal(_np(st.positions), c.pos)
+
+
+@pytest.mark.parametrize("N,loss,eps,ck_every,chunk", [(64, "amplitude", 0.0, 1, 0), (64, "poisson", 0.5, 2, 4),
+                                                       (128, "anscombe", 0.1, 1, 0), (192, "amplitude", 0.0, 3, 0)])
+def test_lsqml_step_matches_oracle(N, loss, eps, ck_every, chunk):
+    """The LSQML engine (Sec. 3.3) over two iterations: the object and probe
+    steps and the illumination sums of every group step against the oracle,
+    each step started from the GPU state and sums (first iteration with the
+    running sums, then with the previous iteration's)."""
+    from paper_2505_14372_amd import api
+    c = Case(synth.make_small(N=N, M=2, S=3, scan=3, step=5, seed=50 + N, loss=loss, eps=eps, amp_noise=0.3))
+    d = c.device()
+    prob = c.problem(max_batch=len(c.batch), checkpoint_every=ck_every, lsqml=True)
+    prob.set_chunk(chunk)
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    il = api.IllumSums(c.S, c.H, c.W, c.N)
+    kw = dict(beta_object=0.9, beta_probe=0.7, delta_object=1e-2, delta_probe=1e-2, gamma=1e-3)
+    pats = c.pats.astype(np.float64)
+    for it in range(2):
+        for b in ([0, 4, 8], [1, 2, 3, 5, 6, 7]):
+            P0 = _np(st.probe).astype(np.complex128)
+            O0 = _np(st.object).astype(np.complex128)
+            oil = dict(obj_cur=_np(il.obj_cur).astype(np.float64), probe_cur=_np(il.probe_cur).astype(np.float64),
+                       obj_prev=None if il.obj_prev is None else _np(il.obj_prev).astype(np.float64),
+                       probe_prev=None if il.probe_prev is None else _np(il.probe_prev).astype(np.float64),
+                       first=il.obj_prev is None)
+            onew, oloss, info = orc.lsqml_step(dict(probe=P0, object=O0, positions=c.pos.astype(np.float64)), oil,
+                                               pats, b, c.geom, **kw)
+            loss_g = prob.lsqml_step(st, il, d["pats"], torch.tensor(b, dtype=torch.int32, device="cuda"), **kw)
+            prob.check()
+            assert abs(loss_g.item() - oloss) < TOL_I * abs(oloss), (loss_g.item(), oloss)
+            errs = dict(dO=rel_l2(_np(st.object).astype(np.complex128) - O0, onew["object"] - O0),
+                        dP=rel_l2(_np(st.probe).astype(np.complex128) - P0, onew["probe"] - P0),
+                        obj_cur=rel_l2(_np(il.obj_cur), oil["obj_cur"]),
+                        probe_cur=rel_l2(_np(il.probe_cur), oil["probe_cur"]))
+            print(N, it, errs, info["alpha"], info["alpha_probe"])
+            assert all(v < TOL_G for v in errs.values()), errs
+        il.end_iteration()
+    assert np.array_equal(_np(st.positions), c.pos)
+
+
+def test_lsqml_needs_its_scratch():
+    from paper_2505_14372_amd import _lib, api
+    c = Case(synth.make_small(N=64, M=1, S=1, scan=2, step=4, seed=3, loss="amplitude"))
+    d = c.device()
+    prob = c.problem(max_batch=4)
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    il = api.IllumSums(c.S, c.H, c.W, c.N)
+    with pytest.raises(_lib.PtyError) as e:
+        prob.lsqml_step(st, il, d["pats"], d["batch"])
+    assert e.value.status == _lib.PTY_ESTATE
