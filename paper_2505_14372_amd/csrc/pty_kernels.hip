@@ -45,16 +45,6 @@ __device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw_g
 }
 
 
-// PTY_ROW_PF: the forward row pass loads the next mode's row one iteration
-// ahead (tuning switch).
-#ifndef PTY_ROW_PF
-#define PTY_ROW_PF 0
-#endif
-// PTY_COL_MLOOP: the propagation column passes loop over the modes inside a
-// workgroup with a one-mode prefetch (tuning switch).
-#ifndef PTY_COL_MLOOP
-#define PTY_COL_MLOOP 0
-#endif
 #ifndef PTY_NT_CKPT
 #define PTY_NT_CKPT 0
 #endif
@@ -176,12 +166,6 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) pw[a] = 0.f;
   }
-  float2 nx[PTY_ROW_PF && !FROM_REAL ? E : 1];
-  if constexpr (PTY_ROW_PF && !FROM_REAL) {
-    const float2* t0 = ws + ((size_t)it.tile0 * N + y) * N;
-#pragma unroll
-    for (int a = 0; a < E; ++a) nx[a] = t0[l + L * a];
-  }
   for (int m = 0; m < r.M; ++m) {
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
@@ -189,15 +173,6 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
       const CT* src = static_cast<const CT*>(store.src) + (((size_t)it.ck0 + (size_t)m * n_ck + store.src_slot) * N + y) * N;
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = Ck<HALF>::load(src + l + L * a);
-    } else if constexpr (PTY_ROW_PF) {
-      // this mode's row was loaded one iteration ahead; load the next one now
-#pragma unroll
-      for (int a = 0; a < E; ++a) v[a] = nx[a];
-      if (m + 1 < r.M) {
-#pragma unroll
-        for (int a = 0; a < E; ++a) nx[a] = trow[(size_t)N * N + l + L * a];
-      }
-      line_fft<N, true>(v, l, tw, sx, WaveSync{});
     } else {
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = trow[l + L * a];
@@ -410,37 +385,6 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   const int c = ColMap<N>::col(), l = ColMap<N>::lane();
   const int ux = blockIdx.x * CB + c;
   float2* sx = xch + c * ColMap<N>::STRIDE;
-  if constexpr (PTY_COL_MLOOP && (OP == COL_PROP || OP == COL_PROP_ADJ)) {
-    // one workgroup walks the modes of its item (grid z = 1); the next
-    // mode's column is loaded while the current one is transformed
-    const float2* H = r.prop + (size_t)(OP == COL_PROP ? i : i - 1) * N * N;
-    float2* t0 = ws + (size_t)it.tile0 * N * N;
-    float2 v[E], nx[E];
-#pragma unroll
-    for (int a = 0; a < E; ++a) v[a] = t0[(size_t)(l + L * a) * N + ux];
-    for (int mm = 0; mm < r.M; ++mm) {
-      float2* tile = t0 + (size_t)mm * N * N;
-      const bool more = mm + 1 < r.M;
-      if (more) {
-#pragma unroll
-        for (int a = 0; a < E; ++a) nx[a] = tile[(size_t)N * N + (size_t)(l + L * a) * N + ux];
-      }
-      line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
-#pragma unroll
-      for (int a = 0; a < E; ++a) {
-        float2 h = H[(size_t)(l + L * a) * N + ux];
-        v[a] = (OP == COL_PROP) ? cmul(v[a], h) : cjmul(h, v[a]);
-      }
-      line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
-#pragma unroll
-      for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = v[a];
-      if (more) {
-#pragma unroll
-        for (int a = 0; a < E; ++a) v[a] = nx[a];
-      }
-    }
-    return;
-  }
   float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
   float2 v[E];
   if constexpr (OP == COL_SHIFT) {
@@ -796,8 +740,7 @@ struct Launch {
     }
   }
   static void col(const LaunchCtx& L, int op, int step) {
-    const bool mloop = PTY_COL_MLOOP && (op == COL_PROP || op == COL_PROP_ADJ);
-    dim3 g(ColPass<N>::NBLK, L.n_items, mloop ? 1 : L.max_modes);
+    dim3 g(ColPass<N>::NBLK, L.n_items, L.max_modes);
     switch (op) {
       case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
       case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
