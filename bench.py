@@ -4,11 +4,17 @@ probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 512]
                     [--no-cpu-baseline] [--cpu-positions 16]
+                    [--workload cfg3_ms256|cfg2_ms192|cfg1_ms128|cfg0_spoa64|serving]
+                    [--engine adam|sgd|epie|lsqml] [--regularize]
+                    [--checkpoint-every k] [--checkpoint-half] [--strategy ...] [--chunk n]
 
 A step is one reconstruct_step over one group of `batch` positions drawn
 from a seeded permutation of the 128 x 128 scan (16384 positions = 32 groups
 per epoch), with every input resident in HBM before the timed region.
-Prints one JSON line.
+Prints one JSON line. The headline is the default: Adam, float32
+checkpoints, no regularizers; the other options measure the conventional
+engines, the regularizers and the storage and schedule variants on the
+same workload.
 """
 from __future__ import annotations
 
@@ -30,6 +36,9 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
 
+ENGINES = {"adam": "Adam", "sgd": "SGD", "epie": "ePIE", "lsqml": "LSQML"}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -46,21 +55,26 @@ def parse():
                    help="store entry-wave checkpoints as IEEE half pairs (reduced-precision storage)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    p.add_argument("--engine", default="adam", choices=list(ENGINES),
+                   help="group step: gradient descent with Adam (the headline) or SGD, or the ePIE / LSQML engines")
+    p.add_argument("--regularize", action="store_true",
+                   help="enable every cost regularizer and constraint in the step")
     p.add_argument("--requests", type=int, default=16, help="serving stream: number of reconstructions")
     p.add_argument("--iters", type=int, default=50, help="serving stream: iterations per reconstruction")
     return p.parse_args()
 
 
-def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False):
+def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam"):
     """Algorithmic HBM bytes one launch of a kernel class must move (complex64
     tile T = 8 N^2 bytes, per launch over B positions and M modes; a
-    checkpoint is T, or T/2 when stored as half floats)."""
+    checkpoint is T, or T/2 when stored as half floats; LSQML adds the
+    read-modify-write of a float illumination sum, T per position)."""
     T = 8 * N * N
     C = T // 2 if ck_half else T
     if name == "row_fwd":      # read + write every mode tile, write the entry-wave checkpoint, read the object patch
         return B * (M * (2 * T + C) + T)
     if name == "row_adj":      # read + write tiles, read checkpoints, read object patch, RMW object gradient
-        return B * (M * (2 * T + C) + 3 * T)
+        return B * (M * (2 * T + C) + 3 * T) + (B * T if engine == "lsqml" else 0)
     if name in ("col_prop", "col_prop_adj"):   # read + write every tile
         return B * 2 * M * T
     if name == "far_loss":     # tiles read, far field written and re-read, seed written; pattern read
@@ -118,13 +132,35 @@ def main():
     for s0 in range(0, J, chunk):
         pats[s0:s0 + chunk].copy_(torch.from_numpy(wl.patterns[s0:s0 + chunk]))
     prob = api.Problem(N, M, S, H, W, J, dz=wl.dz, dx=wl.dx, wavelength=wl.wavelength, loss=wl.loss, eps=wl.eps,
-                       max_batch=B, checkpoint_every=args.checkpoint_every, checkpoint_half=args.checkpoint_half)
+                       max_batch=B, checkpoint_every=args.checkpoint_every, checkpoint_half=args.checkpoint_half,
+                       lsqml=args.engine == "lsqml")
     prob.set_chunk(args.chunk)
     prob.set_strategy(args.strategy)
-    state = api.ReconState(probe, obj, pos, adam=True)
-    opt = api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2)
+    if args.regularize:
+        k = np.fft.fftfreq(N) * N
+        prob.set_regularizers(obj_l2=1e-3, probe_l2=1e-6, obj_l1=1e-3, obj_tikhonov=1e-2, obj_tv=1e-2,
+                              layers_tikhonov=1e-2, layers_tv=1e-2, tv_delta=1e-2, amp_range=(0.0, 1.0),
+                              probe_support=(k[:, None] ** 2 + k[None, :] ** 2) <= (N / 3) ** 2, layer_sigma=0.5,
+                              obj_lowpass_sigma=0.5, phase_deramp=True)
+    state = api.ReconState(probe, obj, pos, adam=args.engine == "adam")
     rng = np.random.default_rng(12345)
     n_groups = J // B
+    if args.engine == "lsqml":
+        illum = api.IllumSums(S, H, W, N)
+        counter = [0]
+
+        def step(batch, loss):
+            prob.lsqml_step(state, illum, pats, batch, loss=loss)
+            counter[0] += 1
+            if counter[0] % n_groups == 0:
+                illum.end_iteration()
+    else:
+        opt = {"adam": api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2),
+               "sgd": api.Optimizer(kind="sgd", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2),
+               "epie": api.Optimizer(kind="epie", lr_object=1.0, lr_probe=1.0)}[args.engine]
+
+        def step(batch, loss):
+            prob.reconstruct_step(state, pats, batch, opt, loss)
 
     def groups():
         while True:
@@ -137,7 +173,7 @@ def main():
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
-        prob.reconstruct_step(state, pats, batches[w], opt, loss)
+        step(batches[w], loss)
         print(f"[bench] warmup step {w} done", file=sys.stderr, flush=True)
     prob.check()
     torch.cuda.synchronize()
@@ -151,7 +187,7 @@ def main():
     t_start = time.perf_counter()
     for k in range(args.steps):
         starts[k].record(stream)
-        prob.reconstruct_step(state, pats, batches[args.warmup + k], opt, loss)
+        step(batches[args.warmup + k], loss)
         ends[k].record(stream)
         if (k + 1) % 8 == 0:
             print(f"[bench] timed step {k + 1}/{args.steps} queued", file=sys.stderr, flush=True)
@@ -173,7 +209,7 @@ def main():
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_s = dom_ms / dom_n / 1000.0
-    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half)
+    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine)
     flops_launch = kernel_flops_per_launch(dom, N, M, B, S)
     gbs = bytes_launch / avg_s / 1e9
     tfl = flops_launch / avg_s / 1e12
@@ -183,7 +219,9 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
-    traffic = None if prob.checkpoint_half else measured_traffic(dom)
+    # the counters were taken on the default configuration only
+    default_cfg = not prob.checkpoint_half and args.engine == "adam" and not args.regularize
+    traffic = measured_traffic(dom) if default_cfg else None
     roof.update({"kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4),
                  "traffic": traffic, "algorithmic_bytes": bytes_launch, "algorithmic_flops": flops_launch})
     kernels = {k: {"total_ms": round(v[0], 3), "launches": int(v[1]), "avg_ms": round(v[0] / v[1], 4),
@@ -194,9 +232,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: probe {N}x{N}, {M} modes, {S} slices of {wl.dz[0] if S > 1 else 0} A, "
-                               f"object {H}x{W}x{S} complex64, {J} positions, groups of {B}, Poisson loss, Adam",
+                               f"object {H}x{W}x{S} complex64, {J} positions, groups of {B}, {wl.loss} loss, "
+                               f"{ENGINES[args.engine]}{', all regularizers' if args.regularize else ''}",
                    "global_batch": B, "checkpoint_every": prob.checkpoint_every,
-                   "checkpoint_storage": "f16" if prob.checkpoint_half else "f32", "strategy": args.strategy},
+                   "checkpoint_storage": "f16" if prob.checkpoint_half else "f32", "strategy": args.strategy,
+                   "engine": args.engine, "regularizers": bool(args.regularize)},
         "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
         "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
         "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),

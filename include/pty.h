@@ -292,7 +292,8 @@ typedef struct {
 
 typedef struct {
   double beta_object, beta_probe;   /* step scales (0 freezes) */
-  double delta_object, delta_probe; /* added to the illumination sums (> 0) */
+  double delta_object, delta_probe; /* relative regularisers (> 0): delta * max of the
+                                       illumination sum in use is added to it */
   double gamma;                     /* added to the step-size denominators (>= 0) */
 } pty_lsqml;
 
@@ -302,12 +303,12 @@ typedef struct {
  * is carried to slice i - 1 by F^-1 conj(H) F (no normalisers). With
  * D_i = sum_j sum_m chi_i conj(psi_i) and W_i = sum_j sum_m |psi_i|^2 scattered
  * into object coordinates, A_i the object-view illumination sum:
- *   dO_i = D_i / (A_i + delta_object),
+ *   dO_i = D_i / (A_i + delta_object max A_i),
  *   alpha_i = Re <dO_i, D_i> / (<|dO_i|^2, W_i> + gamma)   (0 if that is 0),
  *   O_i += beta_object alpha_i dO_i.
  * Probe: dP_m = sum_j (slice-0 entry-wave update shifted back by -delta_j),
  * T = sum_j prod_i |O_i|^2 over window j, Bp the probe-view sum:
- *   dP'_m = dP_m / (Bp + delta_probe),
+ *   dP'_m = dP_m / (Bp + delta_probe max Bp),
  *   alpha_P = Re sum_m <dP'_m, dP_m> / (sum_m <|dP'_m|^2, T> + gamma),
  *   P += beta_probe alpha_P dP'.
  * Positions are kept; the constraints of pty_set_regularizers apply, the cost

@@ -405,8 +405,9 @@ def epie_update(probe, obj, positions, patterns, batch_idx, geom: Geometry):
 #   i - 1 by F^-1 conj(H) F;
 # * object, per slice i: the direction summed over the group and the modes,
 #   D_i = sum_j sum_m chi_i,m conj(psi_i,m) (scattered into object
-#   coordinates), normalised by the illumination sum A_i:
-#   dO_hat_i = D_i / (A_i + delta_O);
+#   coordinates), normalised by the illumination sum A_i, regularised
+#   relative to its maximum (dose-independent):
+#   dO_hat_i = D_i / (A_i + delta_O max A_i);
 # * the step is computed per group (one per slice), the least-squares fit of
 #   dO_hat_i psi to chi over the group:
 #   alpha_i = Re <dO_hat_i, D_i> / (<|dO_hat_i|^2, W_i> + gamma) with
@@ -415,7 +416,7 @@ def epie_update(probe, obj, positions, patterns, batch_idx, geom: Geometry):
 #   itself: O_i += beta_O alpha_i dO_hat_i;
 # * probe, at slice 0: the direction is the entry-wave update conj(O_0) chi_0
 #   shifted back by -delta_j, summed over the group, per mode: dP_m;
-#   dP_hat_m = dP_m / (B + delta_P); the illumination of the probe is the
+#   dP_hat_m = dP_m / (B + delta_P max B); the illumination of the probe is the
 #   object's transparency T_j = prod_i |O_i|^2 over window j (probe view,
 #   integer window offset), so alpha_P = Re sum_m <dP_hat_m, dP_m> /
 #   (sum_m <|dP_hat_m|^2, sum_j T_j> + gamma) and P += beta_P alpha_P dP_hat;
@@ -428,7 +429,7 @@ def epie_update(probe, obj, positions, patterns, batch_idx, geom: Geometry):
 #   state before the step.
 
 def lsqml_step(state, illum, patterns, batch_idx, geom: Geometry, beta_object=1.0, beta_probe=1.0,
-               delta_object=1e-3, delta_probe=1e-3, gamma=0.0):
+               delta_object=1e-2, delta_probe=1e-2, gamma=0.0):
     """One LSQML group step.
 
     illum: dict(obj_prev [S][H][W], obj_cur [S][H][W], probe_prev [N][N],
@@ -472,7 +473,7 @@ def lsqml_step(state, illum, patterns, batch_idx, geom: Geometry, beta_object=1.
     A = illum["obj_cur"] if illum["first"] else illum["obj_prev"]
     Bp = illum["probe_cur"] if illum["first"] else illum["probe_prev"]
     new = dict(state)
-    dO_hat = D / (A + delta_object)
+    dO_hat = D / (A + delta_object * A.max(axis=(1, 2), keepdims=True))
     alpha = np.zeros(S)
     for i in range(S):
         num = np.real(np.vdot(dO_hat[i], D[i]))
@@ -480,7 +481,7 @@ def lsqml_step(state, illum, patterns, batch_idx, geom: Geometry, beta_object=1.
         alpha[i] = num / den if den > 0 else 0.0
     new["object"] = O + beta_object * alpha[:, None, None] * dO_hat
     dP = ifft2u(dP_hat_spec)
-    dP_hat = dP / (Bp + delta_probe)
+    dP_hat = dP / (Bp + delta_probe * Bp.max())
     num = np.real(np.vdot(dP_hat, dP))
     den = np.sum(np.abs(dP_hat) ** 2 * T_sum[None]) + gamma
     alpha_p = num / den if den > 0 else 0.0

@@ -265,7 +265,7 @@ class Problem:
         return loss
 
     def lsqml_step(self, state: ReconState, illum: "IllumSums", patterns, batch_idx, beta_object=1.0,
-                   beta_probe=1.0, delta_object=1e-3, delta_probe=1e-3, gamma=0.0, loss=None):
+                   beta_probe=1.0, delta_object=1e-2, delta_probe=1e-2, gamma=0.0, loss=None):
         """One LSQML group step (pty_lsqml_step); needs Problem(..., lsqml=True)."""
         B = self._check_inputs(state.probe, state.object, state.positions, batch_idx, patterns)
         for t, shape, name in ((illum.obj_cur, (self.S, self.H, self.W), "obj_cur"),

@@ -117,7 +117,7 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8, bo
     const size_t HW = (size_t)g->obj_h * g->obj_w;
     b += align256((size_t)S * HW * sizeof(float));                     // illumination scatter
     b += align256((size_t)(kLsqSplit + 1) * N2 * sizeof(float));       // transparency partials + sum
-    b += align256(((size_t)S * lsq_blocks(HW) * 2 + S + 1) * sizeof(double));
+    b += align256(((size_t)S * lsq_blocks(HW) * 3 + 2 * S + 2) * sizeof(double));
   }
   s.bytes = b;
   return s;
@@ -497,7 +497,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
     const size_t HW = (size_t)g->obj_h * g->obj_w;
     if ((st = dmalloc(&c->lsq_w, (size_t)S * HW, e)) || (st = dmalloc(&c->lsq_part, (size_t)kLsqSplit * N2, e)) ||
         (st = dmalloc(&c->lsq_wp, N2, e)) ||
-        (st = dmalloc(&c->lsq_sums, (size_t)S * lsq_blocks(HW) * 2 + S + 1, e)))
+        (st = dmalloc(&c->lsq_sums, (size_t)S * lsq_blocks(HW) * 3 + 2 * S + 2, e)))
       return fail(st);
   }
   if (max_batch > 0) {
@@ -927,7 +927,7 @@ extern "C" pty_status pty_lsqml_step(pty_ctx* c, void* stream, pty_state* st, co
   if (!std::isfinite(o->beta_object) || !std::isfinite(o->beta_probe) || !(dO > 0.f) || !(dP > 0.f) ||
       !std::isfinite(o->delta_object) || !std::isfinite(o->delta_probe) || !(o->gamma >= 0.0) ||
       !std::isfinite(o->gamma)) {
-    c->err = "LSQML needs finite betas, deltas > 0 (in float) and gamma >= 0";
+    c->err = "LSQML needs finite betas, relative deltas > 0 (in float) and gamma >= 0";
     return PTY_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -965,10 +965,12 @@ extern "C" pty_status pty_lsqml_step(pty_ctx* c, void* stream, pty_state* st, co
   {
     ProfScope p(P_OPTIM, s);
     launch_lsq_transparency(s, c->items, B, (const float2*)st->object, S, g.obj_h, g.obj_w, N, c->lsq_part, c->lsq_wp);
+    // lsq_sums: [S*nb*3 + S] sums and maxima of the object step, [S] alpha_i, [2] probe alpha and max
+    const size_t nb3 = (size_t)S * lsq_blocks(HW) * 3 + S;
     launch_lsq_object(s, (float2*)st->object, c->gobj, c->lsq_w, il->obj_cur, il->obj_prev, S, HW, dO, o->gamma,
-                      (float)o->beta_object, c->lsq_sums, c->lsq_sums + (size_t)S * lsq_blocks(HW) * 2);
+                      (float)o->beta_object, c->lsq_sums, c->lsq_sums + nb3);
     launch_lsq_probe(s, (float2*)st->probe, c->gprobe, c->lsq_wp, il->probe_cur, il->probe_prev, M, N * N, dP,
-                     o->gamma, (float)o->beta_probe, c->lsq_sums + (size_t)S * lsq_blocks(HW) * 2 + S);
+                     o->gamma, (float)o->beta_probe, c->lsq_sums + nb3 + S);
   }
   { ProfScope p(P_REG, s); apply_constraints(c, s, st); }
   HIPCHECK(c, hipGetLastError());

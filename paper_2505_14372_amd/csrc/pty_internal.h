@@ -139,13 +139,14 @@ constexpr int kLsqSplit = 32;
 void launch_lsq_transparency(hipStream_t s, const Item* items, int n_items, const float2* O, int S, int H,
                              int W, int N, float* part, float* wp);
 // Object step: D = -g (g the chain's object accumulator), A = prev or cur + w,
-// alpha_i from double sums (part: S * lsq_blocks(H * W) * 2 doubles, alpha: S
-// doubles), O -= beta alpha_i g / (A + delta), cur += w.
+// A' = A + delta max A per slice, alpha_i from double sums (part: S *
+// lsq_blocks(H * W) * 3 + S doubles of partial sums, partial maxima and
+// maxima; alpha: S doubles), O -= beta alpha_i g / A', cur += w.
 int lsq_blocks(size_t n);
 void launch_lsq_object(hipStream_t s, float2* O, const float2* g, const float* w, float* cur, const float* prev,
                        int S, size_t HW, float delta, double gamma, float beta, double* part, double* alpha);
 // Probe step, likewise with the probe accumulator g [M][N][N], the
-// transparency sum wp [N][N] and one alpha.
+// transparency sum wp [N][N]; alpha: 2 doubles (step, max B).
 void launch_lsq_probe(hipStream_t s, float2* P, const float2* g, const float* wp, float* cur, const float* prev,
                       int M, int N2, float delta, double gamma, float beta, double* alpha);
 

@@ -1116,17 +1116,54 @@ __global__ __launch_bounds__(kThreads) void k_lsq_transp_sum(const float* __rest
   wp[r] = acc;
 }
 
-// Object step sums per slice (blockIdx.y), with D = -g and
-// A = prev or cur + w: part = (sum |D|^2 / (A + delta), sum |D|^2 w / (A + delta)^2).
+// Per-slice maximum of the illumination sum in use, A = prev or cur + w:
+// partial maxima per block (grid nb x S), then one block per slice.
+__global__ __launch_bounds__(kThreads) void k_lsq_obj_pmax(const float* __restrict__ w, const float* __restrict__ cur,
+                                                            const float* __restrict__ prev, size_t HW,
+                                                            double* __restrict__ pmax) {
+  const size_t base = (size_t)blockIdx.y * HW;
+  float mx = 0.f;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < HW; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = base + e;
+    mx = fmaxf(mx, prev ? prev[q] : cur[q] + w[q]);
+  }
+  __shared__ float red[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < kThreads / 64; ++v) mx = fmaxf(mx, red[v]);
+    pmax[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = mx;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lsq_obj_amax(const double* __restrict__ pmax, int nblk,
+                                                            double* __restrict__ amax) {
+  double mx = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) mx = fmax(mx, pmax[(size_t)blockIdx.x * nblk + b]);
+  __shared__ double red[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < kThreads / 64; ++v) mx = fmax(mx, red[v]);
+    amax[blockIdx.x] = mx;
+  }
+}
+
+// Object step sums per slice (blockIdx.y), with D = -g, A = prev or cur + w
+// and A' = A + delta max A: part = (sum |D|^2 / A', sum |D|^2 w / A'^2).
 __global__ __launch_bounds__(kThreads) void k_lsq_obj_sums(const float2* __restrict__ g, const float* __restrict__ w,
                                                             const float* __restrict__ cur,
                                                             const float* __restrict__ prev, size_t HW, float delta,
+                                                            const double* __restrict__ amax,
                                                             double* __restrict__ part) {
   const size_t base = (size_t)blockIdx.y * HW;
+  const double reg = (double)delta * amax[blockIdx.y];
   double num = 0.0, den = 0.0;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < HW; e += (size_t)gridDim.x * blockDim.x) {
     const size_t q = base + e;
-    const double A = (prev ? (double)prev[q] : (double)cur[q] + (double)w[q]) + delta;
+    const double A = (prev ? (double)prev[q] : (double)cur[q] + (double)w[q]) + reg;
     const double d2 = (double)cabs2(g[q]);
     num += d2 / A;
     den += d2 * (double)w[q] / (A * A);
@@ -1177,30 +1214,46 @@ __global__ __launch_bounds__(kThreads) void k_lsq_alpha(const double* __restrict
   }
 }
 
-// O -= beta alpha_s g / (A + delta) (that is, O += beta alpha_s dO), then cur += w.
+// O -= beta alpha_s g / (A + delta max A) (that is, O += beta alpha_s dO), then cur += w.
 __global__ void k_lsq_obj_update(float2* __restrict__ O, const float2* __restrict__ g, const float* __restrict__ w,
                                  float* __restrict__ cur, const float* __restrict__ prev, int S, size_t HW,
-                                 float delta, float beta, const double* __restrict__ alpha) {
+                                 float delta, float beta, const double* __restrict__ alpha,
+                                 const double* __restrict__ amax) {
   const size_t n = (size_t)S * HW;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     const float ws = w[e];
-    const float A = (prev ? prev[e] : cur[e] + ws) + delta;
+    const float A = (prev ? prev[e] : cur[e] + ws) + delta * (float)amax[e / HW];
     const float f = beta * (float)alpha[e / HW] / A;
     O[e] = csub(O[e], cscale(g[e], f));
     cur[e] += ws;
   }
 }
 
-// Probe step size: one block reduces over M * N2 values (D = -g, A = prev or
-// cur + wp per pixel) and writes alpha = num / (den + gamma).
+// Probe step size: one block finds max B (B = prev or cur + wp per pixel),
+// stores it in alpha[1], then reduces over M * N2 values (D = -g,
+// B' = B + delta max B) and writes alpha[0] = num / (den + gamma).
 __global__ __launch_bounds__(1024) void k_lsq_probe_alpha(const float2* __restrict__ g, const float* __restrict__ wp,
                                                            const float* __restrict__ cur,
                                                            const float* __restrict__ prev, int M, int N2,
                                                            float delta, double gamma, double* __restrict__ alpha) {
+  __shared__ float rmax[16];
+  __shared__ double bmax;
+  float mx = 0.f;
+  for (int r = threadIdx.x; r < N2; r += blockDim.x) mx = fmaxf(mx, prev ? prev[r] : cur[r] + wp[r]);
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) rmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < (int)(blockDim.x >> 6); ++v) mx = fmaxf(mx, rmax[v]);
+    bmax = mx;
+    alpha[1] = mx;
+  }
+  __syncthreads();
+  const double reg = (double)delta * bmax;
   double num = 0.0, den = 0.0;
   for (int e = threadIdx.x; e < M * N2; e += blockDim.x) {
     const int r = e % N2;
-    const double A = (prev ? (double)prev[r] : (double)cur[r] + (double)wp[r]) + delta;
+    const double A = (prev ? (double)prev[r] : (double)cur[r] + (double)wp[r]) + reg;
     const double d2 = (double)cabs2(g[e]);
     num += d2 / A;
     den += d2 * (double)wp[r] / (A * A);
@@ -1221,17 +1274,18 @@ __global__ __launch_bounds__(1024) void k_lsq_probe_alpha(const float2* __restri
       n += red[0][v];
       d += red[1][v];
     }
-    *alpha = d > 0.0 ? n / d : 0.0;
+    alpha[0] = d > 0.0 ? n / d : 0.0;
   }
 }
 
 __global__ void k_lsq_probe_update(float2* __restrict__ P, const float2* __restrict__ g, const float* __restrict__ wp,
                                    const float* __restrict__ cur, const float* __restrict__ prev, int M, int N2,
                                    float delta, float beta, const double* __restrict__ alpha) {
+  const float reg = delta * (float)alpha[1];
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < M * N2; e += gridDim.x * blockDim.x) {
     const int r = e % N2;
-    const float A = (prev ? prev[r] : cur[r] + wp[r]) + delta;
-    P[e] = csub(P[e], cscale(g[e], beta * (float)(*alpha) / A));
+    const float A = (prev ? prev[r] : cur[r] + wp[r]) + reg;
+    P[e] = csub(P[e], cscale(g[e], beta * (float)alpha[0] / A));
   }
 }
 
@@ -1301,10 +1355,14 @@ int lsq_blocks(size_t n) {
 void launch_lsq_object(hipStream_t s, float2* O, const float2* g, const float* w, float* cur, const float* prev,
                        int S, size_t HW, float delta, double gamma, float beta, double* part, double* alpha) {
   const int nb = lsq_blocks(HW);
-  hipLaunchKernelGGL(k_lsq_obj_sums, dim3(nb, S), dim3(kThreads), 0, s, g, w, cur, prev, HW, delta, part);
+  double* pmax = part + (size_t)S * nb * 2;      // after the sums: S * nb partial maxima, then S maxima
+  double* amax = pmax + (size_t)S * nb;
+  hipLaunchKernelGGL(k_lsq_obj_pmax, dim3(nb, S), dim3(kThreads), 0, s, w, cur, prev, HW, pmax);
+  hipLaunchKernelGGL(k_lsq_obj_amax, dim3(S), dim3(kThreads), 0, s, pmax, nb, amax);
+  hipLaunchKernelGGL(k_lsq_obj_sums, dim3(nb, S), dim3(kThreads), 0, s, g, w, cur, prev, HW, delta, amax, part);
   hipLaunchKernelGGL(k_lsq_alpha, dim3(S), dim3(kThreads), 0, s, part, nb, gamma, alpha);
   hipLaunchKernelGGL(k_lsq_obj_update, dim3(reg_blocks((size_t)S * HW)), dim3(kThreads), 0, s, O, g, w, cur, prev,
-                     S, HW, delta, beta, alpha);
+                     S, HW, delta, beta, alpha, amax);
 }
 void launch_lsq_probe(hipStream_t s, float2* P, const float2* g, const float* wp, float* cur, const float* prev,
                       int M, int N2, float delta, double gamma, float beta, double* alpha) {
