@@ -156,7 +156,7 @@ def main():
                 illum.end_iteration()
     else:
         opt = {"adam": api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2),
-               "sgd": api.Optimizer(kind="sgd", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2),
+               "sgd": api.Optimizer(kind="sgd", lr_object=1e-8, lr_probe=1e-10, lr_pos=1e-8),
                "epie": api.Optimizer(kind="epie", lr_object=1.0, lr_probe=1.0)}[args.engine]
 
         def step(batch, loss):

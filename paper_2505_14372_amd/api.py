@@ -264,9 +264,12 @@ class Problem:
         state.step = cs.step
         return loss
 
-    def lsqml_step(self, state: ReconState, illum: "IllumSums", patterns, batch_idx, beta_object=1.0,
-                   beta_probe=1.0, delta_object=1e-2, delta_probe=1e-2, gamma=0.0, loss=None):
-        """One LSQML group step (pty_lsqml_step); needs Problem(..., lsqml=True)."""
+    def lsqml_step(self, state: ReconState, illum: "IllumSums", patterns, batch_idx, beta_object=0.1,
+                   beta_probe=0.1, delta_object=1e-2, delta_probe=1e-2, gamma=0.0, loss=None):
+        """One LSQML group step (pty_lsqml_step); needs Problem(..., lsqml=True).
+        Every slice takes its full least-squares correction and also passes it
+        on to the slices before it, so with many slices full steps (beta = 1)
+        overshoot; the default scale is 0.1."""
         B = self._check_inputs(state.probe, state.object, state.positions, batch_idx, patterns)
         for t, shape, name in ((illum.obj_cur, (self.S, self.H, self.W), "obj_cur"),
                                (illum.obj_prev, (self.S, self.H, self.W), "obj_prev"),

@@ -603,11 +603,9 @@ __global__ void k_loss_reduce(const ReqTable reqs, const float* __restrict__ los
   const ReqDev& r = reqs.r[blockIdx.x];
   __shared__ double red[kThreads];
   double acc = 0.0;
-  for (int b = r.item0; b < r.item0 + r.n_items; ++b) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += blockDim.x) s += (double)loss_part[(size_t)b * nblk + k];
-    acc += s;
-  }
+  const float* part = loss_part + (size_t)r.item0 * nblk;
+  const size_t n = (size_t)r.n_items * nblk;
+  for (size_t e = threadIdx.x; e < n; e += blockDim.x) acc += (double)part[e];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -618,25 +616,40 @@ __global__ void k_loss_reduce(const ReqTable reqs, const float* __restrict__ los
 }
 
 // Probe-spectrum gradient per request: gphat_m(u) = scale * sum_b h_hat_{b,m}(u) conj(R_b(u)).
-template <int N>
-__global__ __launch_bounds__(kThreads) void k_probe_grad(const Item* __restrict__ items,
-                                                         const ReqTable reqs,
-                                                         const float2* __restrict__ ws,
-                                                         const float2* __restrict__ ramps, float scale) {
+// A workgroup of PIX x SPLIT threads covers PIX consecutive pixels; thread
+// row s sums the items b = item0 + s, s + SPLIT, ... and the rows are added
+// in a fixed order (deterministic for a given launch shape).
+template <int N, int PIX, int SPLIT>
+__global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restrict__ items, const ReqTable reqs,
+                                                            const float2* __restrict__ ws,
+                                                            const float2* __restrict__ ramps, float scale) {
   const ReqDev& r = reqs.r[blockIdx.z];
   const int m = blockIdx.y;
   if (m >= r.M || !r.gphat) return;
-  const int p = blockIdx.x * kThreads + threadIdx.x;
+  constexpr int split = SPLIT, pix = PIX;
+  const int px = threadIdx.x % pix, s = threadIdx.x / pix;
+  const int p = blockIdx.x * pix + px;
   const int uy = p / N, ux = p % N;
   float2 acc = make_float2(0.f, 0.f);
-  for (int b = r.item0; b < r.item0 + r.n_items; ++b) {
+  for (int b = r.item0 + s; b < r.item0 + r.n_items; b += split) {
     const Item it = items[b];
     if (!it.valid) continue;
     float2 R = cmul(ramps[(size_t)b * 2 * N + uy], ramps[(size_t)b * 2 * N + N + ux]);
     float2 h = ws[(size_t)(it.tile0 + m) * N * N + p];
     acc = cadd(acc, cmul(h, cconj(R)));
   }
-  r.gphat[(size_t)m * N * N + p] = cscale(acc, scale);
+  if constexpr (SPLIT == 1) {
+    r.gphat[(size_t)m * N * N + p] = cscale(acc, scale);
+    return;
+  }
+  __shared__ float2 red[PIX * SPLIT];
+  red[s * pix + px] = acc;
+  __syncthreads();
+  if (s == 0) {
+    float2 t = red[px];
+    for (int q = 1; q < split; ++q) t = cadd(t, red[q * pix + px]);
+    r.gphat[(size_t)m * N * N + p] = cscale(t, scale);
+  }
 }
 
 // Per item: dL/dX = 2 pi * scale * sum over modes and blocks of the partials;
@@ -756,8 +769,16 @@ struct Launch {
       hipLaunchKernelGGL((k_far_loss<N, false>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.tw, step, L.loss_part, L.flags, L.item_off);
   }
   static void probe_grad(const LaunchCtx& L, float scale) {
-    dim3 g(N * N / kThreads, L.max_modes, L.n_reqs);
-    hipLaunchKernelGGL((k_probe_grad<N>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, scale);
+    // many (pixel block, mode) pairs: 256 pixels per workgroup, every thread
+    // walks all items; few: 64 pixels per workgroup and the items split 16 ways
+    static_assert((N * N) % 256 == 0, "pixel blocks must tile the probe");
+    const bool small = (N * N / 256) * L.max_modes * L.n_reqs < 1024;
+    if (small)
+      hipLaunchKernelGGL((k_probe_grad<N, 64, 16>), dim3(N * N / 64, L.max_modes, L.n_reqs), dim3(1024), 0, L.stream,
+                         L.items, L.reqs, L.ws, L.ramps, scale);
+    else
+      hipLaunchKernelGGL((k_probe_grad<N, 256, 1>), dim3(N * N / 256, L.max_modes, L.n_reqs), dim3(256), 0, L.stream,
+                         L.items, L.reqs, L.ws, L.ramps, scale);
   }
   static void plain2d(hipStream_t s, const float2* tw, const float2* src, float2* dst, int n_tiles, bool inverse,
                       float scale, bool accumulate) {
