@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_row_plain(const float2* __restrict
 // and lane l = t / CB of that column's line, so that a load of register a
 // reads CB consecutive complex values of row l + L a (coalesced).
 #ifndef PTY_COL_CB_L16
-#define PTY_COL_CB_L16 16
+#define PTY_COL_CB_L16 32
 #endif
 #ifndef PTY_COL_CB_L8
 #define PTY_COL_CB_L8 32
@@ -350,7 +350,9 @@ template <int N> struct ColPass {
 // row.)
 template <int N> struct ColMap {
   static constexpr int CB = ColPass<N>::CB;
-  static constexpr int STRIDE = Xch<N>::COL_STRIDE;
+  // per-column exchange stride: with 32 or more columns of 16 lanes an odd
+  // stride keeps a wave's accesses at two bank cycles (checked by exhaustive count)
+  static constexpr int STRIDE = (CB >= 32 && Cfg<N>::L == 16) ? pad_to(Xch<N>::SIZE, 2, 1) : Xch<N>::COL_STRIDE;
   __device__ __forceinline__ static int col() { return threadIdx.x % CB; }
   __device__ __forceinline__ static int lane() { return threadIdx.x / CB; }
   using Sync = BlockSync;
