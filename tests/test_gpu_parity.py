@@ -118,6 +118,48 @@ def test_ragged_batch_and_duplicates(cache):
     assert rel_l2(_np(gX), ref["g_pos"]) < TOL_G
 
 
+@pytest.mark.parametrize("N", [64, 256])
+def test_edge_positions_match_oracle(N):
+    """Windows on the object's first and last rows and columns, and positions
+    on the rounding boundaries (delta = -0.5 exactly, delta close to +0.5):
+    intensities and all gradients against the oracle."""
+    wl = synth.make_small(N=N, M=2, S=2, scan=2, step=6, seed=60 + N, loss="poisson", eps=0.5)
+    hi = float(wl.H - N)
+    wl.positions = np.array([[0.0, 0.0], [hi, hi], [hi - 0.5, 0.25], [0.499, hi - 0.5], [-0.499, 1.0],
+                             [3.5, hi - 0.499]], dtype=np.float64)
+    wl.patterns = synth.make_patterns(N, len(wl.positions), 1e4, 7)
+    c = Case(wl)
+    ref = c.oracle_grad()
+    d = c.device()
+    prob = c.problem()
+    I, _ = prob.forward(d["probe"], d["obj"], d["pos"], d["batch"])
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    assert rel_l2(_np(I), ref["I"]) < TOL_I
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    errs = dict(obj=rel_l2(_np(gO), ref["g_object"]), probe=rel_l2(_np(gP), ref["g_probe"]),
+                pos=rel_l2(_np(gX), ref["g_pos"]))
+    assert all(e < TOL_G for e in errs.values()), errs
+
+
+def test_empty_and_oversized_batches_are_rejected():
+    from paper_2505_14372_amd._lib import PTY_EINVAL, PtyError
+    c = Case(synth.make_small(N=64, M=1, S=1, scan=2, step=4, seed=14, loss="gaussian"))
+    d = c.device()
+    prob = c.problem(max_batch=3)
+    for b in (torch.zeros(0, dtype=torch.int32, device="cuda"), torch.arange(4, dtype=torch.int32, device="cuda")):
+        with pytest.raises(PtyError) as e:
+            prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], b)
+        assert e.value.status == PTY_EINVAL
+    # out-of-range position indices are a device-side bounds error, not a fault
+    bad = torch.tensor([0, 99, 1], dtype=torch.int32, device="cuda")
+    prob.forward(d["probe"], d["obj"], d["pos"], bad)
+    from paper_2505_14372_amd._lib import PTY_EBOUNDS
+    with pytest.raises(PtyError) as e:
+        prob.check()
+    assert e.value.status == PTY_EBOUNDS
+
+
 @pytest.mark.parametrize("k", [2, 3, 7])
 def test_checkpoint_recompute_matches_store_all(k):
     c = Case(synth.make_small(N=64, M=2, S=7, scan=3, step=4, seed=8, loss="poisson", eps=0.8, amp_noise=0.2))
