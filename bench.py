@@ -64,15 +64,17 @@ def parse():
     return p.parse_args()
 
 
-def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam"):
+def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spectral=False):
     """Algorithmic HBM bytes one launch of a kernel class must move (complex64
     tile T = 8 N^2 bytes, per launch over B positions and M modes; a
-    checkpoint is T, or T/2 when stored as half floats; LSQML adds the
+    checkpoint is T, or T/2 when stored as half floats; with spectral
+    checkpoints the forward column pass writes the checkpoint as its output
+    tile and the forward row pass stores nothing extra; LSQML adds the
     read-modify-write of a float illumination sum, T per position)."""
     T = 8 * N * N
     C = T // 2 if ck_half else T
     if name == "row_fwd":      # read + write every mode tile, write the entry-wave checkpoint, read the object patch
-        return B * (M * (2 * T + C) + T)
+        return B * (M * (2 * T + (0 if spectral else C)) + T)
     if name == "row_adj":      # read + write tiles, read checkpoints, read object patch, RMW object gradient
         return B * (M * (2 * T + C) + 3 * T) + (B * T if engine == "lsqml" else 0)
     if name in ("col_prop", "col_prop_adj"):   # read + write every tile
@@ -209,7 +211,8 @@ def main():
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_s = dom_ms / dom_n / 1000.0
-    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine)
+    spectral = prob.checkpoint_every == 1 and not prob.checkpoint_half and args.strategy != "resident"
+    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral)
     flops_launch = kernel_flops_per_launch(dom, N, M, B, S)
     gbs = bytes_launch / avg_s / 1e9
     tfl = flops_launch / avg_s / 1e12

@@ -295,6 +295,9 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
   L.pos_part = c->pos_part;
   L.flags = c->flags;
   L.resident = use_resident(c->strategy, c->g.N, c->ck_every) ? 1 : 0;
+  // every slice stored in float: the column passes write the entry waves' row
+  // spectra straight into the checkpoint slots (the resident chains ignore it)
+  L.ck_spec = (c->ck_every == 1 && !c->ck_half) ? 1 : 0;
   return L;
 }
 
@@ -332,12 +335,15 @@ void run_forward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<i
     }
     return;
   }
-  { ProfScope p(P_COL_SHIFT, L.stream); launch_col(L, N, COL_SHIFT, 0); }
+  // F: spectral checkpoints only when the entry waves are kept
+  LaunchCtx F = L;
+  F.ck_spec = save && L.ck_spec;
+  { ProfScope p(P_COL_SHIFT, L.stream); launch_col(F, N, COL_SHIFT, 0); }
   PsiStore st{};
-  st.mode = save ? 1 : 0;
+  st.mode = save ? (F.ck_spec ? 3 : 1) : 0;
   for (int i = 0; i < S_max; ++i) {
-    { ProfScope p(P_ROW_FWD, L.stream); launch_rows_fwd(L, N, i, st, false); }
-    if (i < S_max - 1) { ProfScope p(P_COL_PROP, L.stream); launch_col(L, N, COL_PROP, i); }
+    { ProfScope p(P_ROW_FWD, L.stream); launch_rows_fwd(F, N, i, st, false); }
+    if (i < S_max - 1) { ProfScope p(P_COL_PROP, L.stream); launch_col(F, N, COL_PROP, i); }
     if (std::find(far_steps.begin(), far_steps.end(), i) != far_steps.end()) {
       ProfScope p(P_FAR_LOSS, L.stream);
       launch_far_loss(L, N, i, save);
@@ -367,6 +373,7 @@ void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<
   for (int t = 0; t < S_max; ++t) {
     const int i = S_max - 1 - t;   // single-request slice index (k > 1 only)
     PsiLoad psi{};
+    psi.spec = L.ck_spec;
     if (k > 1 && i % k != 0) {
       const int i0 = (i / k) * k;
       const int i1 = std::min(i0 + k - 1, S_max - 1);
@@ -380,6 +387,7 @@ void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<
         st.src = L.ck;
         st.src_slot = i0 / k;
         R.emax = 0;
+        R.ck_spec = 0;
         launch_rows_fwd(R, N, i0, st, true);
         for (int s = i0 + 1; s <= i1; ++s) {
           launch_col(R, N, COL_PROP, s - 1);

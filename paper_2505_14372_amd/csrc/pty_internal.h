@@ -23,7 +23,7 @@ struct Item {
   float dy, dx;     // subpixel remainder of the position
   int valid;        // window inside the object
   int tile0;        // first workspace tile (modes follow)
-  long long ck0;    // first checkpoint tile (modes x stored slices follow)
+  long long ck0;    // first checkpoint tile: slot s of mode m is tile ck0 + m + s * (n_items * M)
 };
 
 // One reconstruction taking part in a launch. Passed by value in the kernel
@@ -58,9 +58,17 @@ struct ReqTable {
   ReqDev r[kMaxReqs];
 };
 
+// Checkpoint tile of (item, mode m, stored slot s). Slot-major within a
+// request, so the entry waves of one slice for the whole group are contiguous.
+__device__ __forceinline__ size_t ck_tile(const Item& it, const ReqDev& r, int m, int slot) {
+  return (size_t)it.ck0 + (size_t)m + (size_t)slot * ((size_t)r.n_items * (size_t)r.M);
+}
+
 // Where the forward row pass stores entry waves.
 struct PsiStore {
-  int mode;                 // 0: nowhere, 1: checkpoint slots, 2: segment buffer
+  int mode;                 // 0: nowhere, 1: checkpoint slots, 2: segment buffer,
+                            // 3: none, the input row spectrum is read from checkpoint slot i
+                            //    (spectral checkpoints, written by the column passes)
   void* seg;                // segment buffer [tiles][seg_len][N][N] (checkpoint storage type)
   int seg_len, seg_slot;
   const void* src;          // FROM_REAL source (checkpoint buffer)
@@ -71,6 +79,7 @@ struct PsiStore {
 // Where the adjoint row pass reads entry waves.
 struct PsiLoad {
   int from_seg;             // 0: checkpoint slot i / ck_every, 1: segment buffer
+  int spec;                 // the checkpoint slot holds the row spectrum F_x(psi_i) (float2)
   const void* seg;
   int seg_len, seg_base;    // slice i is at slot i - seg_base
 };
@@ -92,6 +101,9 @@ struct LaunchCtx {
   int* flags;
   int emax;                 // the first forward records the window maxima (ePIE)
   int wsum;                 // the adjoint row pass scatters the illumination (LSQML)
+  int ck_spec;              // spectral checkpoints: the forward column passes write the row
+                            // spectrum F_x(psi_i) of every entry wave into checkpoint slot i
+                            // (every slice stored, float2 storage, two-pass kernels)
 };
 
 void launch_items(const LaunchCtx& L, int N);

@@ -7,11 +7,16 @@
 //   propagator for the gap after slice i (already divided by N^2):
 //                                     prop[i*N*N + u_y*N + u_x]
 //   probe spectrum (unitary):         phat[m*N*N + u_y*N + u_x]
-//   entry-wave checkpoints:           ck[(ck0(b) + m*n_ck + slot) * N*N + ...]
+//   entry-wave checkpoints:           ck[(ck0(b) + m + slot * n_items * M) * N*N + ...]
+//                                     (slot-major: one slice's waves of the group are contiguous);
+//                                     with every slice stored in float they hold the row
+//                                     spectrum F_x(psi_i), written by the column passes
 //
 // One slice step is two passes over a tile, each a batched launch:
 //   row pass    : inverse row DFT -> entry wave psi_i (real space, optionally
 //                 checkpointed) -> times the object patch -> forward row DFT
+//                 (the adjoint row pass recovers psi_i from a spectral
+//                 checkpoint with the same inverse row DFT)
 //   column pass : forward column DFT -> times the propagator -> inverse
 //                 column DFT
 // so that F^-1 H F between slices costs one read and one write of the tile
@@ -111,7 +116,7 @@ __global__ void k_items(const ReqTable reqs, int n_reqs, Item* __restrict__ item
     it.dx = d1;
     it.valid = ok ? 1 : 0;
     it.tile0 = r.tile_base + local * r.M;
-    it.ck0 = r.ck_base + (long long)local * r.M * r.n_ck;
+    it.ck0 = r.ck_base + (long long)local * r.M;
     items[b] = it;
     if (!ok) raise_flag(flags, kFlagBounds);
   }
@@ -160,7 +165,6 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
   const float2* orow = r.obj + ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
 #pragma unroll
   for (int a = 0; a < E; ++a) o[a] = orow[l + L * a];
-  const int n_ck = r.n_ck;
   float pw[EMAX ? E : 1];
   if constexpr (EMAX) {
 #pragma unroll
@@ -170,16 +174,21 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
     if constexpr (FROM_REAL) {
-      const CT* src = static_cast<const CT*>(store.src) + (((size_t)it.ck0 + (size_t)m * n_ck + store.src_slot) * N + y) * N;
+      const CT* src = static_cast<const CT*>(store.src) + (ck_tile(it, r, m, store.src_slot) * N + y) * N;
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = Ck<HALF>::load(src + l + L * a);
     } else {
+      // the row spectrum comes from the work tile, or (spectral checkpoints)
+      // from checkpoint slot i, where the column pass left it
+      const float2* in = store.mode == 3
+                             ? static_cast<const float2*>(ck_) + (ck_tile(it, r, m, i) * N + y) * N
+                             : trow;
 #pragma unroll
-      for (int a = 0; a < E; ++a) v[a] = trow[l + L * a];
+      for (int a = 0; a < E; ++a) v[a] = in[l + L * a];
       line_fft<N, true>(v, l, tw, sx, WaveSync{});
     }
     if (store.mode == 1 && (i % r.ck_every) == 0) {
-      CT* dst = ck + (((size_t)it.ck0 + (size_t)m * n_ck + i / r.ck_every) * N + y) * N;
+      CT* dst = ck + (ck_tile(it, r, m, i / r.ck_every) * N + y) * N;
 #pragma unroll
       for (int a = 0; a < E; ++a) Ck<HALF>::store(dst + l + L * a, v[a]);
     } else if (store.mode == 2) {
@@ -224,7 +233,9 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 //   h = conj(O_i) g ; tile row = DFT_x(h)
 // With WSUM the illumination sum_m |psi_i,m|^2 of the window is also scattered
 // into r.wsum (LSQML).
-template <int N, bool HALF, bool WSUM = false>
+// With SPEC the checkpoint slot holds the row spectrum F_x(psi_i) (float2),
+// and psi_i is recovered with the forward pass's own inverse row DFT.
+template <int N, bool HALF, bool WSUM = false, bool SPEC = false>
 __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ items,
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, const void* __restrict__ ck_,
@@ -271,10 +282,18 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     line_fft<N, true>(v, l, tw, sx, WaveSync{});
     const CT* prow;
     if (psi.from_seg) prow = static_cast<const CT*>(psi.seg) + (((size_t)(it.tile0 + m) * psi.seg_len + (i - psi.seg_base)) * N + y) * N;
-    else prow = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i / r.ck_every) * N + y) * N;
+    else prow = ck + (ck_tile(it, r, m, i / r.ck_every) * N + y) * N;
+    float2 ps[SPEC ? E : 1];
+    if constexpr (SPEC) {
+#pragma unroll
+      for (int a = 0; a < E; ++a) ps[a] = Ck<false>::load(reinterpret_cast<const float2*>(prow) + l + L * a);
+      line_fft<N, true>(ps, l, tw, sx, WaveSync{});
+    }
 #pragma unroll
     for (int a = 0; a < E; ++a) {
-      float2 p = Ck<HALF>::load(prow + l + L * a);
+      float2 p;
+      if constexpr (SPEC) p = ps[a];
+      else p = Ck<HALF>::load(prow + l + L * a);
       if constexpr (WSUM) pw[a] += cabs2(p);
       acc[a] = cadd(acc[a], cjmul(p, v[a]));
       v[a] = cjmul(o[a], v[a]);
@@ -369,7 +388,8 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
                                                   const ReqTable reqs,
                                                   float2* __restrict__ ws, const float2* __restrict__ ramps,
                                                   const float2* __restrict__ twg, int step,
-                                                  float* __restrict__ pos_part, int item_off) {
+                                                  float* __restrict__ pos_part, int item_off,
+                                                  float2* __restrict__ ck_out) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
   __shared__ float2 tw[N];
   __shared__ float2 xch[CB * ColMap<N>::STRIDE];
@@ -446,8 +466,17 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
       }
     }
   }
+  // spectral checkpoints: the entry wave's row spectrum goes to checkpoint slot
+  // 0 (COL_SHIFT) or i + 1 (COL_PROP) instead of the work tile
+  float2* dst = tile;
+  if constexpr (OP == COL_SHIFT || OP == COL_PROP) {
+    if (ck_out) {
+      const int slot = OP == COL_SHIFT ? 0 : i + 1;
+      dst = ck_out + ck_tile(it, r, m, slot) * N * N;
+    }
+  }
 #pragma unroll
-  for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = v[a];
+  for (int a = 0; a < E; ++a) dst[(size_t)(l + L * a) * N + ux] = v[a];
 }
 
 // Plain column DFT of M probe-sized tiles (in place): tile = scale * DFT_y(tile).
@@ -743,6 +772,13 @@ struct Launch {
   }
   static void rows_adj(const LaunchCtx& L, int step, PsiLoad psi, float scale) {
     dim3 g(Pass<N>::NBLK, L.n_items);
+    if (psi.spec) {
+      if (L.wsum)
+        hipLaunchKernelGGL((k_row_adj<N, false, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+      else
+        hipLaunchKernelGGL((k_row_adj<N, false, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+      return;
+    }
     if (L.wsum) {
       if (L.ck_half)
         hipLaunchKernelGGL((k_row_adj<N, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
@@ -756,11 +792,12 @@ struct Launch {
   }
   static void col(const LaunchCtx& L, int op, int step) {
     dim3 g(ColPass<N>::NBLK, L.n_items, L.max_modes);
+    float2* ck_out = L.ck_spec ? static_cast<float2*>(L.ck) : nullptr;
     switch (op) {
-      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
-      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
-      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
-      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off); break;
+      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out); break;
+      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out); break;
+      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr); break;
+      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr); break;
     }
   }
   static void far_loss(const LaunchCtx& L, int step, bool grad) {
@@ -1499,7 +1536,7 @@ __global__ __launch_bounds__(Res<N>::THREADS) void k_res_fwd(const Item* __restr
       res_load_row<N>(v, tile, y, l);
       res_line_fft<N, true, L + 1, 1>(v, l, tw, tile + y * Res<N>::P);       // entry wave psi_i
       if (save && (i % r.ck_every) == 0) {
-        CT* dst = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i / r.ck_every) * N + y) * N;
+        CT* dst = ck + (ck_tile(it, r, m, i / r.ck_every) * N + y) * N;
 #pragma unroll
         for (int a = 0; a < E; ++a) Ck<HALF>::store(dst + l + L * a, v[a]);
       }
@@ -1556,7 +1593,7 @@ __global__ __launch_bounds__(Res<N>::THREADS) void k_res_adj(const Item* __restr
         res_load_row<N>(v, tile, y, l);
       }
       res_line_fft<N, true, L + 1, 1>(v, l, tw, tile + y * Res<N>::P);       // gradient wrt phi_i
-      const CT* prow = ck + (((size_t)it.ck0 + (size_t)m * r.n_ck + i) * N + y) * N;
+      const CT* prow = ck + (ck_tile(it, r, m, i) * N + y) * N;
       const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
       float* g = r.gobj ? reinterpret_cast<float*>(r.gobj + orow) : nullptr;
 #pragma unroll
