@@ -1066,6 +1066,7 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   L.ws = G->ws;
   L.ck = G->ck;
   L.ck_half = 0;
+  L.ck_spec = 1;   // every slice of every request stored in float
   L.resident = use_resident(items[0].ctx ? items[0].ctx->strategy : PTY_STRATEGY_AUTO, N, 1) ? 1 : 0;
   L.ramps = G->ramps;
   L.tw = G->tw;
