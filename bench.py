@@ -64,21 +64,35 @@ def parse():
     return p.parse_args()
 
 
-def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spectral=False):
-    """Algorithmic HBM bytes one launch of a kernel class must move (complex64
-    tile T = 8 N^2 bytes, per launch over B positions and M modes; a
-    checkpoint is T, or T/2 when stored as half floats; with spectral
-    checkpoints the forward column pass writes the checkpoint as its output
-    tile and the forward row pass stores nothing extra; LSQML adds the
-    read-modify-write of a float illumination sum, T per position)."""
+def live_fraction(N, bandlimit, S):
+    """Fraction of row-spectrum columns u_x that the circular band limit
+    (fraction of Nyquist) keeps; the others are zero after a propagation and
+    are neither written nor read."""
+    if S < 2 or bandlimit <= 0:
+        return 1.0
+    k = np.fft.fftfreq(N) * N
+    return float(np.mean(k * k <= (bandlimit * N / 2.0) ** 2 * (1 + 1e-9)))
+
+
+def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spectral=False, live=1.0):
+    """Algorithmic HBM bytes one launch of a kernel class must move at an
+    interior slice (complex64 tile T = 8 N^2 bytes, per launch over B
+    positions and M modes; a checkpoint is T, or T/2 when stored as half
+    floats; with spectral checkpoints the forward column pass writes the
+    checkpoint as its output tile and the forward row pass stores nothing
+    extra; of a band-limited row spectrum only the live fraction of columns
+    moves; LSQML adds the read-modify-write of a float illumination sum, T per
+    position)."""
     T = 8 * N * N
     C = T // 2 if ck_half else T
-    if name == "row_fwd":      # read + write every mode tile, write the entry-wave checkpoint, read the object patch
-        return B * (M * (2 * T + (0 if spectral else C)) + T)
-    if name == "row_adj":      # read + write tiles, read checkpoints, read object patch, RMW object gradient
-        return B * (M * (2 * T + C) + 3 * T) + (B * T if engine == "lsqml" else 0)
-    if name in ("col_prop", "col_prop_adj"):   # read + write every tile
-        return B * 2 * M * T
+    Tl = T * live
+    if name == "row_fwd":      # read (band-limited) + write every mode tile, [write the checkpoint], read the object patch
+        return int(B * (M * (Tl + T + (0 if spectral else C)) + T))
+    if name == "row_adj":      # read tile and checkpoint (band-limited), write tile, read object patch, RMW gradient
+        ck = Tl if spectral else C
+        return int(B * (M * (Tl + T + ck) + 3 * T) + (B * T if engine == "lsqml" else 0))
+    if name in ("col_prop", "col_prop_adj"):   # read + write the live columns of every tile
+        return int(B * 2 * M * Tl)
     if name == "far_loss":     # tiles read, far field written and re-read, seed written; pattern read
         return B * (4 * M * T + T // 2)
     if name == "col_shift":    # write every tile (the probe spectrum stays in cache)
@@ -212,7 +226,8 @@ def main():
     dom_ms, dom_n = prof[dom]
     avg_s = dom_ms / dom_n / 1000.0
     spectral = prob.checkpoint_every == 1 and not prob.checkpoint_half and args.strategy != "resident"
-    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral)
+    live = live_fraction(N, wl.bandlimit, S)
+    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral, live)
     flops_launch = kernel_flops_per_launch(dom, N, M, B, S)
     gbs = bytes_launch / avg_s / 1e9
     tfl = flops_launch / avg_s / 1e12

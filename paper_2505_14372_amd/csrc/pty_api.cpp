@@ -219,6 +219,7 @@ struct pty_ctx {
   double* deramp = nullptr;        // device [S][3] angles, then [S][deramp_blocks][4] partial sums
   float* reg_part = nullptr;       // cost partial sums
   float* emax = nullptr;           // ePIE window maxima [max_batch][S][2]
+  uint8_t* live = nullptr;         // [N] columns where the propagators are nonzero, or null (all)
   // LSQML scratch (pty_options.lsqml): illumination scatter [S][H][W],
   // transparency partials [kLsqSplit][N][N] and sum [N][N], step sums
   float* lsq_w = nullptr;
@@ -273,6 +274,7 @@ ReqDev base_req(pty_ctx* c) {
   r.inv_sigma2 = c->g.loss == PTY_LOSS_GAUSSIAN ? (float)(1.0 / (c->g.sigma * c->g.sigma)) : 1.f;
   r.ck_every = c->ck_every;
   r.n_ck = c->n_ck;
+  r.live = c->live;
   return r;
 }
 
@@ -523,10 +525,19 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   std::vector<uint8_t> mask;
   if (g->bandlimit_mask) mask.assign(g->bandlimit_mask, g->bandlimit_mask + N2);
   c->g.bandlimit_mask = nullptr;   // copied above; the caller's array is not kept
+  std::vector<uint8_t> live(N, 0);
   for (int i = 0; i < S - 1; ++i) {
     std::vector<float2> H = propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y, g->tilt_x, mask);
     if (hipMemcpy(c->prop + (size_t)i * N2, H.data(), N2 * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       return fail(PTY_EHIP);
+    for (size_t e = 0; e < N2; ++e)
+      if (H[e].x != 0.f || H[e].y != 0.f) live[e % N] = 1;
+  }
+  // columns of the row spectrum that every propagator zeroes (band limit):
+  // the propagation column passes skip them and their consumers read zeros
+  if (S > 1 && std::find(live.begin(), live.end(), 0) != live.end()) {
+    if ((st = dmalloc(&c->live, (size_t)N, e))) return fail(st);
+    if (hipMemcpy(c->live, live.data(), N, hipMemcpyHostToDevice) != hipSuccess) return fail(PTY_EHIP);
   }
   if (hipMemset(c->flags, 0, 4 * sizeof(int)) != hipSuccess) return fail(PTY_EHIP);
   *out = c;
@@ -561,7 +572,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->tw); dfree(c->prop); dfree(c->phat); dfree(c->gphat); dfree(c->gprobe); dfree(c->gobj);
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
-  dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax);
+  dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
   dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums);
   delete c;
 }

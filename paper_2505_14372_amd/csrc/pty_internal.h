@@ -52,6 +52,9 @@ struct ReqDev {
   float* emax;              // [n_items][S][2] window maxima of sum_m |psi_i|^2 and |O_i|^2 (ePIE) or null
   int modulus;              // far-field weight: 0 loss gradient, 1 modulus update (ePIE, LSQML)
   float* wsum;              // [S][H][W] scatter of sum_m |psi_i|^2 (LSQML) or null
+  const uint8_t* live;      // [N] 1 where the propagators' column u_x has a nonzero value, or null
+                            // (no band limit): a propagation column pass leaves the other
+                            // columns of its output unwritten, and their consumers read zeros
 };
 
 struct ReqTable {

@@ -160,6 +160,14 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
   const int l = threadIdx.x % L, line = threadIdx.x / L;
   const int y = blockIdx.x * LINES + line;
   float2* sx = xch + line * Xch<N>::ROW_STRIDE;
+  // the row spectrum of slice i >= 1 was written by a propagation column pass,
+  // which leaves the columns outside the propagator's support unwritten (zero)
+  unsigned lmask = ~0u;
+  if (r.live && i >= 1) {
+    lmask = 0u;
+#pragma unroll
+    for (int a = 0; a < E; ++a) lmask |= (r.live[l + L * a] ? 1u : 0u) << a;
+  }
   // object patch row, shared by every mode
   float2 o[E];
   const float2* orow = r.obj + ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
                              ? static_cast<const float2*>(ck_) + (ck_tile(it, r, m, i) * N + y) * N
                              : trow;
 #pragma unroll
-      for (int a = 0; a < E; ++a) v[a] = in[l + L * a];
+      for (int a = 0; a < E; ++a) v[a] = (lmask >> a) & 1u ? in[l + L * a] : make_float2(0.f, 0.f);
       line_fft<N, true>(v, l, tw, sx, WaveSync{});
     }
     if (store.mode == 1 && (i % r.ck_every) == 0) {
@@ -255,6 +263,17 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   float2* sx = xch + line * Xch<N>::ROW_STRIDE;
   using CT = typename Ck<HALF>::T;
   const CT* ck = static_cast<const CT*>(ck_);
+  // columns outside the propagator's support: zero in g for i < S - 1 (it came
+  // through an adjoint propagation column pass) and in a spectral checkpoint
+  // for i >= 1 (written by a forward one); those columns were never written
+  unsigned live = ~0u;
+  if (r.live) {
+    live = 0u;
+#pragma unroll
+    for (int a = 0; a < E; ++a) live |= (r.live[l + L * a] ? 1u : 0u) << a;
+  }
+  const unsigned gmask = (r.live && i < r.S - 1) ? live : ~0u;
+  const unsigned cmask = (r.live && i >= 1) ? live : ~0u;
   float2 acc[E];
   const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
   // ePIE: object step divided by max sum_m |psi_i|^2, wave step by max |O_i|^2
@@ -278,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
 #pragma unroll
-    for (int a = 0; a < E; ++a) v[a] = trow[l + L * a];
+    for (int a = 0; a < E; ++a) v[a] = (gmask >> a) & 1u ? trow[l + L * a] : make_float2(0.f, 0.f);
     line_fft<N, true>(v, l, tw, sx, WaveSync{});
     const CT* prow;
     if (psi.from_seg) prow = static_cast<const CT*>(psi.seg) + (((size_t)(it.tile0 + m) * psi.seg_len + (i - psi.seg_base)) * N + y) * N;
@@ -286,7 +305,9 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     float2 ps[SPEC ? E : 1];
     if constexpr (SPEC) {
 #pragma unroll
-      for (int a = 0; a < E; ++a) ps[a] = Ck<false>::load(reinterpret_cast<const float2*>(prow) + l + L * a);
+      for (int a = 0; a < E; ++a)
+        ps[a] = (cmask >> a) & 1u ? Ck<false>::load(reinterpret_cast<const float2*>(prow) + l + L * a)
+                                  : make_float2(0.f, 0.f);
       line_fft<N, true>(ps, l, tw, sx, WaveSync{});
     }
 #pragma unroll
@@ -402,12 +423,22 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   if constexpr (OP == COL_PROP) { i = step; if (i >= r.S - 1) return; }
   if constexpr (OP == COL_PROP_ADJ) { i = r.S - 1 - step; if (i < 1) return; }
   if constexpr (OP == COL_FINAL) { if (r.S - 1 - step != 0) return; }
+  if constexpr (OP == COL_PROP || OP == COL_PROP_ADJ) {
+    // outside the propagator's support the output columns are zero: a
+    // workgroup with no live column has nothing to do (its consumers read zeros)
+    if (r.live) {
+      bool any = false;
+      for (int q = 0; q < CB; ++q) any |= r.live[blockIdx.x * CB + q] != 0;
+      if (!any) return;
+    }
+  }
   load_twiddles<N>(tw, twg);
   __syncthreads();
   const int c = ColMap<N>::col(), l = ColMap<N>::lane();
   const int ux = blockIdx.x * CB + c;
   float2* sx = xch + c * ColMap<N>::STRIDE;
   float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
+  const bool live_col = (OP == COL_PROP || OP == COL_PROP_ADJ) ? (!r.live || r.live[ux] != 0) : true;
   float2 v[E];
   if constexpr (OP == COL_SHIFT) {
     const float2* ry = ramps + (size_t)b * 2 * N;
@@ -422,7 +453,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
     line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
   } else {
 #pragma unroll
-    for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
+    for (int a = 0; a < E; ++a) v[a] = live_col ? tile[(size_t)(l + L * a) * N + ux] : make_float2(0.f, 0.f);
     line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
     if constexpr (OP == COL_PROP || OP == COL_PROP_ADJ) {
       const float2* H = r.prop + (size_t)(OP == COL_PROP ? i : i - 1) * N * N;
@@ -475,8 +506,10 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
       dst = ck_out + ck_tile(it, r, m, slot) * N * N;
     }
   }
+  if (live_col) {
 #pragma unroll
-  for (int a = 0; a < E; ++a) dst[(size_t)(l + L * a) * N + ux] = v[a];
+    for (int a = 0; a < E; ++a) dst[(size_t)(l + L * a) * N + ux] = v[a];
+  }
 }
 
 // Plain column DFT of M probe-sized tiles (in place): tile = scale * DFT_y(tile).
