@@ -86,11 +86,11 @@ def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spec
     T = 8 * N * N
     C = T // 2 if ck_half else T
     Tl = T * live
-    if name == "row_fwd":      # read (band-limited) + write every mode tile, [write the checkpoint], read the object patch
-        return int(B * (M * (Tl + T + (0 if spectral else C)) + T))
-    if name == "row_adj":      # read tile and checkpoint (band-limited), write tile, read object patch, RMW gradient
+    if name == "row_fwd":      # read + write every mode tile (both band-limited), [write the checkpoint], read the object patch
+        return int(B * (M * (2 * Tl + (0 if spectral else C)) + T))
+    if name == "row_adj":      # read tile and checkpoint, write tile (all band-limited), read object patch, RMW gradient
         ck = Tl if spectral else C
-        return int(B * (M * (Tl + T + ck) + 3 * T) + (B * T if engine == "lsqml" else 0))
+        return int(B * (M * (2 * Tl + ck) + 3 * T) + (B * T if engine == "lsqml" else 0))
     if name in ("col_prop", "col_prop_adj"):   # read + write the live columns of every tile
         return int(B * 2 * M * Tl)
     if name == "far_loss":     # tiles read, far field written and re-read, seed written; pattern read

@@ -162,12 +162,16 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
   float2* sx = xch + line * Xch<N>::ROW_STRIDE;
   // the row spectrum of slice i >= 1 was written by a propagation column pass,
   // which leaves the columns outside the propagator's support unwritten (zero)
-  unsigned lmask = ~0u;
-  if (r.live && i >= 1) {
-    lmask = 0u;
+  unsigned live = ~0u;
+  if (r.live) {
+    live = 0u;
 #pragma unroll
-    for (int a = 0; a < E; ++a) lmask |= (r.live[l + L * a] ? 1u : 0u) << a;
+    for (int a = 0; a < E; ++a) live |= (r.live[l + L * a] ? 1u : 0u) << a;
   }
+  const unsigned lmask = i >= 1 ? live : ~0u;
+  // the output of slices i < S - 1 feeds only the propagation column pass,
+  // which reads the live columns alone
+  const unsigned omask = i < r.S - 1 ? live : ~0u;
   // object patch row, shared by every mode
   float2 o[E];
   const float2* orow = r.obj + ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
@@ -213,7 +217,8 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
     for (int a = 0; a < E; ++a) v[a] = cmul(v[a], o[a]);
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
 #pragma unroll
-    for (int a = 0; a < E; ++a) trow[l + L * a] = v[a];
+    for (int a = 0; a < E; ++a)
+      if ((omask >> a) & 1u) trow[l + L * a] = v[a];
   }
   if constexpr (EMAX) {
     float mp = 0.f, mo = 0.f;
@@ -274,6 +279,9 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   }
   const unsigned gmask = (r.live && i < r.S - 1) ? live : ~0u;
   const unsigned cmask = (r.live && i >= 1) ? live : ~0u;
+  // the output of slices i >= 1 feeds only the adjoint propagation column
+  // pass, which reads the live columns alone (slice 0 feeds the final one)
+  const unsigned omask = cmask;
   float2 acc[E];
   const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
   // ePIE: object step divided by max sum_m |psi_i|^2, wave step by max |O_i|^2
@@ -321,7 +329,8 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     }
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
 #pragma unroll
-    for (int a = 0; a < E; ++a) trow[l + L * a] = v[a];
+    for (int a = 0; a < E; ++a)
+      if ((omask >> a) & 1u) trow[l + L * a] = v[a];
   }
   if (r.gobj) {
     float* g = reinterpret_cast<float*>(r.gobj + orow);
