@@ -104,12 +104,14 @@ def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spec
     return 0
 
 
-def kernel_flops_per_launch(name, N, M, B, S):
-    """FFT flops of one launch by the 5 n log2 n convention per 1D transform."""
+def kernel_flops_per_launch(name, N, M, B, S, spectral=False):
+    """FFT flops of one launch by the 5 n log2 n convention per 1D transform
+    (the adjoint row pass transforms three lines per row with spectral
+    checkpoints: g, the recovered entry wave and h)."""
     per_line = 5 * N * np.log2(N)
     lines = B * M * N
-    n_fft = {"row_fwd": 2, "row_adj": 2, "col_prop": 2, "col_prop_adj": 2, "far_loss": 2, "col_shift": 1,
-             "col_final": 1}.get(name, 0)
+    n_fft = {"row_fwd": 2, "row_adj": 3 if spectral else 2, "col_prop": 2, "col_prop_adj": 2, "far_loss": 2,
+             "col_shift": 1, "col_final": 1}.get(name, 0)
     return n_fft * lines * per_line
 
 
@@ -228,7 +230,7 @@ def main():
     spectral = prob.checkpoint_every == 1 and not prob.checkpoint_half and args.strategy != "resident"
     live = live_fraction(N, wl.bandlimit, S)
     bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral, live)
-    flops_launch = kernel_flops_per_launch(dom, N, M, B, S)
+    flops_launch = kernel_flops_per_launch(dom, N, M, B, S, spectral)
     gbs = bytes_launch / avg_s / 1e9
     tfl = flops_launch / avg_s / 1e12
     if gbs / HBM_PEAK_GBS >= tfl / FP32_PEAK_TFLOPS:
