@@ -4,7 +4,7 @@ probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 512]
                     [--no-cpu-baseline] [--cpu-positions 16]
-                    [--workload cfg3_ms256|cfg2_ms192|cfg1_ms128|cfg0_spoa64|serving]
+                    [--workload ms256_m8_s30|ms192_m6_s20|ms128_m4_s8|spoa64|serving]
                     [--engine adam|sgd|epie|lsqml] [--regularize]
                     [--checkpoint-every k] [--checkpoint-half] [--strategy ...] [--chunk n]
 
@@ -45,7 +45,7 @@ def parse():
     p.add_argument("--steps", type=int, default=32)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--batch", type=int, default=0, help="positions per group (0: the workload's)")
-    p.add_argument("--workload", default="cfg3_ms256")
+    p.add_argument("--workload", default="ms256_m8_s30")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-positions", type=int, default=16)
     p.add_argument("--checkpoint-every", type=int, default=1)
@@ -279,7 +279,7 @@ def kernel_source_hash():
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_cfg3_ms256_b512.md")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_ms256_m8_s30_b512.md")
     try:
         text = open(path).read()
         data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])

@@ -165,11 +165,11 @@ LAMBDA_300KV = 0.019688
 
 # name: (N, M, S, dz, scan, step, jitter, phi_max, dose, loss, eps, batch, seed, weights)
 CONFIGS = {
-    "cfg0_spoa64": (64, 1, 1, 0.0, 16, 4, 0.0, 0.3, 1e4, "amplitude", 0.0, 256, 0, None),
-    "cfg1_ms128": (128, 4, 8, 2.0, 32, 8, 0.5, 0.1, 1e5, "poisson", 0.8, 1024, 1,
+    "spoa64": (64, 1, 1, 0.0, 16, 4, 0.0, 0.3, 1e4, "amplitude", 0.0, 256, 0, None),
+    "ms128_m4_s8": (128, 4, 8, 2.0, 32, 8, 0.5, 0.1, 1e5, "poisson", 0.8, 1024, 1,
                    (0.6, 0.2, 0.12, 0.08)),
-    "cfg2_ms192": (192, 6, 20, 2.0, 64, 11, 0.5, 0.1, 1e5, "poisson", 0.8, 256, 2, None),
-    "cfg3_ms256": (256, 8, 30, 1.0, 128, 8, 0.5, 0.1, 1e6, "poisson", 0.8, 512, 3, None),
+    "ms192_m6_s20": (192, 6, 20, 2.0, 64, 11, 0.5, 0.1, 1e5, "poisson", 0.8, 256, 2, None),
+    "ms256_m8_s30": (256, 8, 30, 1.0, 128, 8, 0.5, 0.1, 1e6, "poisson", 0.8, 512, 3, None),
 }
 
 

@@ -16,8 +16,8 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.fixture(scope="module")
-def cfg2():
-    wl = synth.make_workload("cfg2_ms192", with_patterns=True, pattern_pool=16)
+def ms192():
+    wl = synth.make_workload("ms192_m6_s20", with_patterns=True, pattern_pool=16)
     # a minibatch of 4 positions keeps the FP64 checks within seconds
     return Case(wl, batch=[1000, 1001, 1065, 2222])
 
@@ -34,9 +34,9 @@ def _run(c, budget=0):
     return prob, loss.item(), obj.grad.cpu().numpy(), probe.grad.cpu().numpy(), pos.grad.cpu().numpy()
 
 
-def test_autograd_matches_oracle_and_finite_differences(cfg2):
-    c = cfg2
-    print(f"cfg2 N={c.N} M={c.M} S={c.S} H={c.H} B={len(c.batch)}", flush=True)
+def test_autograd_matches_oracle_and_finite_differences(ms192):
+    c = ms192
+    print(f"ms192 N={c.N} M={c.M} S={c.S} H={c.H} B={len(c.batch)}", flush=True)
     prob, loss, gO, gP, gX = _run(c)
     assert prob.checkpoint_every == 1
     ref = c.oracle_grad()
@@ -94,8 +94,8 @@ def test_autograd_matches_oracle_and_finite_differences(cfg2):
         assert err < 1e-3, (group, err)
 
 
-def test_autograd_recompute_under_budget_matches(cfg2):
-    c = cfg2
+def test_autograd_recompute_under_budget_matches(ms192):
+    c = ms192
     from paper_2505_14372_amd import api
     full = api.workspace_bytes(c.N, c.M, c.S, c.H, c.W, len(c.pos), len(c.batch), 1)
     a = _run(c)
@@ -106,9 +106,9 @@ def test_autograd_recompute_under_budget_matches(cfg2):
         assert rel_l2(y, x) < 1e-6
 
 
-def test_autograd_rejects_stale_tape(cfg2):
+def test_autograd_rejects_stale_tape(ms192):
     from paper_2505_14372_amd.autograd import multislice_loss
-    c = cfg2
+    c = ms192
     d = c.device()
     prob = c.problem()
     obj = d["obj"].clone().requires_grad_(True)
@@ -118,10 +118,10 @@ def test_autograd_rejects_stale_tape(cfg2):
         l1.backward()
 
 
-def test_torch_optimizer_step_decreases_loss(cfg2):
+def test_torch_optimizer_step_decreases_loss(ms192):
     """A few Adam steps of torch.optim on the autograd loss reduce it."""
     from paper_2505_14372_amd.autograd import multislice_loss
-    c = cfg2
+    c = ms192
     d = c.device()
     prob = c.problem()
     obj = d["obj"].clone().requires_grad_(True)

@@ -20,7 +20,7 @@ B = 512
 
 @pytest.fixture(scope="module")
 def full():
-    wl = synth.make_workload("cfg3_ms256", pattern_pool=64)
+    wl = synth.make_workload("ms256_m8_s30", pattern_pool=64)
     rng = np.random.default_rng(3)
     batch = np.sort(rng.choice(wl.J, size=B, replace=False)).astype(np.int32)
     c = Case(wl, batch=batch)
