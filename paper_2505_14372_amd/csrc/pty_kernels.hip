@@ -83,6 +83,32 @@ template <> struct Ck<true> {
   __device__ __forceinline__ static float2 load(const T* p) { return __half22float2(*p); }
 };
 
+// Raw buffer view of one tile (base uniform across the workgroup): an offset
+// at or past the end (kOff) reads zero and drops a store without touching
+// memory, so the lanes of band-limited columns in a column pass need no
+// branch. (In the row passes the same form raised register use and was
+// slower than plain masked accesses.)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kOff = 0x80000000u;
+struct TileBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ TileBuf(const void* base, unsigned bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)) {}
+  __device__ __forceinline__ float2 ld(unsigned off) const {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+  }
+  __device__ __forceinline__ void st(unsigned off, float2 x) const {
+    const u32x2 v = {__float_as_uint(x.x), __float_as_uint(x.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+  }
+};
+// byte offset of element (y, x) of an N x N tile, or kOff when the lane is masked off
+template <int N>
+__device__ __forceinline__ unsigned tile_off(bool on, int y, int x) {
+  return on ? (unsigned)((y * N + x) * 8) : kOff;
+}
+
 // ============================================================ items
 
 // One workgroup per batch entry: find its request, integer window offset and
@@ -461,8 +487,11 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
     }
     line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
   } else {
+    {
+      const TileBuf tb(tile, N * N * 8);
 #pragma unroll
-    for (int a = 0; a < E; ++a) v[a] = live_col ? tile[(size_t)(l + L * a) * N + ux] : make_float2(0.f, 0.f);
+      for (int a = 0; a < E; ++a) v[a] = tb.ld(tile_off<N>(live_col, l + L * a, ux));
+    }
     line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
     if constexpr (OP == COL_PROP || OP == COL_PROP_ADJ) {
       const float2* H = r.prop + (size_t)(OP == COL_PROP ? i : i - 1) * N * N;
@@ -515,10 +544,9 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
       dst = ck_out + ck_tile(it, r, m, slot) * N * N;
     }
   }
-  if (live_col) {
+  const TileBuf out(dst, N * N * 8);
 #pragma unroll
-    for (int a = 0; a < E; ++a) dst[(size_t)(l + L * a) * N + ux] = v[a];
-  }
+  for (int a = 0; a < E; ++a) out.st(tile_off<N>(live_col, l + L * a, ux), v[a]);
 }
 
 // Plain column DFT of M probe-sized tiles (in place): tile = scale * DFT_y(tile).
