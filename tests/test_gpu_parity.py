@@ -142,6 +142,30 @@ def test_edge_positions_match_oracle(N):
     assert all(e < TOL_G for e in errs.values()), errs
 
 
+@pytest.mark.parametrize("N", [64, 256])
+def test_stale_workspace_is_never_read(N):
+    """Columns outside the propagator's support are neither written nor read:
+    after a call whose detector weights are NaN everywhere (every work tile
+    and checkpoint full of NaN), the next call on the same context still
+    matches the oracle, so no consumer picked up a column it was not given."""
+    from paper_2505_14372_amd._lib import PTY_ENONFINITE, PtyError
+    c = Case(synth.make_small(N=N, M=2, S=3, scan=2, step=6, seed=70 + N, loss="gaussian", amp_noise=0.2))
+    ref = c.oracle_grad()
+    d = c.device()
+    prob = c.problem()
+    bad = torch.full_like(d["pats"], float("nan"))
+    prob.loss_and_grad(d["probe"], d["obj"], d["pos"], bad, d["batch"])
+    with pytest.raises(PtyError) as e:
+        prob.check()
+    assert e.value.status == PTY_ENONFINITE
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    errs = dict(obj=rel_l2(_np(gO), ref["g_object"]), probe=rel_l2(_np(gP), ref["g_probe"]),
+                pos=rel_l2(_np(gX), ref["g_pos"]))
+    assert all(e_ < TOL_G for e_ in errs.values()), errs
+
+
 def test_empty_and_oversized_batches_are_rejected():
     from paper_2505_14372_amd._lib import PTY_EINVAL, PtyError
     c = Case(synth.make_small(N=64, M=1, S=1, scan=2, step=4, seed=14, loss="gaussian"))
