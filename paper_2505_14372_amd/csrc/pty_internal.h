@@ -60,6 +60,9 @@ struct ReqDev {
 struct ReqTable {
   ReqDev r[kMaxReqs];
 };
+// passed by value with a few pointers and ints beside it: keep the kernel
+// arguments under 4 KiB
+static_assert(sizeof(ReqTable) + 256 <= 4096, "request table too large for the kernel arguments");
 
 // Checkpoint tile of (item, mode m, stored slot s). Slot-major within a
 // request, so the entry waves of one slice for the whole group are contiguous.
