@@ -561,3 +561,36 @@ def test_lsqml_needs_its_scratch():
     with pytest.raises(_lib.PtyError) as e:
         prob.lsqml_step(st, il, d["pats"], d["batch"])
     assert e.value.status == _lib.PTY_ESTATE
+
+
+@pytest.mark.parametrize("engine", ["epie", "lsqml"])
+def test_conventional_engines_under_resident_strategy_and_chunks(engine):
+    """The conventional engines always run on the two-pass kernels: asking for
+    the LDS-resident chains and a chunked schedule changes nothing."""
+    from paper_2505_14372_amd import api
+    c = Case(synth.make_small(N=64, M=2, S=3, scan=3, step=5, seed=80, loss="amplitude", amp_noise=0.3))
+    d = c.device()
+    prob = c.problem(max_batch=len(c.batch), lsqml=engine == "lsqml")
+    prob.set_strategy("resident")
+    prob.set_chunk(4)
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    b = [0, 2, 3, 5, 6, 8]
+    P0, O0, X0 = c.o_args()
+    pats = c.pats.astype(np.float64)
+    bt = torch.tensor(b, dtype=torch.int32, device="cuda")
+    if engine == "epie":
+        prob.reconstruct_step(st, d["pats"], bt, api.Optimizer(kind="epie", lr_object=0.8, lr_probe=0.5))
+        ref, _ = orc.reconstruct_step(dict(probe=P0, object=O0, positions=X0), pats, b, c.geom,
+                                      dict(kind="epie", lr_object=0.8, lr_probe=0.5, lr_pos=0.0))
+    else:
+        il = api.IllumSums(c.S, c.H, c.W, c.N)
+        kw = dict(beta_object=0.5, beta_probe=0.5, delta_object=1e-2, delta_probe=1e-2, gamma=0.0)
+        prob.lsqml_step(st, il, d["pats"], bt, **kw)
+        oil = dict(obj_prev=None, probe_prev=None, obj_cur=np.zeros((c.S, c.H, c.W)), probe_cur=np.zeros((c.N, c.N)),
+                   first=True)
+        ref, _, _ = orc.lsqml_step(dict(probe=P0, object=O0, positions=X0), oil, pats, b, c.geom, **kw)
+    prob.check()
+    dO = _np(st.object).astype(np.complex128) - O0
+    dP = _np(st.probe).astype(np.complex128) - P0
+    assert rel_l2(dO, ref["object"] - O0) < TOL_G
+    assert rel_l2(dP, ref["probe"] - P0) < TOL_G
