@@ -13,7 +13,10 @@
  *   - the exact vector-Jacobian product of Sec. 3.2 back to the object, the
  *     probe modes and the positions, with overlapping object gradients
  *     scatter-added;
- *   - one optimiser step (SGD or Adam, Sec. 3.2) on all three variables.
+ *   - one optimiser step (SGD or Adam, Sec. 3.2) on all three variables,
+ *     with the cost and constraint regularizers of Sec. 3.4;
+ *   - the conventional engines of Sec. 3.3 on the same kernels: ePIE / 3PIE
+ *     (pty_reconstruct_step, PTY_OPT_EPIE) and LSQML (pty_lsqml_step).
  *
  * Conventions (fixed readings of the paper):
  *   - complex numbers are interleaved float32 pairs (pty_c64);
@@ -38,7 +41,8 @@
  *   - every array argument is a DEVICE pointer to C-contiguous memory owned
  *     by the caller, except pty_geometry.dz (host, copied at create);
  *   - the library allocates device memory only in pty_create /
- *     pty_group_create (workspace sized for max_batch), never in a call;
+ *     pty_group_create (workspace sized for max_batch) and in
+ *     pty_set_regularizers (masks and filter taps), never in a step;
  *   - calls are asynchronous and stream-ordered on the given hipStream_t
  *     (passed as void*; NULL = the null stream); scalar results (loss) are
  *     written to device doubles;
@@ -113,7 +117,10 @@ typedef struct pty_ctx pty_ctx;
 
 /* Create a context for one geometry with workspace for groups of up to
  * max_batch positions. checkpoint_every = 1 stores every slice's entry wave
- * during the forward pass; k > 1 stores every k-th and recomputes the others
+ * during the forward pass (in float storage as its row spectrum, which the
+ * forward pass produces anyway, so storing costs no extra write; the
+ * backward pass recovers the wave with an inverse row DFT); k > 1 stores
+ * every k-th and recomputes the others
  * segment by segment in the backward pass; 0 picks 1 if the workspace fits
  * in hbm_budget bytes (0 = no limit), else the smallest k that fits.
  * Builds the propagator tables on the device. */
@@ -133,7 +140,7 @@ typedef struct {
 } pty_options;
 
 /* pty_create with the options above; pty_create(g, b, k, budget, out) equals
- * pty_create_ex with checkpoint_half = 0. */
+ * pty_create_ex with checkpoint_half = 0 and lsqml = 0. */
 pty_status pty_create_ex(const pty_geometry* g, const pty_options* opt, pty_ctx** out);
 pty_status pty_workspace_bytes_ex(const pty_geometry* g, const pty_options* opt, size_t* bytes);
 /* Checkpoint storage chosen at create (1 = half floats). */
