@@ -136,7 +136,7 @@ typedef struct {
                                 half floats (round to nearest), halving their HBM
                                 traffic; only the object gradient reads them */
   int32_t lsqml;             /* 1: also allocate the scratch of pty_lsqml_step
-                                (S*H*W + 33*N*N floats and a few sums) */
+                                ((S+1)*H*W + 33*N*N floats and a few sums) */
 } pty_options;
 
 /* pty_create with the options above; pty_create(g, b, k, budget, out) equals

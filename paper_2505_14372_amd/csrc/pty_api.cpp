@@ -117,6 +117,7 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8, bo
     const size_t HW = (size_t)g->obj_h * g->obj_w;
     b += align256((size_t)S * HW * sizeof(float));                     // illumination scatter
     b += align256((size_t)(kLsqSplit + 1) * N2 * sizeof(float));       // transparency partials + sum
+    b += align256(HW * sizeof(float));                                 // transparency map
     b += align256(((size_t)S * lsq_blocks(HW) * 3 + 2 * S + 2) * sizeof(double));
   }
   s.bytes = b;
@@ -225,6 +226,7 @@ struct pty_ctx {
   float* lsq_w = nullptr;
   float* lsq_part = nullptr;
   float* lsq_wp = nullptr;
+  float* lsq_tau = nullptr;
   double* lsq_sums = nullptr;
   // tape of pty_forward_save
   bool tape_valid = false;
@@ -506,7 +508,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   if (o->lsqml) {
     const size_t HW = (size_t)g->obj_h * g->obj_w;
     if ((st = dmalloc(&c->lsq_w, (size_t)S * HW, e)) || (st = dmalloc(&c->lsq_part, (size_t)kLsqSplit * N2, e)) ||
-        (st = dmalloc(&c->lsq_wp, N2, e)) ||
+        (st = dmalloc(&c->lsq_wp, N2, e)) || (st = dmalloc(&c->lsq_tau, HW, e)) ||
         (st = dmalloc(&c->lsq_sums, (size_t)S * lsq_blocks(HW) * 3 + 2 * S + 2, e)))
       return fail(st);
   }
@@ -573,7 +575,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
   dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
-  dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums);
+  dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums); dfree(c->lsq_tau);
   delete c;
 }
 
@@ -983,7 +985,8 @@ extern "C" pty_status pty_lsqml_step(pty_ctx* c, void* stream, pty_state* st, co
   { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, c->gphat, c->gprobe, M, true, 1.f / N, false); }
   {
     ProfScope p(P_OPTIM, s);
-    launch_lsq_transparency(s, c->items, B, (const float2*)st->object, S, g.obj_h, g.obj_w, N, c->lsq_part, c->lsq_wp);
+    launch_lsq_transparency(s, c->items, B, (const float2*)st->object, S, g.obj_h, g.obj_w, N, c->lsq_tau,
+                            c->lsq_part, c->lsq_wp);
     // lsq_sums: [S*nb*3 + S] sums and maxima of the object step, [S] alpha_i, [2] probe alpha and max
     const size_t nb3 = (size_t)S * lsq_blocks(HW) * 3 + S;
     launch_lsq_object(s, (float2*)st->object, c->gobj, c->lsq_w, il->obj_cur, il->obj_prev, S, HW, dO, o->gamma,

@@ -151,11 +151,12 @@ int deramp_blocks(int H, int W);
 void launch_deramp(hipStream_t s, float2* O, int S, int H, int W, double* theta, double* part);
 
 // LSQML (Sec. 3.3) after the adjoint chain. Transparency sum over the group's
-// valid items (first n_items of items): wp[r] = sum_j prod_i |O_i(n_j + r)|^2,
+// valid items (first n_items of items): wp[r] = sum_j tau(n_j + r) with
+// tau = prod_i |O_i|^2 computed once per object pixel (tau: H * W floats);
 // part holds kLsqSplit * N * N floats.
 constexpr int kLsqSplit = 32;
 void launch_lsq_transparency(hipStream_t s, const Item* items, int n_items, const float2* O, int S, int H,
-                             int W, int N, float* part, float* wp);
+                             int W, int N, float* tau, float* part, float* wp);
 // Object step: D = -g (g the chain's object accumulator), A = prev or cur + w,
 // A' = A + delta max A per slice, alpha_i from double sums (part: S *
 // lsq_blocks(H * W) * 3 + S doubles of partial sums, partial maxima and

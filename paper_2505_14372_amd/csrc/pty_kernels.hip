@@ -1217,11 +1217,21 @@ __global__ void k_deramp_apply(float2* __restrict__ O, int S, int H, int W, cons
 
 // ------------------------------------------------------------ LSQML (Sec. 3.3)
 
-// Transparency of the object stack in the probe view, partial sums over the
-// items b = split, split + kLsqSplit, ...: part[split][r] = sum_b prod_i |O_i(n_b + r)|^2.
+// Transparency of the object stack per object pixel: tau(x) = prod_i |O_i(x)|^2
+// (slices multiplied in order).
+__global__ void k_lsq_tau(const float2* __restrict__ O, int S, size_t HW, float* __restrict__ tau) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < HW; e += (size_t)gridDim.x * blockDim.x) {
+    float t = 1.f;
+    for (int i = 0; i < S; ++i) t *= cabs2(O[(size_t)i * HW + e]);
+    tau[e] = t;
+  }
+}
+
+// Transparency in the probe view, partial sums over the items b = split,
+// split + kLsqSplit, ...: part[split][r] = sum_b tau(n_b + r).
 __global__ __launch_bounds__(kThreads) void k_lsq_transp(const Item* __restrict__ items, int n_items,
-                                                          const float2* __restrict__ O, int S, int H, int W,
-                                                          int N, float* __restrict__ part) {
+                                                          const float* __restrict__ tau, int W, int N,
+                                                          float* __restrict__ part) {
   const int r = blockIdx.x * kThreads + threadIdx.x;
   if (r >= N * N) return;
   const int ry = r / N, rx = r % N;
@@ -1229,10 +1239,7 @@ __global__ __launch_bounds__(kThreads) void k_lsq_transp(const Item* __restrict_
   for (int b = blockIdx.y; b < n_items; b += kLsqSplit) {
     const Item it = items[b];
     if (!it.valid) continue;
-    const float2* o = O + (size_t)(it.ny + ry) * W + it.nx + rx;
-    float t = 1.f;
-    for (int i = 0; i < S; ++i) t *= cabs2(o[(size_t)i * H * W]);
-    acc += t;
+    acc += tau[(size_t)(it.ny + ry) * W + it.nx + rx];
   }
   part[(size_t)blockIdx.y * N * N + r] = acc;
 }
@@ -1472,10 +1479,12 @@ void launch_deramp(hipStream_t s, float2* O, int S, int H, int W, double* theta,
   hipLaunchKernelGGL(k_deramp_apply, dim3(reg_blocks((size_t)S * H * W)), dim3(kThreads), 0, s, O, S, H, W, theta);
 }
 void launch_lsq_transparency(hipStream_t s, const Item* items, int n_items, const float2* O, int S, int H,
-                             int W, int N, float* part, float* wp) {
+                             int W, int N, float* tau, float* part, float* wp) {
   const int N2 = N * N;
+  const size_t HW = (size_t)H * W;
+  hipLaunchKernelGGL(k_lsq_tau, dim3(reg_blocks(HW)), dim3(kThreads), 0, s, O, S, HW, tau);
   hipLaunchKernelGGL(k_lsq_transp, dim3((N2 + kThreads - 1) / kThreads, kLsqSplit), dim3(kThreads), 0, s, items,
-                     n_items, O, S, H, W, N, part);
+                     n_items, tau, W, N, part);
   hipLaunchKernelGGL(k_lsq_transp_sum, dim3((N2 + kThreads - 1) / kThreads), dim3(kThreads), 0, s, part, N2, wp);
 }
 int lsq_blocks(size_t n) {

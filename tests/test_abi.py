@@ -55,9 +55,10 @@ def test_workspace_sizes_follow_the_layout(lib):
     b6 = api.workspace_bytes(N, M, S, H, W, J, B, checkpoint_every=6)
     assert b6 - b0 >= B * M * (2 + 5 + 5) * tile
     assert b6 < b1
-    # the LSQML scratch: an illumination scatter of the object's size plus small sums
+    # the LSQML scratch: an illumination scatter of the object's size, a transparency map
+    # of one slice's size, plus small sums
     bl = api.workspace_bytes(N, M, S, H, W, J, B, checkpoint_every=1, lsqml=True)
-    assert S * H * W * 4 <= bl - b1 < S * H * W * 4 + 40 * N * N * 4 + 2 ** 20
+    assert (S + 1) * H * W * 4 <= bl - b1 < (S + 1) * H * W * 4 + 40 * N * N * 4 + 2 ** 20
 
 
 def test_invalid_arguments_are_rejected_on_the_host(lib):
