@@ -55,27 +55,68 @@ std::vector<float2> roots(int N) {
 // forward and inverse 2D DFTs around it):
 // H(u) = B(u) exp(-i pi lambda dz |q|^2 + 2 pi i dz (q_y tan t_y + q_x tan t_x)),
 // q = f(u) / dx, B the circular band limit on signed integer bins or the mask.
+int signed_bin(int u, int N) { return u < (N + 1) / 2 ? u : u - N; }
+
+// Band limit B(u): the circle of radius frac * N / 2 on signed integer bins,
+// everything (frac <= 0), or the caller's mask.
+bool keep_bin(int N, double frac, const std::vector<uint8_t>& mask, int y, int x) {
+  if (!mask.empty()) return mask[(size_t)y * N + x] != 0;
+  if (frac <= 0.0) return true;
+  const double r = frac * N / 2.0;
+  const int ky = signed_bin(y, N), kx = signed_bin(x, N);
+  return (double)(ky * ky + kx * kx) <= r * r * (1.0 + 1e-9);
+}
+
 std::vector<float2> propagator(int N, double dx, double lam, double dz, double frac, double tilt_y,
                                double tilt_x, const std::vector<uint8_t>& mask) {
   std::vector<float2> H((size_t)N * N);
-  const double r = frac * N / 2.0;
-  const double r2 = r * r * (1.0 + 1e-9);
   const double inv_n2 = 1.0 / ((double)N * (double)N);
   const double ty = std::tan(tilt_y), tx = std::tan(tilt_x);
   for (int y = 0; y < N; ++y) {
-    const int ky = y < (N + 1) / 2 ? y : y - N;
+    const int ky = signed_bin(y, N);
     const double qy = (double)ky / N / dx;
     for (int x = 0; x < N; ++x) {
-      const int kx = x < (N + 1) / 2 ? x : x - N;
+      const int kx = signed_bin(x, N);
       const double qx = (double)kx / N / dx;
-      const bool keep = mask.empty() ? (frac <= 0.0 || (double)(ky * ky + kx * kx) <= r2)
-                                     : mask[(size_t)y * N + x] != 0;
+      const bool keep = keep_bin(N, frac, mask, y, x);
       const double ph = -kPiD * lam * dz * (qy * qy + qx * qx) + 2.0 * kPiD * dz * (qy * ty + qx * tx);
       H[(size_t)y * N + x] = keep ? make_float2((float)(std::cos(ph) * inv_n2), (float)(std::sin(ph) * inv_n2))
                                   : make_float2(0.f, 0.f);
     }
   }
   return H;
+}
+
+// The phase of H is a sum of a k_y and a k_x term, so H = B(u) Hy(k_y) Hx(k_x).
+// When every row y of the band limit keeps exactly the bins |k_x| <= K_y (a
+// circle, no limit, or a mask of that shape), the column passes rebuild H
+// from the two factors and K_y instead of reading the N x N table:
+// py[y] = (Hy / N^2, K_y as int bits, 0) with K_y = -1 for an empty row,
+// px[x] = Hx. Returns false when the band limit is not of that form.
+bool separable_propagator(int N, double dx, double lam, double dz, double frac, double tilt_y, double tilt_x,
+                          const std::vector<uint8_t>& mask, std::vector<float4>& py, std::vector<float2>& px) {
+  py.assign(N, make_float4(0.f, 0.f, 0.f, 0.f));
+  px.assign(N, make_float2(0.f, 0.f));
+  const double inv_n2 = 1.0 / ((double)N * (double)N);
+  const double ty = std::tan(tilt_y), tx = std::tan(tilt_x);
+  for (int y = 0; y < N; ++y) {
+    int K = -1;
+    for (int x = 0; x < N; ++x)
+      if (keep_bin(N, frac, mask, y, x)) K = std::max(K, std::abs(signed_bin(x, N)));
+    for (int x = 0; x < N; ++x)
+      if (keep_bin(N, frac, mask, y, x) != (std::abs(signed_bin(x, N)) <= K)) return false;
+    const double q = (double)signed_bin(y, N) / N / dx;
+    const double ph = -kPiD * lam * dz * q * q + 2.0 * kPiD * dz * q * ty;
+    float kb;
+    std::memcpy(&kb, &K, sizeof kb);
+    py[y] = make_float4((float)(std::cos(ph) * inv_n2), (float)(std::sin(ph) * inv_n2), kb, 0.f);
+  }
+  for (int x = 0; x < N; ++x) {
+    const double q = (double)signed_bin(x, N) / N / dx;
+    const double ph = -kPiD * lam * dz * q * q + 2.0 * kPiD * dz * q * tx;
+    px[x] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+  }
+  return true;
 }
 
 struct Sizes {
@@ -99,6 +140,8 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8, bo
   size_t b = 0;
   b += align256(g->N * sizeof(float2));                             // roots
   b += align256((size_t)std::max(S - 1, 0) * N2 * sizeof(float2));  // propagators
+  b += align256((size_t)std::max(S - 1, 0) * g->N * sizeof(float4));   // separable factors (y)
+  b += align256((size_t)std::max(S - 1, 0) * g->N * sizeof(float2));   // separable factors (x)
   b += 3 * align256((size_t)M * N2 * sizeof(float2));               // phat, gphat, gprobe
   b += align256((size_t)S * g->obj_h * g->obj_w * sizeof(float2));  // object gradient
   b += align256((size_t)g->n_positions * 2 * sizeof(float));        // dense position gradient
@@ -221,6 +264,9 @@ struct pty_ctx {
   float* reg_part = nullptr;       // cost partial sums
   float* emax = nullptr;           // ePIE window maxima [max_batch][S][2]
   uint8_t* live = nullptr;         // [N] columns where the propagators are nonzero, or null (all)
+  int live_k = -1;                 // live columns are |k_x| <= live_k (-1: look them up in live)
+  float4* prop_y = nullptr;        // [S-1][N] separable propagator factors, or null (table only)
+  float2* prop_x = nullptr;        // [S-1][N]
   // LSQML scratch (pty_options.lsqml): illumination scatter [S][H][W],
   // transparency partials [kLsqSplit][N][N] and sum [N][N], step sums
   float* lsq_w = nullptr;
@@ -277,6 +323,9 @@ ReqDev base_req(pty_ctx* c) {
   r.ck_every = c->ck_every;
   r.n_ck = c->n_ck;
   r.live = c->live;
+  r.live_k = c->live_k;
+  r.prop_y = c->prop_y;
+  r.prop_x = c->prop_x;
   return r;
 }
 
@@ -528,18 +577,43 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   if (g->bandlimit_mask) mask.assign(g->bandlimit_mask, g->bandlimit_mask + N2);
   c->g.bandlimit_mask = nullptr;   // copied above; the caller's array is not kept
   std::vector<uint8_t> live(N, 0);
+  std::vector<float4> py_all;
+  std::vector<float2> px_all;
+  bool sep = S > 1;
   for (int i = 0; i < S - 1; ++i) {
     std::vector<float2> H = propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y, g->tilt_x, mask);
     if (hipMemcpy(c->prop + (size_t)i * N2, H.data(), N2 * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       return fail(PTY_EHIP);
     for (size_t e = 0; e < N2; ++e)
       if (H[e].x != 0.f || H[e].y != 0.f) live[e % N] = 1;
+    std::vector<float4> py;
+    std::vector<float2> px;
+    if (sep && separable_propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y, g->tilt_x, mask,
+                                    py, px)) {
+      py_all.insert(py_all.end(), py.begin(), py.end());
+      px_all.insert(px_all.end(), px.begin(), px.end());
+    } else {
+      sep = false;
+    }
+  }
+  if (sep) {
+    if ((st = dmalloc(&c->prop_y, py_all.size(), e)) || (st = dmalloc(&c->prop_x, px_all.size(), e))) return fail(st);
+    if (hipMemcpy(c->prop_y, py_all.data(), py_all.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->prop_x, px_all.data(), px_all.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(PTY_EHIP);
   }
   // columns of the row spectrum that every propagator zeroes (band limit):
   // the propagation column passes skip them and their consumers read zeros
   if (S > 1 && std::find(live.begin(), live.end(), 0) != live.end()) {
     if ((st = dmalloc(&c->live, (size_t)N, e))) return fail(st);
     if (hipMemcpy(c->live, live.data(), N, hipMemcpyHostToDevice) != hipSuccess) return fail(PTY_EHIP);
+    // a symmetric band |k_x| <= K (any circular limit) is tested without the table
+    int K = -1;
+    for (int x = 0; x < N; ++x)
+      if (live[x]) K = std::max(K, std::abs(signed_bin(x, N)));
+    bool interval = true;
+    for (int x = 0; x < N; ++x) interval &= (live[x] != 0) == (std::abs(signed_bin(x, N)) <= K);
+    c->live_k = interval ? K : -1;
   }
   if (hipMemset(c->flags, 0, 4 * sizeof(int)) != hipSuccess) return fail(PTY_EHIP);
   *out = c;
@@ -575,6 +649,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
   dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
+  dfree(c->prop_y); dfree(c->prop_x);
   dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums); dfree(c->lsq_tau);
   delete c;
 }

@@ -55,6 +55,9 @@ struct ReqDev {
   const uint8_t* live;      // [N] 1 where the propagators' column u_x has a nonzero value, or null
                             // (no band limit): a propagation column pass leaves the other
                             // columns of its output unwritten, and their consumers read zeros
+  int live_k;               // >= 0: the live columns are exactly |k_x| <= live_k (no table lookup)
+  const float4* prop_y;     // [S-1][N] (Hy / N^2, K_y bits, 0): H = [|k_x| <= K_y] Hy Hx, or null
+  const float2* prop_x;     // [S-1][N] Hx
 };
 
 struct ReqTable {

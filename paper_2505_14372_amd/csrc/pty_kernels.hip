@@ -103,6 +103,29 @@ struct TileBuf {
     __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
   }
 };
+// Is column x of the row spectrum inside the propagators' support?
+template <int N>
+__device__ __forceinline__ bool col_live(const ReqDev& r, int x) {
+  if (!r.live) return true;
+  if (r.live_k >= 0) return abs(x < (N + 1) / 2 ? x : x - N) <= r.live_k;
+  return r.live[x] != 0;
+}
+
+// Row-pass load of x[l + L a] for the register slots a set in `mask`, zero in
+// the others. A masked slot loads the lane's slot-0 element of the same row
+// instead (a line the wave reads anyway), so the loads are unconditional: no
+// per-slot branch, and the compiler may issue them together.
+template <int N>
+__device__ __forceinline__ void load_row_masked(float2 (&v)[Cfg<N>::E], const float2* row, int l, unsigned mask) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
+#pragma unroll
+  for (int a = 0; a < E; ++a) {
+    const bool on = (mask >> a) & 1u;
+    const float2 t = row[on ? l + L * a : l];
+    v[a] = on ? t : make_float2(0.f, 0.f);
+  }
+}
+
 // byte offset of element (y, x) of an N x N tile, or kOff when the lane is masked off
 template <int N>
 __device__ __forceinline__ unsigned tile_off(bool on, int y, int x) {
@@ -192,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
   if (r.live) {
     live = 0u;
 #pragma unroll
-    for (int a = 0; a < E; ++a) live |= (r.live[l + L * a] ? 1u : 0u) << a;
+    for (int a = 0; a < E; ++a) live |= (col_live<N>(r, l + L * a) ? 1u : 0u) << a;
   }
   const unsigned lmask = i >= 1 ? live : ~0u;
   // the output of slices i < S - 1 feeds only the propagation column pass,
@@ -301,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   if (r.live) {
     live = 0u;
 #pragma unroll
-    for (int a = 0; a < E; ++a) live |= (r.live[l + L * a] ? 1u : 0u) << a;
+    for (int a = 0; a < E; ++a) live |= (col_live<N>(r, l + L * a) ? 1u : 0u) << a;
   }
   const unsigned gmask = (r.live && i < r.S - 1) ? live : ~0u;
   const unsigned cmask = (r.live && i >= 1) ? live : ~0u;
@@ -329,21 +352,17 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   }
   for (int m = 0; m < r.M; ++m) {
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
-    float2 v[E];
-#pragma unroll
-    for (int a = 0; a < E; ++a) v[a] = (gmask >> a) & 1u ? trow[l + L * a] : make_float2(0.f, 0.f);
-    line_fft<N, true>(v, l, tw, sx, WaveSync{});
     const CT* prow;
     if (psi.from_seg) prow = static_cast<const CT*>(psi.seg) + (((size_t)(it.tile0 + m) * psi.seg_len + (i - psi.seg_base)) * N + y) * N;
     else prow = ck + (ck_tile(it, r, m, i / r.ck_every) * N + y) * N;
+    // both rows are requested before the first transform (its LDS fences
+    // would otherwise hold the second request back by a whole memory latency)
+    float2 v[E];
     float2 ps[SPEC ? E : 1];
-    if constexpr (SPEC) {
-#pragma unroll
-      for (int a = 0; a < E; ++a)
-        ps[a] = (cmask >> a) & 1u ? Ck<false>::load(reinterpret_cast<const float2*>(prow) + l + L * a)
-                                  : make_float2(0.f, 0.f);
-      line_fft<N, true>(ps, l, tw, sx, WaveSync{});
-    }
+    load_row_masked<N>(v, trow, l, gmask);
+    if constexpr (SPEC) load_row_masked<N>(ps, reinterpret_cast<const float2*>(prow), l, cmask);
+    line_fft<N, true>(v, l, tw, sx, WaveSync{});
+    if constexpr (SPEC) line_fft<N, true>(ps, l, tw, sx, WaveSync{});
 #pragma unroll
     for (int a = 0; a < E; ++a) {
       float2 p;
@@ -446,10 +465,13 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
                                                   const float2* __restrict__ twg, int step,
                                                   float* __restrict__ pos_part, int item_off,
                                                   float2* __restrict__ ck_out) {
-  constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB;
+  constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB, T = ColPass<N>::THREADS;
+  constexpr bool PROP = OP == COL_PROP || OP == COL_PROP_ADJ;
+  static_assert(T >= N, "the staged tables take one entry per thread");
   __shared__ float2 tw[N];
+  __shared__ float4 hy[PROP ? N : 1];
   __shared__ float2 xch[CB * ColMap<N>::STRIDE];
-  __shared__ float red[2][ColPass<N>::THREADS / 64];
+  __shared__ float red[2][T / 64];
   const int b = item_off + blockIdx.y, m = blockIdx.z;
   const Item it = items[b];
   const ReqDev& r = reqs.r[it.req];
@@ -458,23 +480,51 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   if constexpr (OP == COL_PROP) { i = step; if (i >= r.S - 1) return; }
   if constexpr (OP == COL_PROP_ADJ) { i = r.S - 1 - step; if (i < 1) return; }
   if constexpr (OP == COL_FINAL) { if (r.S - 1 - step != 0) return; }
-  if constexpr (OP == COL_PROP || OP == COL_PROP_ADJ) {
+  if constexpr (PROP) {
     // outside the propagator's support the output columns are zero: a
     // workgroup with no live column has nothing to do (its consumers read zeros)
     if (r.live) {
       bool any = false;
-      for (int q = 0; q < CB; ++q) any |= r.live[blockIdx.x * CB + q] != 0;
+      if (r.live_k >= 0) {
+        for (int q = 0; q < CB; ++q) {
+          const int x = blockIdx.x * CB + q;
+          any |= abs(x < (N + 1) / 2 ? x : x - N) <= r.live_k;
+        }
+      } else {
+        for (int q = 0; q < CB; ++q) any |= r.live[blockIdx.x * CB + q] != 0;
+      }
       if (!any) return;
     }
   }
-  load_twiddles<N>(tw, twg);
-  __syncthreads();
-  const int c = ColMap<N>::col(), l = ColMap<N>::lane();
+  const int c = ColMap<N>::col(), l = ColMap<N>::lane(), t = threadIdx.x;
   const int ux = blockIdx.x * CB + c;
   float2* sx = xch + c * ColMap<N>::STRIDE;
   float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
-  const bool live_col = (OP == COL_PROP || OP == COL_PROP_ADJ) ? (!r.live || r.live[ux] != 0) : true;
+  const bool live_col = PROP ? col_live<N>(r, ux) : true;
+  // Memory requests in the order they are needed, all before the first wait:
+  // the staged tables (twiddles; the y factors and row limits of a separable
+  // propagator), this column's x factor, then the tile column.
+  const int gap = OP == COL_PROP ? i : i - 1;
+  const bool sep = PROP && r.prop_y != nullptr;
+  float2 tw_t = make_float2(0.f, 0.f);
+  float4 hy_t = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 hx = make_float2(0.f, 0.f);
+  if (t < N) {
+    tw_t = twg[t];
+    if (sep) hy_t = r.prop_y[(size_t)gap * N + t];
+  }
+  if (sep) hx = r.prop_x[(size_t)gap * N + ux];
   float2 v[E];
+  if constexpr (OP != COL_SHIFT) {
+    const TileBuf tb(tile, N * N * 8);
+#pragma unroll
+    for (int a = 0; a < E; ++a) v[a] = tb.ld(tile_off<N>(live_col, l + L * a, ux));
+  }
+  if (t < N) {
+    tw[t] = tw_t;
+    if constexpr (PROP) hy[t] = hy_t;
+  }
+  __syncthreads();
   if constexpr (OP == COL_SHIFT) {
     const float2* ry = ramps + (size_t)b * 2 * N;
     const float2 rx = ramps[(size_t)b * 2 * N + N + ux];
@@ -487,18 +537,25 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
     }
     line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
   } else {
-    {
-      const TileBuf tb(tile, N * N * 8);
-#pragma unroll
-      for (int a = 0; a < E; ++a) v[a] = tb.ld(tile_off<N>(live_col, l + L * a, ux));
-    }
     line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
-    if constexpr (OP == COL_PROP || OP == COL_PROP_ADJ) {
-      const float2* H = r.prop + (size_t)(OP == COL_PROP ? i : i - 1) * N * N;
+    if constexpr (PROP) {
+      if (sep) {
+        // H = [|k_x| <= K_y] Hy(k_y) Hx(k_x), factors staged above
+        const int akx = abs(ux < (N + 1) / 2 ? ux : ux - N);
 #pragma unroll
-      for (int a = 0; a < E; ++a) {
-        float2 h = H[(size_t)(l + L * a) * N + ux];
-        v[a] = (OP == COL_PROP) ? cmul(v[a], h) : cjmul(h, v[a]);
+        for (int a = 0; a < E; ++a) {
+          const float4 q = hy[l + L * a];
+          float2 h = cmul(make_float2(q.x, q.y), hx);
+          if (akx > __float_as_int(q.z)) h = make_float2(0.f, 0.f);
+          v[a] = (OP == COL_PROP) ? cmul(v[a], h) : cjmul(h, v[a]);
+        }
+      } else {
+        const float2* H = r.prop + (size_t)gap * N * N;
+#pragma unroll
+        for (int a = 0; a < E; ++a) {
+          float2 h = H[(size_t)(l + L * a) * N + ux];
+          v[a] = (OP == COL_PROP) ? cmul(v[a], h) : cjmul(h, v[a]);
+        }
       }
       line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
     } else {  // COL_FINAL

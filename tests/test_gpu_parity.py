@@ -44,6 +44,13 @@ def _case(name):
         k = np.fft.fftfreq(128) * 128
         wl.bandlimit_mask = (np.abs(k)[:, None] <= 40) & (np.abs(k)[None, :] <= 40)
         return Case(wl)
+    if name == "n64_offset_mask":      # a band-limit mask whose rows are not centred intervals
+        wl = synth.make_small(N=64, M=2, S=3, scan=3, step=5, seed=7, loss="poisson", eps=0.8, phi_max=0.2,
+                              dose=1e5)
+        k = np.fft.fftfreq(64) * 64
+        wl.bandlimit_mask = ((k[None, :] >= -10) & (k[None, :] <= 20) & (np.abs(k)[:, None] <= 18)) | \
+            ((np.abs(k)[None, :] <= 3) & (np.abs(k)[:, None] <= 25))
+        return Case(wl)
     if name == "n64_amp_eps_nobl":
         return Case(synth.make_small(N=64, M=2, S=3, scan=3, step=5, seed=5, loss="amplitude", eps=0.5,
                                      bandlimit=0.0, amp_noise=0.1))
@@ -51,7 +58,7 @@ def _case(name):
 
 
 CASES = ["n64_spoa_amp", "n64_ms_poisson", "n128_ms_poisson", "n192_ms_anscombe", "n256_ms_gaussian",
-         "n64_amp_eps_nobl", "n128_tilt_mask_dz"]
+         "n64_amp_eps_nobl", "n128_tilt_mask_dz", "n64_offset_mask"]
 
 
 @pytest.fixture(scope="module")
