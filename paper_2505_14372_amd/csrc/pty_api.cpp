@@ -265,6 +265,7 @@ struct pty_ctx {
   float* emax = nullptr;           // ePIE window maxima [max_batch][S][2]
   uint8_t* live = nullptr;         // [N] columns where the propagators are nonzero, or null (all)
   int live_k = -1;                 // live columns are |k_x| <= live_k (-1: look them up in live)
+  unsigned live_blocks = 0;        // column-pass blocks holding a live column (bit per block; 0: all)
   float4* prop_y = nullptr;        // [S-1][N] separable propagator factors, or null (table only)
   float2* prop_x = nullptr;        // [S-1][N]
   // LSQML scratch (pty_options.lsqml): illumination scatter [S][H][W],
@@ -351,6 +352,7 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
   // every slice stored in float: the column passes write the entry waves' row
   // spectra straight into the checkpoint slots (the resident chains ignore it)
   L.ck_spec = (c->ck_every == 1 && !c->ck_half) ? 1 : 0;
+  L.col_live_blocks = c->live_blocks;
   return L;
 }
 
@@ -614,6 +616,10 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
     bool interval = true;
     for (int x = 0; x < N; ++x) interval &= (live[x] != 0) == (std::abs(signed_bin(x, N)) <= K);
     c->live_k = interval ? K : -1;
+    const int nb = col_blocks(N), cb = N / nb;
+    for (int q = 0; q < nb; ++q)
+      for (int x = q * cb; x < (q + 1) * cb; ++x)
+        if (live[x]) c->live_blocks |= 1u << q;
   }
   if (hipMemset(c->flags, 0, 4 * sizeof(int)) != hipSuccess) return fail(PTY_EHIP);
   *out = c;
@@ -1203,6 +1209,12 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   L.n_reqs = n;
   L.n_items = item0;
   L.max_modes = M_max;
+  // a column block runs when any request has a live column in it
+  L.col_live_blocks = 0;
+  for (int q = 0; q < n; ++q) {
+    if (items[q].ctx->live_blocks == 0) { L.col_live_blocks = 0; break; }
+    L.col_live_blocks |= items[q].ctx->live_blocks;
+  }
   for (int q = 0; q < n; ++q) {
     pty_ctx* c = items[q].ctx;
     launch_plain2d(N, s, G->tw, (const float2*)items[q].state->probe, c->phat, c->g.n_modes, false, 1.f / N, false);

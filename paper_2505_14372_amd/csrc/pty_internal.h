@@ -110,6 +110,8 @@ struct LaunchCtx {
   int* flags;
   int emax;                 // the first forward records the window maxima (ePIE)
   int wsum;                 // the adjoint row pass scatters the illumination (LSQML)
+  unsigned col_live_blocks; // column blocks a propagation column pass runs (bit q: columns of
+                            // block q; 0: all), the union over the launch's requests
   int ck_spec;              // spectral checkpoints: the forward column passes write the row
                             // spectrum F_x(psi_i) of every entry wave into checkpoint slot i
                             // (every slice stored, float2 storage, two-pass kernels)

@@ -464,10 +464,13 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
                                                   float2* __restrict__ ws, const float2* __restrict__ ramps,
                                                   const float2* __restrict__ twg, int step,
                                                   float* __restrict__ pos_part, int item_off,
-                                                  float2* __restrict__ ck_out) {
+                                                  float2* __restrict__ ck_out, unsigned long long colmap) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB, T = ColPass<N>::THREADS;
   constexpr bool PROP = OP == COL_PROP || OP == COL_PROP_ADJ;
   static_assert(T >= N, "the staged tables take one entry per thread");
+  static_assert(ColPass<N>::NBLK <= 8, "the column-block map holds 8 entries");
+  // column block of this workgroup: entry blockIdx.x of the launch's block list
+  const int cb = (int)((colmap >> (8 * blockIdx.x)) & 0xffu);
   __shared__ float2 tw[N];
   __shared__ float4 hy[PROP ? N : 1];
   __shared__ float2 xch[CB * ColMap<N>::STRIDE];
@@ -487,17 +490,17 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
       bool any = false;
       if (r.live_k >= 0) {
         for (int q = 0; q < CB; ++q) {
-          const int x = blockIdx.x * CB + q;
+          const int x = cb * CB + q;
           any |= abs(x < (N + 1) / 2 ? x : x - N) <= r.live_k;
         }
       } else {
-        for (int q = 0; q < CB; ++q) any |= r.live[blockIdx.x * CB + q] != 0;
+        for (int q = 0; q < CB; ++q) any |= r.live[cb * CB + q] != 0;
       }
       if (!any) return;
     }
   }
   const int c = ColMap<N>::col(), l = ColMap<N>::lane(), t = threadIdx.x;
-  const int ux = blockIdx.x * CB + c;
+  const int ux = cb * CB + c;
   float2* sx = xch + c * ColMap<N>::STRIDE;
   float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
   const bool live_col = PROP ? col_live<N>(r, ux) : true;
@@ -586,7 +589,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
       if (threadIdx.x == 0) {
         float t0 = 0.f, t1 = 0.f;
         for (int w = 0; w < ColPass<N>::THREADS / 64; ++w) { t0 += red[0][w]; t1 += red[1][w]; }
-        float* dst = pos_part + ((size_t)(it.tile0 + m) * ColPass<N>::NBLK + blockIdx.x) * 2;
+        float* dst = pos_part + ((size_t)(it.tile0 + m) * ColPass<N>::NBLK + cb) * 2;
         dst[0] = t0;
         dst[1] = t1;
       }
@@ -918,13 +921,23 @@ struct Launch {
     }
   }
   static void col(const LaunchCtx& L, int op, int step) {
-    dim3 g(ColPass<N>::NBLK, L.n_items, L.max_modes);
+    // A propagation pass runs only the column blocks holding a live column,
+    // listed one after the other in blockIdx.x: consecutive workgroups go to
+    // the XCDs in turn, so every XCD gets an equal share of the live blocks
+    // (with the whole range, block q would always land on XCD q).
+    const unsigned live = (op == COL_PROP || op == COL_PROP_ADJ) ? L.col_live_blocks : 0u;
+    unsigned long long map = 0;
+    int nb = 0;
+    for (int q = 0; q < ColPass<N>::NBLK; ++q)
+      if (!live || ((live >> q) & 1u)) map |= (unsigned long long)q << (8 * nb++);
+    if (nb == 0) return;
+    dim3 g(nb, L.n_items, L.max_modes);
     float2* ck_out = L.ck_spec ? static_cast<float2*>(L.ck) : nullptr;
     switch (op) {
-      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out); break;
-      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out); break;
-      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr); break;
-      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr); break;
+      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map); break;
+      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map); break;
+      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map); break;
+      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map); break;
     }
   }
   static void far_loss(const LaunchCtx& L, int step, bool grad) {
