@@ -7,6 +7,7 @@ probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
                     [--workload ms256_m8_s30|ms192_m6_s20|ms128_m4_s8|spoa64|serving]
                     [--engine adam|sgd|epie|lsqml] [--regularize]
                     [--checkpoint-every k] [--checkpoint-half] [--strategy ...] [--chunk n]
+                    [--reduction auto|atomic|ordered]
 
 A step is one reconstruct_step over one group of `batch` positions drawn
 from a seeded permutation of the 128 x 128 scan (16384 positions = 32 groups
@@ -51,6 +52,9 @@ def parse():
     p.add_argument("--checkpoint-every", type=int, default=1)
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--strategy", default="auto", choices=["auto", "two_pass", "resident"])
+    p.add_argument("--reduction", default="auto", choices=["auto", "atomic", "ordered"],
+                   help="object-gradient accumulation: float atomics or the bit-reproducible ordered sum; "
+                        "auto takes the one measured faster for the workload (atomic at 256^2, else ordered)")
     p.add_argument("--checkpoint-half", action="store_true",
                    help="store entry-wave checkpoints as IEEE half pairs (reduced-precision storage)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -74,7 +78,8 @@ def live_fraction(N, bandlimit, S):
     return float(np.mean(k * k <= (bandlimit * N / 2.0) ** 2 * (1 + 1e-9)))
 
 
-def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spectral=False, live=1.0):
+def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spectral=False, live=1.0,
+                            ordered=False):
     """Algorithmic HBM bytes one launch of a kernel class must move at an
     interior slice (complex64 tile T = 8 N^2 bytes, per launch over B
     positions and M modes; a checkpoint is T, or T/2 when stored as half
@@ -82,7 +87,9 @@ def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spec
     checkpoint as its output tile and the forward row pass stores nothing
     extra; of a band-limited row spectrum only the live fraction of columns
     moves; LSQML adds the read-modify-write of a float illumination sum, T per
-    position)."""
+    position; with the ordered reduction the adjoint row pass stores each
+    position's object-gradient contribution, T, instead of adding it into the
+    gradient, 2T)."""
     T = 8 * N * N
     C = T // 2 if ck_half else T
     Tl = T * live
@@ -90,7 +97,7 @@ def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spec
         return int(B * (M * (2 * Tl + (0 if spectral else C)) + T))
     if name == "row_adj":      # read tile and checkpoint, write tile (all band-limited), read object patch, RMW gradient
         ck = Tl if spectral else C
-        return int(B * (M * (2 * Tl + ck) + 3 * T) + (B * T if engine == "lsqml" else 0))
+        return int(B * (M * (2 * Tl + ck) + (2 if ordered else 3) * T) + (B * T if engine == "lsqml" else 0))
     if name in ("col_prop", "col_prop_adj"):   # read + write the live columns of every tile
         return int(B * 2 * M * Tl)
     if name == "far_loss":     # tiles read, far field written and re-read, seed written; pattern read
@@ -117,6 +124,8 @@ def kernel_flops_per_launch(name, N, M, B, S, spectral=False):
 
 def main():
     args = parse()
+    if args.reduction == "auto":
+        args.reduction = "atomic" if args.workload == "ms256_m8_s30" else "ordered"
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (how the path would shard "
                                    "over GPUs is described in the design notes)"}))
@@ -154,6 +163,7 @@ def main():
                        lsqml=args.engine == "lsqml")
     prob.set_chunk(args.chunk)
     prob.set_strategy(args.strategy)
+    prob.set_reduction(args.reduction)
     if args.regularize:
         k = np.fft.fftfreq(N) * N
         prob.set_regularizers(obj_l2=1e-3, probe_l2=1e-6, obj_l1=1e-3, obj_tikhonov=1e-2, obj_tv=1e-2,
@@ -229,7 +239,8 @@ def main():
     avg_s = dom_ms / dom_n / 1000.0
     spectral = prob.checkpoint_every == 1 and not prob.checkpoint_half and args.strategy != "resident"
     live = live_fraction(N, wl.bandlimit, S)
-    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral, live)
+    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral, live,
+                                           args.reduction == "ordered")
     flops_launch = kernel_flops_per_launch(dom, N, M, B, S, spectral)
     gbs = bytes_launch / avg_s / 1e9
     tfl = flops_launch / avg_s / 1e12
@@ -240,7 +251,10 @@ def main():
         roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
     # the counters were taken on the default configuration only
-    default_cfg = not prob.checkpoint_half and args.engine == "adam" and not args.regularize
+    # the committed counter summary covers the default configuration only
+    default_cfg = (args.workload == "ms256_m8_s30" and B == 512 and prob.checkpoint_every == 1 and
+                   not prob.checkpoint_half and args.engine == "adam" and not args.regularize and
+                   args.strategy != "resident" and args.chunk == 0 and args.reduction == "atomic")
     traffic = measured_traffic(dom) if default_cfg else None
     roof.update({"kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4),
                  "traffic": traffic, "algorithmic_bytes": bytes_launch, "algorithmic_flops": flops_launch})
@@ -256,7 +270,7 @@ def main():
                                f"{ENGINES[args.engine]}{', all regularizers' if args.regularize else ''}",
                    "global_batch": B, "checkpoint_every": prob.checkpoint_every,
                    "checkpoint_storage": "f16" if prob.checkpoint_half else "f32", "strategy": args.strategy,
-                   "engine": args.engine, "regularizers": bool(args.regularize)},
+                   "reduction": args.reduction, "engine": args.engine, "regularizers": bool(args.regularize)},
         "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
         "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
         "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),
@@ -303,7 +317,8 @@ def bench_serving(args):
     work = sum(r.J * r.n_iters for r in reqs)
     print(f"[bench] {len(reqs)} requests built in {time.time() - t0:.1f}s, "
           f"{work} position-iterations", file=sys.stderr, flush=True)
-    srv = serving.Server(hbm_budget=int(0.5 * torch.cuda.get_device_properties(0).total_memory))
+    srv = serving.Server(hbm_budget=int(0.5 * torch.cuda.get_device_properties(0).total_memory),
+                         reduction=args.reduction)
     for r in reqs:
         srv.submit(r)
     t1 = time.perf_counter()
@@ -311,7 +326,7 @@ def bench_serving(args):
     t_served = time.perf_counter() - t1
     print(f"[bench] served stream done in {t_served:.1f}s", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
-    fifo = serving.run_fifo(reqs)
+    fifo = serving.run_fifo(reqs, reduction=args.reduction)
     t_fifo = time.perf_counter() - t1
     print(f"[bench] one-at-a-time done in {t_fifo:.1f}s", file=sys.stderr, flush=True)
     p50, p99 = serving.latency_stats(served)
@@ -326,7 +341,8 @@ def bench_serving(args):
         "warmup": 0, "ms_per_step": round(1000 * t_served / len(reqs), 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"serving: {len(reqs)} Poisson arrivals (2/s), probe 64-256, 1-6 modes, "
-                               f"1-16 slices, 16^2-48^2 scans, {args.iters} Adam iterations each"},
+                               f"1-16 slices, 16^2-48^2 scans, {args.iters} Adam iterations each",
+                   "reduction": args.reduction},
         "iteration_latency_p50_s": round(p50, 4), "iteration_latency_p99_s": round(p99, 4),
         "one_at_a_time": {"value": round(work / t_fifo, 1), "iteration_latency_p50_s": round(f50, 4),
                           "iteration_latency_p99_s": round(f99, 4), "wall_s": round(t_fifo, 2)},

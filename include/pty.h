@@ -164,6 +164,24 @@ int32_t pty_checkpoint_every(const pty_ctx* ctx);
 #define PTY_STRATEGY_RESIDENT 2
 pty_status pty_set_strategy(pty_ctx* ctx, int32_t strategy);
 
+/* How the object gradient (Sec. 3.2: the sum over the group of every
+ * position's windowed contribution, slice by slice) is accumulated.
+ * ATOMIC (default): the adjoint row pass adds each contribution with float
+ * atomics; the summation order, and so the last bits of the gradient, vary
+ * from run to run. ORDERED: the adjoint row pass stores each position's
+ * contribution in a scratch area allocated at create (max_batch x N x N
+ * complex64) and a second kernel adds them tile by tile in batch order, so
+ * loss_and_grad and reconstruct_step give bit-identical results on repeated
+ * calls with the same inputs, and a reconstruction gives the same bits alone
+ * or in a grouped step (the dense position gradient excepted when a batch
+ * lists one position twice). ORDERED also avoids the contention of many
+ * overlapping windows (a whole dense scan in one group). It applies to the
+ * two-pass kernels; with it set, RESIDENT runs two-pass. The LSQML
+ * illumination sums stay atomic. Returns PTY_EINVAL for another mode. */
+#define PTY_REDUCE_ATOMIC 0
+#define PTY_REDUCE_ORDERED 1
+pty_status pty_set_reduction(pty_ctx* ctx, int32_t mode);
+
 /* Schedule of pty_loss_and_grad and pty_reconstruct_step: the group is taken
  * through the forward and adjoint passes in consecutive chunks of
  * `positions` batch entries, one chunk after the other, so that a chunk's
@@ -337,7 +355,10 @@ void pty_destroy(pty_ctx* ctx);
  * A pty_group owns a workspace for one window size N and runs one step over
  * position chunks of several reconstructions (contexts with that N, any M,
  * S, object size, loss) in shared kernel launches. Entry waves are stored for
- * every slice (no recompute) in the group's workspace. */
+ * every slice (no recompute) in the group's workspace. A grouped step uses
+ * the ordered object-gradient reduction when every context in it is set to
+ * PTY_REDUCE_ORDERED (the group holds max_items x N x N complex64 of scratch
+ * for it), else atomics. */
 typedef struct pty_group pty_group;
 
 typedef struct {

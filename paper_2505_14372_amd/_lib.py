@@ -18,6 +18,7 @@ LOSS_IDS = {"amplitude": 0, "anscombe": 1, "poisson": 2, "gaussian": 3}
 OPT_SGD, OPT_ADAM, OPT_EPIE = 0, 1, 2
 OPT_KINDS = {"sgd": OPT_SGD, "adam": OPT_ADAM, "epie": OPT_EPIE}
 STRATEGIES = {"auto": 0, "two_pass": 1, "resident": 2}
+REDUCTIONS = {"atomic": 0, "ordered": 1}
 PTY_ACCUMULATE = 1
 PTY_POS_DENSE = 2
 
@@ -28,7 +29,7 @@ EXPORTS = (
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
-    "pty_set_regularizers", "pty_set_strategy", "pty_lsqml_step",
+    "pty_set_regularizers", "pty_set_strategy", "pty_set_reduction", "pty_lsqml_step",
 )
 
 
@@ -125,6 +126,7 @@ def load():
         "pty_profile_enable": ([i32], None),
         "pty_set_regularizers": ([vp, C.POINTER(Regularizers)], i32),
         "pty_set_strategy": ([vp, i32], i32),
+        "pty_set_reduction": ([vp, i32], i32),
         "pty_lsqml_step": ([vp, vp, C.POINTER(State), C.POINTER(Illum), vp, vp, i32, C.POINTER(Lsqml), vp], i32),
         "pty_profile_collect": ([C.c_char_p, sz, C.POINTER(f64), C.POINTER(i64), i32], i32),
     }

@@ -180,6 +180,12 @@ class Problem:
         if st:
             self._err(st, "pty_set_strategy")
 
+    def set_reduction(self, mode: str):
+        """Object-gradient accumulation: 'atomic' (default) or 'ordered' (bit-reproducible)."""
+        st = self.lib.pty_set_reduction(self.ctx, _lib.REDUCTIONS[mode])
+        if st:
+            self._err(st, "pty_set_reduction")
+
     def set_chunk(self, positions: int):
         """Positions per launch in loss_and_grad / reconstruct_step (0: the whole group)."""
         st = self.lib.pty_set_chunk(self.ctx, int(positions))

@@ -155,6 +155,7 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8, bo
     b += align256((size_t)max_batch * nblk * sizeof(float));
     b += align256((size_t)max_batch * M * nblk * 2 * sizeof(float));
     b += align256((size_t)max_batch * S * 2 * sizeof(float));          // ePIE window maxima
+    b += align256((size_t)max_batch * N2 * sizeof(float2));            // ordered reduction scratch
   }
   if (lsqml) {
     const size_t HW = (size_t)g->obj_h * g->obj_w;
@@ -189,12 +190,12 @@ pty_status validate_geometry(const pty_geometry* g, std::string& err) {
 enum ProfClass {
   P_ITEMS, P_COL_SHIFT, P_ROW_FWD, P_COL_PROP, P_FAR_LOSS, P_LOSS_REDUCE, P_ROW_ADJ, P_COL_PROP_ADJ,
   P_COL_FINAL, P_PROBE_GRAD, P_POS_REDUCE, P_PLAIN2D, P_FILL, P_OPTIM, P_RECOMPUTE, P_REG, P_RES_FWD, P_RES_ADJ,
-  P_NCLASS
+  P_OBJ_GATHER, P_NCLASS
 };
 const char* kProfNames[P_NCLASS] = {"items", "col_shift", "row_fwd", "col_prop", "far_loss", "loss_reduce",
                                     "row_adj", "col_prop_adj", "col_final", "probe_grad", "pos_reduce",
                                     "plain2d", "fill", "optimizer", "recompute", "regularizers", "res_fwd",
-                                    "res_adj"};
+                                    "res_adj", "obj_gather"};
 
 struct ProfRec { int cls; hipEvent_t a, b; };
 
@@ -239,6 +240,7 @@ struct pty_ctx {
   int max_batch = 0, ck_every = 1, n_ck = 1;
   int chunk = 0;              // positions per launch in fused loss-and-gradient calls (0: all)
   int strategy = PTY_STRATEGY_AUTO;
+  int reduce = PTY_REDUCE_ATOMIC;
   Sizes sz;
   float2 *tw = nullptr, *prop = nullptr, *phat = nullptr, *gphat = nullptr, *gprobe = nullptr, *gobj = nullptr;
   float* gpos = nullptr;
@@ -249,6 +251,7 @@ struct pty_ctx {
   Item* items = nullptr;
   float2* ramps = nullptr;
   float *loss_part = nullptr, *pos_part = nullptr;
+  float2* cscr = nullptr;          // ordered object-gradient reduction scratch [max_batch][N][N]
   // regularization
   bool reg_on = false, con_on = false;
   RegDev rg{};
@@ -287,6 +290,7 @@ struct pty_group {
   float2 *tw = nullptr, *ws = nullptr, *ck = nullptr, *ramps = nullptr;
   Item* items = nullptr;
   float *loss_part = nullptr, *pos_part = nullptr;
+  float2* cscr = nullptr;   // ordered object-gradient reduction scratch [max_items][N][N]
   int* flags = nullptr;
   std::string err;
 };
@@ -348,7 +352,8 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
   L.loss_part = c->loss_part;
   L.pos_part = c->pos_part;
   L.flags = c->flags;
-  L.resident = use_resident(c->strategy, c->g.N, c->ck_every) ? 1 : 0;
+  L.resident = (use_resident(c->strategy, c->g.N, c->ck_every) && c->reduce != PTY_REDUCE_ORDERED) ? 1 : 0;
+  L.cscr = c->reduce == PTY_REDUCE_ORDERED ? c->cscr : nullptr;
   // every slice stored in float: the column passes write the entry waves' row
   // spectra straight into the checkpoint slots (the resident chains ignore it)
   L.ck_spec = (c->ck_every == 1 && !c->ck_half) ? 1 : 0;
@@ -463,6 +468,16 @@ void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<
       psi.seg_base = i0 + 1;
     }
     { ProfScope p(P_ROW_ADJ, L.stream); launch_rows_adj(L, N, t, psi, scale); }
+    if (L.cscr) {
+      // ordered reduction: add this slice's stored contributions in batch order
+      int mh = 0, mw = 0;
+      for (int q = 0; q < L.n_reqs; ++q) {
+        mh = std::max(mh, L.reqs.r[q].H);
+        mw = std::max(mw, L.reqs.r[q].W);
+      }
+      ProfScope p(P_OBJ_GATHER, L.stream);
+      launch_obj_gather(L, N, t, mh, mw);
+    }
     if (t < S_max - 1) { ProfScope p(P_COL_PROP_ADJ, L.stream); launch_col(L, N, COL_PROP_ADJ, t); }
     if (std::find(final_steps.begin(), final_steps.end(), t) != final_steps.end()) {
       ProfScope p(P_COL_FINAL, L.stream);
@@ -568,7 +583,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
     if ((st = dmalloc(&c->ws, c->sz.tiles * N2, e)) || (st = dmalloc(&c->ck, c->sz.ck_tiles * N2 * ck_elem, e)) ||
         (st = dmalloc(&c->seg, c->sz.seg_tiles * N2 * ck_elem, e)) || (st = dmalloc(&c->ws2, c->sz.ws2_tiles * N2, e)) ||
         (st = dmalloc(&c->items, (size_t)max_batch, e)) || (st = dmalloc(&c->ramps, (size_t)max_batch * 2 * N, e)) ||
-        (st = dmalloc(&c->emax, (size_t)max_batch * S * 2, e)) ||
+        (st = dmalloc(&c->emax, (size_t)max_batch * S * 2, e)) || (st = dmalloc(&c->cscr, (size_t)max_batch * N2, e)) ||
         (st = dmalloc(&c->loss_part, (size_t)max_batch * nblk, e)) ||
         (st = dmalloc(&c->pos_part, (size_t)max_batch * M * nblk * 2, e)))
       return fail(st);
@@ -655,7 +670,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
   dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
-  dfree(c->prop_y); dfree(c->prop_x);
+  dfree(c->prop_y); dfree(c->prop_x); dfree(c->cscr);
   dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums); dfree(c->lsq_tau);
   delete c;
 }
@@ -1097,6 +1112,7 @@ Sizes group_sizes(int N, int max_items, int max_tiles, long long max_ck) {
   b += align256((size_t)max_items * nblk * sizeof(float));
   b += align256((size_t)max_tiles * nblk * 2 * sizeof(float));
   b += align256(4 * sizeof(int));
+  b += align256((size_t)max_items * N2 * sizeof(float2));   // ordered reduction scratch
   s.bytes = b;
   return s;
 }
@@ -1132,7 +1148,8 @@ pty_status pty_group_create(int32_t N, int32_t max_items, int32_t max_tiles, int
       (st = dmalloc(&G->ck, (size_t)max_ckpt_tiles * N2, G->err)) || (st = dmalloc(&G->items, (size_t)max_items, G->err)) ||
       (st = dmalloc(&G->ramps, (size_t)max_items * 2 * N, G->err)) ||
       (st = dmalloc(&G->loss_part, (size_t)max_items * nblk, G->err)) ||
-      (st = dmalloc(&G->pos_part, (size_t)max_tiles * nblk * 2, G->err)) || (st = dmalloc(&G->flags, 4, G->err)))
+      (st = dmalloc(&G->pos_part, (size_t)max_tiles * nblk * 2, G->err)) || (st = dmalloc(&G->flags, 4, G->err)) ||
+      (st = dmalloc(&G->cscr, (size_t)max_items * N2, G->err)))
     return fail(st);
   std::vector<float2> tw = roots(N);
   if (hipMemcpy(G->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return fail(PTY_EHIP);
@@ -1144,7 +1161,7 @@ pty_status pty_group_create(int32_t N, int32_t max_items, int32_t max_tiles, int
 void pty_group_destroy(pty_group* G) {
   if (!G) return;
   dfree(G->tw); dfree(G->ws); dfree(G->ck); dfree(G->items); dfree(G->ramps);
-  dfree(G->loss_part); dfree(G->pos_part); dfree(G->flags);
+  dfree(G->loss_part); dfree(G->pos_part); dfree(G->flags); dfree(G->cscr);
   delete G;
 }
 
@@ -1209,6 +1226,11 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   L.n_reqs = n;
   L.n_items = item0;
   L.max_modes = M_max;
+  // the ordered object-gradient reduction when every request asks for it
+  bool ordered = true;
+  for (int q = 0; q < n; ++q) ordered &= items[q].ctx->reduce == PTY_REDUCE_ORDERED;
+  L.cscr = ordered ? G->cscr : nullptr;
+  if (ordered) L.resident = 0;
   // a column block runs when any request has a live column in it
   L.col_live_blocks = 0;
   for (int q = 0; q < n; ++q) {
@@ -1283,6 +1305,13 @@ extern "C" int32_t pty_profile_collect(char* names, size_t names_len, double* to
     names[m] = '\0';
   }
   return std::min(n, max_entries);
+}
+
+extern "C" pty_status pty_set_reduction(pty_ctx* c, int32_t mode) {
+  if (!c) return PTY_EINVAL;
+  if (mode != PTY_REDUCE_ATOMIC && mode != PTY_REDUCE_ORDERED) { c->err = "unknown reduction mode"; return PTY_EINVAL; }
+  c->reduce = mode;
+  return PTY_OK;
 }
 
 extern "C" pty_status pty_set_chunk(pty_ctx* c, int32_t positions) {

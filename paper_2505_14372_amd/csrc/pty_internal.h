@@ -110,6 +110,9 @@ struct LaunchCtx {
   int* flags;
   int emax;                 // the first forward records the window maxima (ePIE)
   int wsum;                 // the adjoint row pass scatters the illumination (LSQML)
+  float2* cscr;             // ordered object-gradient reduction: per-item contribution scratch
+                            // [items][N][N] (the adjoint row pass stores, k_obj_gather adds), or
+                            // null (float atomics)
   unsigned col_live_blocks; // column blocks a propagation column pass runs (bit q: columns of
                             // block q; 0: all), the union over the launch's requests
   int ck_spec;              // spectral checkpoints: the forward column passes write the row
@@ -122,6 +125,7 @@ void launch_rows_fwd(const LaunchCtx& L, int N, int step, PsiStore st, bool from
 void launch_rows_adj(const LaunchCtx& L, int N, int step, PsiLoad psi, float scale);
 void launch_col(const LaunchCtx& L, int N, int op, int step);
 void launch_far_loss(const LaunchCtx& L, int N, int step, bool grad);
+void launch_obj_gather(const LaunchCtx& L, int N, int step, int max_h, int max_w);
 void launch_probe_grad(const LaunchCtx& L, int N, float scale);
 void launch_loss_reduce(const LaunchCtx& L, int N);
 void launch_pos_reduce(const LaunchCtx& L, int N, float scale);

@@ -302,7 +302,8 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
                                                       const ReqTable reqs,
                                                       float2* __restrict__ ws, const void* __restrict__ ck_,
                                                       const float2* __restrict__ twg, int step,
-                                                      PsiLoad psi, float scale, int item_off) {
+                                                      PsiLoad psi, float scale, int item_off,
+                                                      float2* __restrict__ cscr) {
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
   __shared__ float2 tw[N];
   __shared__ float2 xch[LINES * Xch<N>::ROW_STRIDE];
@@ -378,11 +379,18 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
       if ((omask >> a) & 1u) trow[l + L * a] = v[a];
   }
   if (r.gobj) {
-    float* g = reinterpret_cast<float*>(r.gobj + orow);
+    if (cscr) {
+      // ordered reduction: this position's contribution, added in batch order by k_obj_gather
+      float2* dst = cscr + ((size_t)(item_off + blockIdx.y) * N + y) * N;
 #pragma unroll
-    for (int a = 0; a < E; ++a) {
-      unsafeAtomicAdd(g + 2 * (l + L * a), scale * sa * acc[a].x);
-      unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * sa * acc[a].y);
+      for (int a = 0; a < E; ++a) dst[l + L * a] = cscale(acc[a], scale * sa);
+    } else {
+      float* g = reinterpret_cast<float*>(r.gobj + orow);
+#pragma unroll
+      for (int a = 0; a < E; ++a) {
+        unsafeAtomicAdd(g + 2 * (l + L * a), scale * sa * acc[a].x);
+        unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * sa * acc[a].y);
+      }
     }
   }
   if constexpr (WSUM) {
@@ -780,6 +788,102 @@ __global__ void k_loss_reduce(const ReqTable reqs, const float* __restrict__ los
 // A workgroup of PIX x SPLIT threads covers PIX consecutive pixels; thread
 // row s sums the items b = item0 + s, s + SPLIT, ... and the rows are added
 // in a fixed order (deterministic for a given launch shape).
+// Ordered object-gradient reduction for slice i = S - 1 - step of every
+// request: one workgroup per kGatherTY x 64 tile of the object gradient sums
+// the stored contributions of the positions whose windows cover the tile and
+// adds the sum to the gradient. Each tile has one owner (no atomics) and the
+// summation order is fixed by the batch order alone: the covering positions
+// are listed in batch order (a block-wide ordered compaction over the
+// request's items, 256 at a time), wave w sums the w-th contiguous quarter of
+// each list in list order (loads for four positions issued ahead of their
+// additions), and the four wave sums are added in wave order at the end.
+constexpr int kGatherTY = 8, kGatherW = 4;
+template <int N>
+__global__ __launch_bounds__(64 * kGatherW) void k_obj_gather(const Item* __restrict__ items, const ReqTable reqs,
+                                                              const float2* __restrict__ cscr, int step,
+                                                              int item_off, int n_items) {
+  const ReqDev& r = reqs.r[blockIdx.z];
+  const int i = r.S - 1 - step;
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kGatherTY;
+  if (i < 0 || !r.gobj || x0 >= r.W || y0 >= r.H) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, x = x0 + lane;
+  const int lo = max(r.item0, item_off), hi = min(r.item0 + r.n_items, item_off + n_items);
+  __shared__ int list[64 * kGatherW];
+  __shared__ int wcnt[kGatherW];
+  __shared__ float2 part[kGatherW - 1][kGatherTY][64];
+  float2 acc[kGatherTY];
+#pragma unroll
+  for (int t = 0; t < kGatherTY; ++t) acc[t] = make_float2(0.f, 0.f);
+  // contribution of position bj to row y0 + t of this thread's column (zero outside its window)
+  auto fetch = [&](int bj, float2 (&v)[kGatherTY]) {
+    const Item it = items[bj];
+    const int wx = x - it.nx;
+    const float2* src = cscr + (size_t)bj * N * N;
+#pragma unroll
+    for (int t = 0; t < kGatherTY; ++t) {
+      const int wy = y0 + t - it.ny;
+      v[t] = (wy >= 0 && wy < N && wx >= 0 && wx < N) ? src[wy * N + wx] : make_float2(0.f, 0.f);
+    }
+  };
+  int total = 0;
+  for (int b0 = lo; b0 < hi; b0 += 64 * kGatherW) {
+    const int b = b0 + (int)threadIdx.x;
+    bool hit = false;
+    if (b < hi) {
+      const Item it = items[b];
+      hit = it.valid && it.ny < y0 + kGatherTY && it.ny + N > y0 && it.nx < x0 + 64 && it.nx + N > x0;
+    }
+    const unsigned long long m = __ballot(hit);
+    if (lane == 0) wcnt[w] = __popcll(m);
+    __syncthreads();
+    int off = 0, cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kGatherW; ++q) {
+      off += q < w ? wcnt[q] : 0;
+      cnt += wcnt[q];
+    }
+    if (hit) list[off + __popcll(m & ((1ull << lane) - 1ull))] = b;
+    __syncthreads();
+    total += cnt;
+    const int per = (cnt + kGatherW - 1) / kGatherW;
+    const int beg = min(w * per, cnt), end = min(beg + per, cnt);
+    int k = beg;
+    for (; k + 4 <= end; k += 4) {
+      float2 v0[kGatherTY], v1[kGatherTY], v2[kGatherTY], v3[kGatherTY];
+      fetch(__builtin_amdgcn_readfirstlane(list[k]), v0);
+      fetch(__builtin_amdgcn_readfirstlane(list[k + 1]), v1);
+      fetch(__builtin_amdgcn_readfirstlane(list[k + 2]), v2);
+      fetch(__builtin_amdgcn_readfirstlane(list[k + 3]), v3);
+#pragma unroll
+      for (int t = 0; t < kGatherTY; ++t) acc[t] = cadd(cadd(cadd(cadd(acc[t], v0[t]), v1[t]), v2[t]), v3[t]);
+    }
+    for (; k < end; ++k) {
+      float2 v0[kGatherTY];
+      fetch(__builtin_amdgcn_readfirstlane(list[k]), v0);
+#pragma unroll
+      for (int t = 0; t < kGatherTY; ++t) acc[t] = cadd(acc[t], v0[t]);
+    }
+    __syncthreads();   // the list is rebuilt for the next items
+  }
+  if (total == 0) return;
+  if (w > 0) {
+#pragma unroll
+    for (int t = 0; t < kGatherTY; ++t) part[w - 1][t][lane] = acc[t];
+  }
+  __syncthreads();
+  if (w != 0 || x >= r.W) return;
+  float2* g = r.gobj + (size_t)i * r.H * r.W;
+#pragma unroll
+  for (int t = 0; t < kGatherTY; ++t) {
+    float2 s = acc[t];
+#pragma unroll
+    for (int q = 1; q < kGatherW; ++q) s = cadd(s, part[q - 1][t][lane]);
+    const int y = y0 + t;
+    if (y < r.H) g[(size_t)y * r.W + x] = cadd(g[(size_t)y * r.W + x], s);
+  }
+}
+
+constexpr int kProbeSplit = 16;
 template <int N, int PIX, int SPLIT>
 __global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restrict__ items, const ReqTable reqs,
                                                             const float2* __restrict__ ws,
@@ -791,25 +895,41 @@ __global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restri
   const int px = threadIdx.x % pix, s = threadIdx.x / pix;
   const int p = blockIdx.x * pix + px;
   const int uy = p / N, ux = p % N;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int b = r.item0 + s; b < r.item0 + r.n_items; b += split) {
+  auto term = [&](int b) {
     const Item it = items[b];
-    if (!it.valid) continue;
+    if (!it.valid) return make_float2(0.f, 0.f);
     float2 R = cmul(ramps[(size_t)b * 2 * N + uy], ramps[(size_t)b * 2 * N + N + ux]);
     float2 h = ws[(size_t)(it.tile0 + m) * N * N + p];
-    acc = cadd(acc, cmul(h, cconj(R)));
-  }
+    return cmul(h, cconj(R));
+  };
   if constexpr (SPLIT == 1) {
-    r.gphat[(size_t)m * N * N + p] = cscale(acc, scale);
-    return;
-  }
-  __shared__ float2 red[PIX * SPLIT];
-  red[s * pix + px] = acc;
-  __syncthreads();
-  if (s == 0) {
-    float2 t = red[px];
-    for (int q = 1; q < split; ++q) t = cadd(t, red[q * pix + px]);
+    // the same summation order as the split form: kProbeSplit interleaved
+    // partial sums over the request's items, added in order (so a request's
+    // gradient has the same bits whichever form its launch uses)
+    float2 part[kProbeSplit];
+#pragma unroll
+    for (int q = 0; q < kProbeSplit; ++q) part[q] = make_float2(0.f, 0.f);
+    for (int b0 = 0; b0 < r.n_items; b0 += kProbeSplit) {
+#pragma unroll
+      for (int q = 0; q < kProbeSplit; ++q)
+        if (b0 + q < r.n_items) part[q] = cadd(part[q], term(r.item0 + b0 + q));
+    }
+    float2 t = part[0];
+#pragma unroll
+    for (int q = 1; q < kProbeSplit; ++q) t = cadd(t, part[q]);
     r.gphat[(size_t)m * N * N + p] = cscale(t, scale);
+  } else {
+    static_assert(SPLIT == kProbeSplit, "the split form takes kProbeSplit interleaved partial sums");
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b = r.item0 + s; b < r.item0 + r.n_items; b += split) acc = cadd(acc, term(b));
+    __shared__ float2 red[PIX * SPLIT];
+    red[s * pix + px] = acc;
+    __syncthreads();
+    if (s == 0) {
+      float2 t = red[px];
+      for (int q = 1; q < split; ++q) t = cadd(t, red[q * pix + px]);
+      r.gphat[(size_t)m * N * N + p] = cscale(t, scale);
+    }
   }
 }
 
@@ -904,20 +1024,20 @@ struct Launch {
     dim3 g(Pass<N>::NBLK, L.n_items);
     if (psi.spec) {
       if (L.wsum)
-        hipLaunchKernelGGL((k_row_adj<N, false, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+        hipLaunchKernelGGL((k_row_adj<N, false, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
       else
-        hipLaunchKernelGGL((k_row_adj<N, false, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+        hipLaunchKernelGGL((k_row_adj<N, false, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
       return;
     }
     if (L.wsum) {
       if (L.ck_half)
-        hipLaunchKernelGGL((k_row_adj<N, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+        hipLaunchKernelGGL((k_row_adj<N, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
       else
-        hipLaunchKernelGGL((k_row_adj<N, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+        hipLaunchKernelGGL((k_row_adj<N, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
     } else if (L.ck_half) {
-      hipLaunchKernelGGL((k_row_adj<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+      hipLaunchKernelGGL((k_row_adj<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
     } else {
-      hipLaunchKernelGGL((k_row_adj<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off);
+      hipLaunchKernelGGL((k_row_adj<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
     }
   }
   static void col(const LaunchCtx& L, int op, int step) {
@@ -940,6 +1060,11 @@ struct Launch {
       default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map); break;
     }
   }
+  static void obj_gather(const LaunchCtx& L, int step, int max_h, int max_w) {
+    dim3 g((max_w + 63) / 64, (max_h + kGatherTY - 1) / kGatherTY, L.n_reqs);
+    hipLaunchKernelGGL((k_obj_gather<N>), g, dim3(64 * kGatherW), 0, L.stream, L.items, L.reqs, L.cscr, step,
+                       L.item_off, L.n_items);
+  }
   static void far_loss(const LaunchCtx& L, int step, bool grad) {
     dim3 g(ColPass<N>::NBLK, L.n_items);
     if (grad)
@@ -953,7 +1078,7 @@ struct Launch {
     static_assert((N * N) % 256 == 0, "pixel blocks must tile the probe");
     const bool small = (N * N / 256) * L.max_modes * L.n_reqs < 1024;
     if (small)
-      hipLaunchKernelGGL((k_probe_grad<N, 64, 16>), dim3(N * N / 64, L.max_modes, L.n_reqs), dim3(1024), 0, L.stream,
+      hipLaunchKernelGGL((k_probe_grad<N, 64, kProbeSplit>), dim3(N * N / 64, L.max_modes, L.n_reqs), dim3(1024), 0, L.stream,
                          L.items, L.reqs, L.ws, L.ramps, scale);
     else
       hipLaunchKernelGGL((k_probe_grad<N, 256, 1>), dim3(N * N / 256, L.max_modes, L.n_reqs), dim3(256), 0, L.stream,
@@ -995,6 +1120,9 @@ void launch_rows_adj(const LaunchCtx& L, int N, int step, PsiLoad psi, float sca
   PTY_DISPATCH(N, rows_adj(L, step, psi, scale));
 }
 void launch_col(const LaunchCtx& L, int N, int op, int step) { PTY_DISPATCH(N, col(L, op, step)); }
+void launch_obj_gather(const LaunchCtx& L, int N, int step, int max_h, int max_w) {
+  PTY_DISPATCH(N, obj_gather(L, step, max_h, max_w));
+}
 void launch_far_loss(const LaunchCtx& L, int N, int step, bool grad) { PTY_DISPATCH(N, far_loss(L, step, grad)); }
 void launch_probe_grad(const LaunchCtx& L, int N, float scale) { PTY_DISPATCH(N, probe_grad(L, scale)); }
 void launch_plain2d(int N, hipStream_t s, const float2* tw, const float2* src, float2* dst, int n_tiles,

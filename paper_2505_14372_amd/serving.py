@@ -106,10 +106,11 @@ class Result:
 
 
 class _Running:
-    def __init__(self, req: ReconRequest, dev, now):
+    def __init__(self, req: ReconRequest, dev, now, reduction="atomic"):
         self.req = req
         self.prob = api.Problem(req.N, req.M, req.S, req.H, req.W, req.J, dz=req.dz, dx=req.dx,
                                 wavelength=req.wavelength, loss=req.loss, eps=req.eps, max_batch=0)
+        self.prob.set_reduction(reduction)
         t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)  # noqa: E731
         self.state = api.ReconState(t(req.probe, np.complex64), t(req.obj, np.complex64),
                                     t(req.positions, np.float32), adam=req.opt.kind == "adam")
@@ -138,8 +139,9 @@ class Server:
     """Admits, batches and runs reconstructions; see the module docstring."""
 
     def __init__(self, hbm_budget: int, group_tiles: Optional[Dict[int, int]] = None, device="cuda",
-                 max_per_launch: int = 16):
+                 max_per_launch: int = 16, reduction: str = "atomic"):
         self.dev = torch.device(device)
+        self.reduction = reduction   # object-gradient accumulation of every reconstruction
         self.budget = int(hbm_budget)
         self.group_tiles = dict(DEFAULT_GROUP_TILES if group_tiles is None else group_tiles)
         self.max_per_launch = min(max_per_launch, 16)
@@ -182,7 +184,7 @@ class Server:
                     raise MemoryError(f"request {req.rid} needs {need + grp_need} bytes, over the budget")
                 break          # arrival order: later requests wait too
             self._group(req.N)
-            self.running.append(_Running(req, self.dev, now))
+            self.running.append(_Running(req, self.dev, now, self.reduction))
             self.used += need
             self.pending.remove(req)
             admitted.append(req.rid)
@@ -277,7 +279,8 @@ class Server:
         del r.state, r.patterns
 
 
-def run_fifo(requests: List[ReconRequest], device="cuda", clock=time.perf_counter) -> Dict[int, Result]:
+def run_fifo(requests: List[ReconRequest], device="cuda", clock=time.perf_counter,
+             reduction: str = "atomic") -> Dict[int, Result]:
     """Baseline: one reconstruction at a time in arrival order (single-request
     reconstruct_step with the same minibatches), starting each at the later of
     its arrival and the previous one's end."""
@@ -291,6 +294,7 @@ def run_fifo(requests: List[ReconRequest], device="cuda", clock=time.perf_counte
         admitted = clock() - t0
         prob = api.Problem(req.N, req.M, req.S, req.H, req.W, req.J, dz=req.dz, dx=req.dx,
                            wavelength=req.wavelength, loss=req.loss, eps=req.eps, max_batch=req.batch)
+        prob.set_reduction(reduction)
         t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)  # noqa: E731
         st = api.ReconState(t(req.probe, np.complex64), t(req.obj, np.complex64), t(req.positions, np.float32),
                             adam=req.opt.kind == "adam")

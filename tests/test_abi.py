@@ -48,9 +48,9 @@ def test_workspace_sizes_follow_the_layout(lib):
     tile = N * N * 8
     b1 = api.workspace_bytes(N, M, S, H, W, J, B, checkpoint_every=1)
     b0 = api.workspace_bytes(N, M, S, H, W, J, 0)
-    # store-all: B*M work tiles + B*M*S checkpoints
-    assert b1 - b0 >= B * M * (1 + S) * tile
-    assert b1 - b0 < B * M * (1 + S) * tile + 64 * 2 ** 20
+    # store-all: B*M work tiles + B*M*S checkpoints + B tiles of ordered-reduction scratch
+    assert b1 - b0 >= B * M * (1 + S) * tile + B * tile
+    assert b1 - b0 < B * M * (1 + S) * tile + B * tile + 64 * 2 ** 20
     # every 6th slice stored: ceil(30/6) = 5 checkpoints, 5 segment slots, a second work buffer
     b6 = api.workspace_bytes(N, M, S, H, W, J, B, checkpoint_every=6)
     assert b6 - b0 >= B * M * (2 + 5 + 5) * tile

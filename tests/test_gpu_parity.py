@@ -333,6 +333,45 @@ def test_nonfinite_flag():
     assert e.value.status == PTY_ENONFINITE
 
 
+@pytest.mark.parametrize("name", ["n64_ms_poisson", "n128_tilt_mask_dz", "n192_ms_anscombe", "n256_ms_gaussian"])
+def test_ordered_reduction_is_bitwise_repeatable(cache, name):
+    """The ordered object-gradient reduction matches the oracle, agrees with the
+    atomic one to rounding, and gives identical bits on a repeated call."""
+    c, ref = _get(cache, name)
+    print(f"case {name} N={c.N} M={c.M} S={c.S} B={len(c.batch)}", flush=True)
+    d = c.device()
+    prob = c.problem()
+    _, gO_at, _, _ = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.set_reduction("ordered")
+    runs = [prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"]) for _ in range(2)]
+    prob.check()
+    (l1, gO1, gP1, gX1), (l2, gO2, gP2, gX2) = runs
+    assert l1.item() == l2.item()
+    assert torch.equal(gO1, gO2) and torch.equal(gP1, gP2) and torch.equal(gX1, gX2)
+    errs = dict(obj=rel_l2(_np(gO1), ref["g_object"]), probe=rel_l2(_np(gP1), ref["g_probe"]),
+                pos=rel_l2(_np(gX1), ref["g_pos"]))
+    print(errs)
+    assert all(e < TOL_G for e in errs.values()), errs
+    assert rel_l2(_np(gO1), _np(gO_at)) < 1e-5
+
+
+@pytest.mark.parametrize("k,chunk", [(1, 4), (2, 0), (3, 5)])
+def test_ordered_reduction_with_chunks_and_recompute(cache, k, chunk):
+    """Chunked schedules and recomputed entry waves under the ordered reduction:
+    oracle parity, and identical bits on a repeated call."""
+    c, ref = _get(cache, "n64_ms_poisson")
+    d = c.device()
+    prob = c.problem(checkpoint_every=k)
+    prob.set_strategy("two_pass")
+    prob.set_reduction("ordered")
+    prob.set_chunk(chunk)
+    runs = [prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"]) for _ in range(2)]
+    prob.check()
+    assert torch.equal(runs[0][1], runs[1][1])
+    assert rel_l2(_np(runs[0][1]), ref["g_object"]) < TOL_G
+    assert abs(runs[0][0].item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+
+
 @pytest.mark.parametrize("kind", ["sgd", "adam"])
 def test_group_step_matches_single_steps(kind):
     """Two reconstructions of one window size (different M, S, object size and
@@ -375,6 +414,39 @@ def test_group_step_matches_single_steps(kind):
                 assert max_rel(_np(a), _np(b)) < 1e-5
             else:
                 assert rel_l2(_np(a), _np(b)) < 1e-4
+
+
+def test_ordered_group_step_gives_the_single_step_bits():
+    """Under the ordered reduction a reconstruction's object, probe and
+    positions after Adam steps have the same bits alone and in grouped steps."""
+    from paper_2505_14372_amd import api
+    cases = [Case(synth.make_small(N=64, M=2, S=3, scan=3, step=4, seed=20, loss="poisson", eps=0.8)),
+             Case(synth.make_small(N=64, M=1, S=5, scan=4, step=5, seed=21, loss="amplitude", eps=0.3))]
+    batches = [[0, 2, 4, 8], [1, 3, 5, 6, 9, 15]]
+    opt = api.Optimizer(kind="adam", lr_object=1e-2, lr_probe=1e-3, lr_pos=1e-2)
+    singles, grouped, probs = [], [], []
+    for c in cases:
+        d = c.device()
+        singles.append(api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=True))
+        grouped.append(api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=True))
+        ps, pg = c.problem(max_batch=16), c.problem(max_batch=16)
+        ps.set_reduction("ordered")
+        pg.set_reduction("ordered")
+        probs.append((ps, pg, d))
+    grp = api.Group(64, max_items=64, max_tiles=128, max_ckpt_tiles=512)
+    for step in range(2):
+        entries = []
+        for q, c in enumerate(cases):
+            ps, pg, d = probs[q]
+            b = torch.tensor(batches[q], dtype=torch.int32, device="cuda")
+            ps.reconstruct_step(singles[q], d["pats"], b, opt)
+            entries.append((pg, grouped[q], d["pats"], b, opt, torch.zeros(1, dtype=torch.float64, device="cuda")))
+        grp.step(entries)
+    torch.cuda.synchronize()
+    for q in range(2):
+        assert torch.equal(grouped[q].object, singles[q].object)
+        assert torch.equal(grouped[q].probe, singles[q].probe)
+        assert torch.equal(grouped[q].positions, singles[q].positions)
 
 
 @pytest.mark.parametrize("name,k", [("n64_ms_poisson", 1), ("n128_ms_poisson", 1), ("n256_ms_gaussian", 1),

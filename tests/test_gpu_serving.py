@@ -39,6 +39,21 @@ def test_served_mix_equals_alone():
     assert 0 < p50 <= p99
 
 
+def test_served_mix_gives_the_alone_bits_under_the_ordered_reduction():
+    from paper_2505_14372_amd import serving
+    reqs = _stream(5, seed=5)
+    print([(r.rid, r.N, r.M, r.S, r.J) for r in reqs], flush=True)
+    srv = serving.Server(hbm_budget=64 << 30, reduction="ordered")
+    for r in reqs:
+        srv.submit(r)
+    mixed = srv.run()
+    alone = serving.run_fifo(reqs, reduction="ordered")
+    for r in reqs:
+        a, b = mixed[r.rid], alone[r.rid]
+        for x, y in ((a.obj, b.obj), (a.probe, b.probe), (a.positions, b.positions)):
+            assert np.array_equal(x, y)
+
+
 def test_admission_respects_budget():
     from paper_2505_14372_amd import api, serving
     reqs = _stream(4, seed=4, iters=1)
