@@ -355,6 +355,24 @@ def test_ordered_reduction_is_bitwise_repeatable(cache, name):
     assert rel_l2(_np(gO1), _np(gO_at)) < 1e-5
 
 
+def test_ordered_reduction_overrides_the_resident_strategy(cache):
+    """RESIDENT with the ordered reduction runs the two-pass kernels: repeatable
+    bits, equal to TWO_PASS with the ordered reduction."""
+    c, ref = _get(cache, "n128_ms_poisson")
+    d = c.device()
+    out = {}
+    for strat in ("resident", "two_pass"):
+        prob = c.problem()
+        prob.set_strategy(strat)
+        prob.set_reduction("ordered")
+        out[strat] = [prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])[1]
+                      for _ in range(2)]
+        prob.check()
+    assert torch.equal(out["resident"][0], out["resident"][1])
+    assert torch.equal(out["resident"][0], out["two_pass"][0])
+    assert rel_l2(_np(out["resident"][0]), ref["g_object"]) < TOL_G
+
+
 @pytest.mark.parametrize("k,chunk", [(1, 4), (2, 0), (3, 5)])
 def test_ordered_reduction_with_chunks_and_recompute(cache, k, chunk):
     """Chunked schedules and recomputed entry waves under the ordered reduction:
@@ -556,9 +574,12 @@ def test_both_strategies_match_oracle(cache, name, strategy):
         assert all(e < TOL_G for e in errs.values()), errs
 
 
-@pytest.mark.parametrize("N,loss,eps,ck_every", [(64, "amplitude", 0.0, 1), (64, "poisson", 0.8, 2),
-                                                 (128, "anscombe", 0.1, 1), (192, "amplitude", 0.0, 3)])
-def test_epie_step_matches_oracle(N, loss, eps, ck_every):
+@pytest.mark.parametrize("N,loss,eps,ck_every,red", [(64, "amplitude", 0.0, 1, "atomic"),
+                                                     (64, "poisson", 0.8, 2, "atomic"),
+                                                     (128, "anscombe", 0.1, 1, "atomic"),
+                                                     (192, "amplitude", 0.0, 3, "atomic"),
+                                                     (128, "poisson", 0.8, 1, "ordered")])
+def test_epie_step_matches_oracle(N, loss, eps, ck_every, red):
     """The ePIE / 3PIE engine (Sec. 3.3): the summed object update and the
     averaged probe update of two consecutive group steps, and the state after
     them, against the oracle (objects with amplitude below 1, so the wave
@@ -567,6 +588,7 @@ def test_epie_step_matches_oracle(N, loss, eps, ck_every):
     c = Case(synth.make_small(N=N, M=2, S=4, scan=3, step=5, seed=40 + N, loss=loss, eps=eps, amp_noise=0.3))
     d = c.device()
     prob = c.problem(max_batch=len(c.batch), checkpoint_every=ck_every)
+    prob.set_reduction(red)
     st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
     beta_o, beta_p = 0.8, 0.5
     opt = api.Optimizer(kind="epie", lr_object=beta_o, lr_probe=beta_p, lr_pos=1.0)
@@ -591,9 +613,12 @@ def test_epie_step_matches_oracle(N, loss, eps, ck_every):
     assert np.array_equal(_np(st.positions), c.pos)
 
 
-@pytest.mark.parametrize("N,loss,eps,ck_every,chunk", [(64, "amplitude", 0.0, 1, 0), (64, "poisson", 0.5, 2, 4),
-                                                       (128, "anscombe", 0.1, 1, 0), (192, "amplitude", 0.0, 3, 0)])
-def test_lsqml_step_matches_oracle(N, loss, eps, ck_every, chunk):
+@pytest.mark.parametrize("N,loss,eps,ck_every,chunk,red", [(64, "amplitude", 0.0, 1, 0, "atomic"),
+                                                           (64, "poisson", 0.5, 2, 4, "atomic"),
+                                                           (128, "anscombe", 0.1, 1, 0, "atomic"),
+                                                           (192, "amplitude", 0.0, 3, 0, "atomic"),
+                                                           (64, "poisson", 0.5, 1, 4, "ordered")])
+def test_lsqml_step_matches_oracle(N, loss, eps, ck_every, chunk, red):
     """The LSQML engine (Sec. 3.3) over two iterations: the object and probe
     steps and the illumination sums of every group step against the oracle,
     each step started from the GPU state and sums (first iteration with the
@@ -603,6 +628,7 @@ def test_lsqml_step_matches_oracle(N, loss, eps, ck_every, chunk):
     d = c.device()
     prob = c.problem(max_batch=len(c.batch), checkpoint_every=ck_every, lsqml=True)
     prob.set_chunk(chunk)
+    prob.set_reduction(red)
     st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
     il = api.IllumSums(c.S, c.H, c.W, c.N)
     kw = dict(beta_object=0.9, beta_probe=0.7, delta_object=1e-2, delta_probe=1e-2, gamma=1e-3)
