@@ -100,8 +100,8 @@ def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spec
         return int(B * (M * (2 * Tl + ck) + (2 if ordered else 3) * T) + (B * T if engine == "lsqml" else 0))
     if name in ("col_prop", "col_prop_adj"):   # read + write the live columns of every tile
         return int(B * 2 * M * Tl)
-    if name == "far_loss":     # tiles read, far field written and re-read, seed written; pattern read
-        return B * (4 * M * T + T // 2)
+    if name == "far_loss":     # tiles read twice (the far field is recomputed, not stored), seed written; pattern read
+        return B * (3 * M * T + T // 2)
     if name == "col_shift":    # write every tile (the probe spectrum stays in cache)
         return B * M * T
     if name == "col_final":    # read + write every tile

@@ -713,7 +713,6 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __
     for (int a = 0; a < E; ++a) {
       v[a] = cscale(v[a], inv);
       I[a] += cabs2(v[a]);
-      if (GRAD) tile[(size_t)(l + L * a) * N + ux] = v[a];
     }
   }
   float wgt[E];
@@ -753,11 +752,16 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_far_loss(const Item* __
     loss_part[(size_t)b * ColPass<N>::NBLK + blockIdx.x] = t;
   }
   if constexpr (GRAD) {
+    // the far field of each mode is transformed again rather than stored and
+    // re-read: three tile passes (read, read, write) instead of four
     for (int m = 0; m < r.M; ++m) {
       float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
       float2 v[E];
 #pragma unroll
-      for (int a = 0; a < E; ++a) v[a] = cscale(tile[(size_t)(l + L * a) * N + ux], wgt[a] * inv);
+      for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
+      line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
+#pragma unroll
+      for (int a = 0; a < E; ++a) v[a] = cscale(cscale(v[a], inv), wgt[a] * inv);
       line_fft<N, true>(v, l, tw, sx, typename ColMap<N>::Sync{});
 #pragma unroll
       for (int a = 0; a < E; ++a) tile[(size_t)(l + L * a) * N + ux] = v[a];
