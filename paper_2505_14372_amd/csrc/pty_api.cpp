@@ -13,6 +13,7 @@
 
 #include "pty.h"
 #include "pty_internal.h"
+#include "pty_prop.hpp"
 
 using namespace pty;
 
@@ -49,74 +50,6 @@ std::vector<float2> roots(int N) {
     t[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
   }
   return t;
-}
-
-// Propagator for one gap, divided by N^2 (the normalisation of the unnormalised
-// forward and inverse 2D DFTs around it):
-// H(u) = B(u) exp(-i pi lambda dz |q|^2 + 2 pi i dz (q_y tan t_y + q_x tan t_x)),
-// q = f(u) / dx, B the circular band limit on signed integer bins or the mask.
-int signed_bin(int u, int N) { return u < (N + 1) / 2 ? u : u - N; }
-
-// Band limit B(u): the circle of radius frac * N / 2 on signed integer bins,
-// everything (frac <= 0), or the caller's mask.
-bool keep_bin(int N, double frac, const std::vector<uint8_t>& mask, int y, int x) {
-  if (!mask.empty()) return mask[(size_t)y * N + x] != 0;
-  if (frac <= 0.0) return true;
-  const double r = frac * N / 2.0;
-  const int ky = signed_bin(y, N), kx = signed_bin(x, N);
-  return (double)(ky * ky + kx * kx) <= r * r * (1.0 + 1e-9);
-}
-
-std::vector<float2> propagator(int N, double dx, double lam, double dz, double frac, double tilt_y,
-                               double tilt_x, const std::vector<uint8_t>& mask) {
-  std::vector<float2> H((size_t)N * N);
-  const double inv_n2 = 1.0 / ((double)N * (double)N);
-  const double ty = std::tan(tilt_y), tx = std::tan(tilt_x);
-  for (int y = 0; y < N; ++y) {
-    const int ky = signed_bin(y, N);
-    const double qy = (double)ky / N / dx;
-    for (int x = 0; x < N; ++x) {
-      const int kx = signed_bin(x, N);
-      const double qx = (double)kx / N / dx;
-      const bool keep = keep_bin(N, frac, mask, y, x);
-      const double ph = -kPiD * lam * dz * (qy * qy + qx * qx) + 2.0 * kPiD * dz * (qy * ty + qx * tx);
-      H[(size_t)y * N + x] = keep ? make_float2((float)(std::cos(ph) * inv_n2), (float)(std::sin(ph) * inv_n2))
-                                  : make_float2(0.f, 0.f);
-    }
-  }
-  return H;
-}
-
-// The phase of H is a sum of a k_y and a k_x term, so H = B(u) Hy(k_y) Hx(k_x).
-// When every row y of the band limit keeps exactly the bins |k_x| <= K_y (a
-// circle, no limit, or a mask of that shape), the column passes rebuild H
-// from the two factors and K_y instead of reading the N x N table:
-// py[y] = (Hy / N^2, K_y as int bits, 0) with K_y = -1 for an empty row,
-// px[x] = Hx. Returns false when the band limit is not of that form.
-bool separable_propagator(int N, double dx, double lam, double dz, double frac, double tilt_y, double tilt_x,
-                          const std::vector<uint8_t>& mask, std::vector<float4>& py, std::vector<float2>& px) {
-  py.assign(N, make_float4(0.f, 0.f, 0.f, 0.f));
-  px.assign(N, make_float2(0.f, 0.f));
-  const double inv_n2 = 1.0 / ((double)N * (double)N);
-  const double ty = std::tan(tilt_y), tx = std::tan(tilt_x);
-  for (int y = 0; y < N; ++y) {
-    int K = -1;
-    for (int x = 0; x < N; ++x)
-      if (keep_bin(N, frac, mask, y, x)) K = std::max(K, std::abs(signed_bin(x, N)));
-    for (int x = 0; x < N; ++x)
-      if (keep_bin(N, frac, mask, y, x) != (std::abs(signed_bin(x, N)) <= K)) return false;
-    const double q = (double)signed_bin(y, N) / N / dx;
-    const double ph = -kPiD * lam * dz * q * q + 2.0 * kPiD * dz * q * ty;
-    float kb;
-    std::memcpy(&kb, &K, sizeof kb);
-    py[y] = make_float4((float)(std::cos(ph) * inv_n2), (float)(std::sin(ph) * inv_n2), kb, 0.f);
-  }
-  for (int x = 0; x < N; ++x) {
-    const double q = (double)signed_bin(x, N) / N / dx;
-    const double ph = -kPiD * lam * dz * q * q + 2.0 * kPiD * dz * q * tx;
-    px[x] = make_float2((float)std::cos(ph), (float)std::sin(ph));
-  }
-  return true;
 }
 
 struct Sizes {
@@ -593,20 +526,23 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   std::vector<uint8_t> mask;
   if (g->bandlimit_mask) mask.assign(g->bandlimit_mask, g->bandlimit_mask + N2);
   c->g.bandlimit_mask = nullptr;   // copied above; the caller's array is not kept
+  static_assert(sizeof(pty_host::F2) == sizeof(float2) && sizeof(pty_host::F4) == sizeof(float4),
+                "host propagator tables are copied as float2 / float4");
   std::vector<uint8_t> live(N, 0);
-  std::vector<float4> py_all;
-  std::vector<float2> px_all;
+  std::vector<pty_host::F4> py_all;
+  std::vector<pty_host::F2> px_all;
   bool sep = S > 1;
   for (int i = 0; i < S - 1; ++i) {
-    std::vector<float2> H = propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y, g->tilt_x, mask);
+    std::vector<pty_host::F2> H =
+        pty_host::propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y, g->tilt_x, mask);
     if (hipMemcpy(c->prop + (size_t)i * N2, H.data(), N2 * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       return fail(PTY_EHIP);
     for (size_t e = 0; e < N2; ++e)
       if (H[e].x != 0.f || H[e].y != 0.f) live[e % N] = 1;
-    std::vector<float4> py;
-    std::vector<float2> px;
-    if (sep && separable_propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y, g->tilt_x, mask,
-                                    py, px)) {
+    std::vector<pty_host::F4> py;
+    std::vector<pty_host::F2> px;
+    if (sep && pty_host::separable_propagator(N, g->dx, g->wavelength, c->dz[i], g->bandlimit, g->tilt_y,
+                                              g->tilt_x, mask, py, px)) {
       py_all.insert(py_all.end(), py.begin(), py.end());
       px_all.insert(px_all.end(), px.begin(), px.end());
     } else {
@@ -625,12 +561,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
     if ((st = dmalloc(&c->live, (size_t)N, e))) return fail(st);
     if (hipMemcpy(c->live, live.data(), N, hipMemcpyHostToDevice) != hipSuccess) return fail(PTY_EHIP);
     // a symmetric band |k_x| <= K (any circular limit) is tested without the table
-    int K = -1;
-    for (int x = 0; x < N; ++x)
-      if (live[x]) K = std::max(K, std::abs(signed_bin(x, N)));
-    bool interval = true;
-    for (int x = 0; x < N; ++x) interval &= (live[x] != 0) == (std::abs(signed_bin(x, N)) <= K);
-    c->live_k = interval ? K : -1;
+    c->live_k = pty_host::live_interval(live, N);
     const int nb = col_blocks(N), cb = N / nb;
     for (int q = 0; q < nb; ++q)
       for (int x = q * cb; x < (q + 1) * cb; ++x)
