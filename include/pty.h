@@ -177,7 +177,9 @@ pty_status pty_set_strategy(pty_ctx* ctx, int32_t strategy);
  * lists one position twice). ORDERED also avoids the contention of many
  * overlapping windows (a whole dense scan in one group). It applies to the
  * two-pass kernels; with it set, RESIDENT runs two-pass. The LSQML
- * illumination sums stay atomic. Returns PTY_EINVAL for another mode. */
+ * illumination sums follow the same mode (a context created with lsqml also
+ * holds max_batch x N x N floats of scratch for them). Returns PTY_EINVAL for
+ * another mode. */
 #define PTY_REDUCE_ATOMIC 0
 #define PTY_REDUCE_ORDERED 1
 pty_status pty_set_reduction(pty_ctx* ctx, int32_t mode);

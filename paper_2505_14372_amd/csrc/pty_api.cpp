@@ -96,6 +96,7 @@ Sizes ctx_sizes(const pty_geometry* g, int max_batch, int k, int ck_elem = 8, bo
     b += align256((size_t)(kLsqSplit + 1) * N2 * sizeof(float));       // transparency partials + sum
     b += align256(HW * sizeof(float));                                 // transparency map
     b += align256(((size_t)S * lsq_blocks(HW) * 3 + 2 * S + 2) * sizeof(double));
+    b += align256((size_t)max_batch * N2 * sizeof(float));             // ordered illumination scratch
   }
   s.bytes = b;
   return s;
@@ -210,6 +211,7 @@ struct pty_ctx {
   float* lsq_part = nullptr;
   float* lsq_wp = nullptr;
   float* lsq_tau = nullptr;
+  float* lsq_wscr = nullptr;       // ordered reduction of the illumination sums [max_batch][N][N]
   double* lsq_sums = nullptr;
   // tape of pty_forward_save
   bool tape_valid = false;
@@ -508,7 +510,8 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
     const size_t HW = (size_t)g->obj_h * g->obj_w;
     if ((st = dmalloc(&c->lsq_w, (size_t)S * HW, e)) || (st = dmalloc(&c->lsq_part, (size_t)kLsqSplit * N2, e)) ||
         (st = dmalloc(&c->lsq_wp, N2, e)) || (st = dmalloc(&c->lsq_tau, HW, e)) ||
-        (st = dmalloc(&c->lsq_sums, (size_t)S * lsq_blocks(HW) * 3 + 2 * S + 2, e)))
+        (st = dmalloc(&c->lsq_sums, (size_t)S * lsq_blocks(HW) * 3 + 2 * S + 2, e)) ||
+        (st = dmalloc(&c->lsq_wscr, (size_t)max_batch * N2, e)))
       return fail(st);
   }
   if (max_batch > 0) {
@@ -602,7 +605,7 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
   dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
   dfree(c->prop_y); dfree(c->prop_x); dfree(c->cscr);
-  dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums); dfree(c->lsq_tau);
+  dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums); dfree(c->lsq_tau); dfree(c->lsq_wscr);
   delete c;
 }
 
@@ -1001,6 +1004,7 @@ extern "C" pty_status pty_lsqml_step(pty_ctx* c, void* stream, pty_state* st, co
   LaunchCtx L = ctx_launch(c, s, r, B);
   L.resident = 0;
   L.wsum = 1;
+  L.wscr = L.cscr ? c->lsq_wscr : nullptr;   // the illumination sums follow the reduction mode
   {
     ProfScope p(P_FILL, s);
     launch_fill(s, (float*)c->gobj, (size_t)S * HW * 2, 0.f);

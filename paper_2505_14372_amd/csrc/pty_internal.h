@@ -110,6 +110,8 @@ struct LaunchCtx {
   int* flags;
   int emax;                 // the first forward records the window maxima (ePIE)
   int wsum;                 // the adjoint row pass scatters the illumination (LSQML)
+  float* wscr;              // ordered reduction of the LSQML illumination sums: per-item
+                            // sum_m |psi_i,m|^2 scratch [items][N][N], or null (atomics)
   float2* cscr;             // ordered object-gradient reduction: per-item contribution scratch
                             // [items][N][N] (the adjoint row pass stores, k_obj_gather adds), or
                             // null (float atomics)

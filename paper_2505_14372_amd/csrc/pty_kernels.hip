@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
                                                       float2* __restrict__ ws, const void* __restrict__ ck_,
                                                       const float2* __restrict__ twg, int step,
                                                       PsiLoad psi, float scale, int item_off,
-                                                      float2* __restrict__ cscr) {
+                                                      float2* __restrict__ cscr, float* __restrict__ wscr) {
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
   __shared__ float2 tw[N];
   __shared__ float2 xch[LINES * Xch<N>::ROW_STRIDE];
@@ -394,7 +394,12 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     }
   }
   if constexpr (WSUM) {
-    if (r.wsum) {
+    if (r.wsum && wscr) {
+      // ordered reduction: stored per position, added in batch order by k_obj_gather
+      float* dst = wscr + ((size_t)(item_off + blockIdx.y) * N + y) * N;
+#pragma unroll
+      for (int a = 0; a < E; ++a) dst[l + L * a] = pw[a];
+    } else if (r.wsum) {
 #pragma unroll
       for (int a = 0; a < E; ++a) unsafeAtomicAdd(r.wsum + orow + l + L * a, pw[a]);
     }
@@ -801,10 +806,12 @@ __global__ void k_loss_reduce(const ReqTable reqs, const float* __restrict__ los
 // request's items, 256 at a time), wave w sums the w-th contiguous quarter of
 // each list in list order (loads for four positions issued ahead of their
 // additions), and the four wave sums are added in wave order at the end.
+// With WS the stored illumination sums of LSQML (wscr) are added the same way into r.wsum.
 constexpr int kGatherTY = 8, kGatherW = 4;
-template <int N>
+template <int N, bool WS>
 __global__ __launch_bounds__(64 * kGatherW) void k_obj_gather(const Item* __restrict__ items, const ReqTable reqs,
-                                                              const float2* __restrict__ cscr, int step,
+                                                              const float2* __restrict__ cscr,
+                                                              const float* __restrict__ wscr, int step,
                                                               int item_off, int n_items) {
   const ReqDev& r = reqs.r[blockIdx.z];
   const int i = r.S - 1 - step;
@@ -815,18 +822,27 @@ __global__ __launch_bounds__(64 * kGatherW) void k_obj_gather(const Item* __rest
   __shared__ int list[64 * kGatherW];
   __shared__ int wcnt[kGatherW];
   __shared__ float2 part[kGatherW - 1][kGatherTY][64];
+  __shared__ float wpart[WS ? kGatherW - 1 : 1][kGatherTY][64];
   float2 acc[kGatherTY];
+  float wacc[kGatherTY];
 #pragma unroll
-  for (int t = 0; t < kGatherTY; ++t) acc[t] = make_float2(0.f, 0.f);
-  // contribution of position bj to row y0 + t of this thread's column (zero outside its window)
-  auto fetch = [&](int bj, float2 (&v)[kGatherTY]) {
+  for (int t = 0; t < kGatherTY; ++t) {
+    acc[t] = make_float2(0.f, 0.f);
+    wacc[t] = 0.f;
+  }
+  // contribution of position bj to row y0 + t of this thread's column (zero
+  // outside its window), and with WS its illumination
+  auto fetch = [&](int bj, float2 (&v)[kGatherTY], float (&w)[kGatherTY]) {
     const Item it = items[bj];
     const int wx = x - it.nx;
     const float2* src = cscr + (size_t)bj * N * N;
+    const float* wsrc = WS ? wscr + (size_t)bj * N * N : nullptr;
 #pragma unroll
     for (int t = 0; t < kGatherTY; ++t) {
       const int wy = y0 + t - it.ny;
-      v[t] = (wy >= 0 && wy < N && wx >= 0 && wx < N) ? src[wy * N + wx] : make_float2(0.f, 0.f);
+      const bool in = wy >= 0 && wy < N && wx >= 0 && wx < N;
+      v[t] = in ? src[wy * N + wx] : make_float2(0.f, 0.f);
+      if constexpr (WS) w[t] = in ? wsrc[wy * N + wx] : 0.f;
     }
   };
   int total = 0;
@@ -854,25 +870,36 @@ __global__ __launch_bounds__(64 * kGatherW) void k_obj_gather(const Item* __rest
     int k = beg;
     for (; k + 4 <= end; k += 4) {
       float2 v0[kGatherTY], v1[kGatherTY], v2[kGatherTY], v3[kGatherTY];
-      fetch(__builtin_amdgcn_readfirstlane(list[k]), v0);
-      fetch(__builtin_amdgcn_readfirstlane(list[k + 1]), v1);
-      fetch(__builtin_amdgcn_readfirstlane(list[k + 2]), v2);
-      fetch(__builtin_amdgcn_readfirstlane(list[k + 3]), v3);
+      float w0[kGatherTY], w1[kGatherTY], w2[kGatherTY], w3[kGatherTY];
+      fetch(__builtin_amdgcn_readfirstlane(list[k]), v0, w0);
+      fetch(__builtin_amdgcn_readfirstlane(list[k + 1]), v1, w1);
+      fetch(__builtin_amdgcn_readfirstlane(list[k + 2]), v2, w2);
+      fetch(__builtin_amdgcn_readfirstlane(list[k + 3]), v3, w3);
 #pragma unroll
-      for (int t = 0; t < kGatherTY; ++t) acc[t] = cadd(cadd(cadd(cadd(acc[t], v0[t]), v1[t]), v2[t]), v3[t]);
+      for (int t = 0; t < kGatherTY; ++t) {
+        acc[t] = cadd(cadd(cadd(cadd(acc[t], v0[t]), v1[t]), v2[t]), v3[t]);
+        if constexpr (WS) wacc[t] = (((wacc[t] + w0[t]) + w1[t]) + w2[t]) + w3[t];
+      }
     }
     for (; k < end; ++k) {
       float2 v0[kGatherTY];
-      fetch(__builtin_amdgcn_readfirstlane(list[k]), v0);
+      float w0[kGatherTY];
+      fetch(__builtin_amdgcn_readfirstlane(list[k]), v0, w0);
 #pragma unroll
-      for (int t = 0; t < kGatherTY; ++t) acc[t] = cadd(acc[t], v0[t]);
+      for (int t = 0; t < kGatherTY; ++t) {
+        acc[t] = cadd(acc[t], v0[t]);
+        if constexpr (WS) wacc[t] += w0[t];
+      }
     }
     __syncthreads();   // the list is rebuilt for the next items
   }
   if (total == 0) return;
   if (w > 0) {
 #pragma unroll
-    for (int t = 0; t < kGatherTY; ++t) part[w - 1][t][lane] = acc[t];
+    for (int t = 0; t < kGatherTY; ++t) {
+      part[w - 1][t][lane] = acc[t];
+      if constexpr (WS) wpart[w - 1][t][lane] = wacc[t];
+    }
   }
   __syncthreads();
   if (w != 0 || x >= r.W) return;
@@ -884,6 +911,18 @@ __global__ __launch_bounds__(64 * kGatherW) void k_obj_gather(const Item* __rest
     for (int q = 1; q < kGatherW; ++q) s = cadd(s, part[q - 1][t][lane]);
     const int y = y0 + t;
     if (y < r.H) g[(size_t)y * r.W + x] = cadd(g[(size_t)y * r.W + x], s);
+  }
+  if constexpr (WS) {
+    if (!r.wsum) return;
+    float* ws = r.wsum + (size_t)i * r.H * r.W;
+#pragma unroll
+    for (int t = 0; t < kGatherTY; ++t) {
+      float s = wacc[t];
+#pragma unroll
+      for (int q = 1; q < kGatherW; ++q) s += wpart[q - 1][t][lane];
+      const int y = y0 + t;
+      if (y < r.H) ws[(size_t)y * r.W + x] += s;
+    }
   }
 }
 
@@ -1028,20 +1067,20 @@ struct Launch {
     dim3 g(Pass<N>::NBLK, L.n_items);
     if (psi.spec) {
       if (L.wsum)
-        hipLaunchKernelGGL((k_row_adj<N, false, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
+        hipLaunchKernelGGL((k_row_adj<N, false, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr, L.wscr);
       else
-        hipLaunchKernelGGL((k_row_adj<N, false, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
+        hipLaunchKernelGGL((k_row_adj<N, false, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr, L.wscr);
       return;
     }
     if (L.wsum) {
       if (L.ck_half)
-        hipLaunchKernelGGL((k_row_adj<N, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
+        hipLaunchKernelGGL((k_row_adj<N, true, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr, L.wscr);
       else
-        hipLaunchKernelGGL((k_row_adj<N, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
+        hipLaunchKernelGGL((k_row_adj<N, false, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr, L.wscr);
     } else if (L.ck_half) {
-      hipLaunchKernelGGL((k_row_adj<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
+      hipLaunchKernelGGL((k_row_adj<N, true>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr, L.wscr);
     } else {
-      hipLaunchKernelGGL((k_row_adj<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr);
+      hipLaunchKernelGGL((k_row_adj<N, false>), g, dim3(kThreads), 0, L.stream, L.items, L.reqs, L.ws, L.ck, L.tw, step, psi, scale, L.item_off, L.cscr, L.wscr);
     }
   }
   static void col(const LaunchCtx& L, int op, int step) {
@@ -1066,8 +1105,12 @@ struct Launch {
   }
   static void obj_gather(const LaunchCtx& L, int step, int max_h, int max_w) {
     dim3 g((max_w + 63) / 64, (max_h + kGatherTY - 1) / kGatherTY, L.n_reqs);
-    hipLaunchKernelGGL((k_obj_gather<N>), g, dim3(64 * kGatherW), 0, L.stream, L.items, L.reqs, L.cscr, step,
-                       L.item_off, L.n_items);
+    if (L.wsum && L.wscr)
+      hipLaunchKernelGGL((k_obj_gather<N, true>), g, dim3(64 * kGatherW), 0, L.stream, L.items, L.reqs, L.cscr,
+                         L.wscr, step, L.item_off, L.n_items);
+    else
+      hipLaunchKernelGGL((k_obj_gather<N, false>), g, dim3(64 * kGatherW), 0, L.stream, L.items, L.reqs, L.cscr,
+                         nullptr, step, L.item_off, L.n_items);
   }
   static void far_loss(const LaunchCtx& L, int step, bool grad) {
     dim3 g(ColPass<N>::NBLK, L.n_items);

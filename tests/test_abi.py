@@ -58,7 +58,8 @@ def test_workspace_sizes_follow_the_layout(lib):
     # the LSQML scratch: an illumination scatter of the object's size, a transparency map
     # of one slice's size, plus small sums
     bl = api.workspace_bytes(N, M, S, H, W, J, B, checkpoint_every=1, lsqml=True)
-    assert (S + 1) * H * W * 4 <= bl - b1 < (S + 1) * H * W * 4 + 40 * N * N * 4 + 2 ** 20
+    # ... and, for the ordered reduction, one float per pixel and position of the group
+    assert (S + 1) * H * W * 4 + B * N * N * 4 <= bl - b1 < (S + 1) * H * W * 4 + B * N * N * 4 + 40 * N * N * 4 + 2 ** 20
 
 
 def test_invalid_arguments_are_rejected_on_the_host(lib):

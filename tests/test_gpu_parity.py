@@ -656,6 +656,28 @@ def test_lsqml_step_matches_oracle(N, loss, eps, ck_every, chunk, red):
     assert np.array_equal(_np(st.positions), c.pos)
 
 
+def test_ordered_lsqml_step_is_bitwise_repeatable():
+    """Under the ordered reduction an LSQML step from the same state and sums
+    (object direction, illumination scatter, steps) gives identical bits."""
+    from paper_2505_14372_amd import api
+    c = Case(synth.make_small(N=64, M=2, S=3, scan=4, step=4, seed=61, loss="poisson", eps=0.5, amp_noise=0.3))
+    d = c.device()
+    prob = c.problem(max_batch=len(c.batch), lsqml=True)
+    prob.set_reduction("ordered")
+    b = torch.tensor([0, 1, 2, 4, 5, 6, 8, 9, 10, 12, 13, 15], dtype=torch.int32, device="cuda")
+    kw = dict(beta_object=0.5, beta_probe=0.5, delta_object=1e-2, delta_probe=1e-2)
+    outs = []
+    for _ in range(2):
+        st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+        il = api.IllumSums(c.S, c.H, c.W, c.N)
+        loss = prob.lsqml_step(st, il, d["pats"], b, **kw)
+        prob.check()
+        outs.append((loss.item(), st.object.clone(), st.probe.clone(), il.obj_cur.clone(), il.probe_cur.clone()))
+    (l0, *a0), (l1, *a1) = outs
+    assert l0 == l1
+    assert all(torch.equal(x, y) for x, y in zip(a0, a1))
+
+
 def test_lsqml_needs_its_scratch():
     from paper_2505_14372_amd import _lib, api
     c = Case(synth.make_small(N=64, M=1, S=1, scan=2, step=4, seed=3, loss="amplitude"))
