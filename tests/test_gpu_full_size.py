@@ -100,3 +100,21 @@ def test_full_size_half_checkpoints(full):
     for x, y in zip(a[1:], b[1:]):
         print(rel_l2(_np(y), _np(x)))
         assert rel_l2(_np(y), _np(x)) < 1e-3
+
+
+def test_full_size_ordered_reduction_is_bitwise_repeatable(full):
+    """The ordered object-gradient reduction at full size: two calls give the
+    same bits, and the result equals the atomic reduction's to rounding."""
+    c = full
+    d = c.device()
+    prob = c.problem(max_batch=B)
+    _, gO_at, gP_at, _ = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.set_reduction("ordered")
+    runs = [prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"]) for _ in range(2)]
+    prob.check()
+    (l1, gO1, gP1, gX1), (l2, gO2, gP2, gX2) = runs
+    assert l1.item() == l2.item()
+    assert torch.equal(gO1, gO2) and torch.equal(gP1, gP2) and torch.equal(gX1, gX2)
+    print(rel_l2(_np(gO1), _np(gO_at)), rel_l2(_np(gP1), _np(gP_at)), flush=True)
+    assert rel_l2(_np(gO1), _np(gO_at)) < 1e-5
+    assert rel_l2(_np(gP1), _np(gP_at)) < 1e-5
