@@ -86,6 +86,8 @@ def test_forward_parity(cache, name):
     I, loss = prob.forward(d["probe"], d["obj"], d["pos"], d["batch"], patterns=d["pats"])
     prob.check()
     assert rel_l2(_np(I), ref["I"]) < TOL_I, rel_l2(_np(I), ref["I"])
+    # element by element: no pixel off by more than TOL_I of the largest intensity
+    assert max_rel(_np(I), ref["I"]) < TOL_I, max_rel(_np(I), ref["I"])
     assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
 
 
@@ -102,6 +104,11 @@ def test_gradient_parity(cache, name):
                 pos=rel_l2(_np(gX), ref["g_pos"]))
     print(errs)
     assert all(e < TOL_G for e in errs.values()), errs
+    # element by element, against the largest entry of each gradient
+    emax = dict(obj=max_rel(_np(gO), ref["g_object"]), probe=max_rel(_np(gP), ref["g_probe"]),
+                pos=max_rel(_np(gX), ref["g_pos"]))
+    print(emax)
+    assert all(e < TOL_G for e in emax.values()), emax
     # object gradient vanishes outside every window
     n = np.floor(c.pos.astype(np.float64)[c.batch] + 0.5).astype(int)
     cover = np.zeros((c.H, c.W), bool)
