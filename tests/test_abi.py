@@ -59,7 +59,8 @@ def test_workspace_sizes_follow_the_layout(lib):
     # of one slice's size, plus small sums
     bl = api.workspace_bytes(N, M, S, H, W, J, B, checkpoint_every=1, lsqml=True)
     # ... and, for the ordered reduction, one float per pixel and position of the group
-    assert (S + 1) * H * W * 4 + B * N * N * 4 <= bl - b1 < (S + 1) * H * W * 4 + B * N * N * 4 + 40 * N * N * 4 + 2 ** 20
+    lsq = (S + 1) * H * W * 4 + B * N * N * 4
+    assert lsq <= bl - b1 < lsq + 40 * N * N * 4 + 2 ** 20
 
 
 def test_invalid_arguments_are_rejected_on_the_host(lib):
@@ -80,6 +81,9 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.pty_group_create(100, 1, 1, 1, C.byref(ctx)) == _lib.PTY_EUNSUPPORTED
     assert lib.pty_group_reconstruct_step(None, None, None, 0) == _lib.PTY_EINVAL
     assert lib.pty_last_error(None) == b"NULL context"
+    assert lib.pty_set_reduction(None, 1) == _lib.PTY_EINVAL
+    assert lib.pty_set_strategy(None, 1) == _lib.PTY_EINVAL
+    assert lib.pty_set_chunk(None, 4) == _lib.PTY_EINVAL
 
 
 @pytest.mark.parametrize("prog", ["line_fft_check", "resident_check"])
