@@ -123,7 +123,9 @@ typedef struct pty_ctx pty_ctx;
  * every k-th and recomputes the others
  * segment by segment in the backward pass; 0 picks 1 if the workspace fits
  * in hbm_budget bytes (0 = no limit), else the smallest k that fits.
- * Builds the propagator tables on the device. */
+ * Builds the propagator tables (and, when the band limit allows, their
+ * separable factors) on the device, and holds max_batch x N x N complex64 of
+ * scratch for the ordered object-gradient reduction (pty_set_reduction). */
 pty_status pty_create(const pty_geometry* g, int32_t max_batch, int32_t checkpoint_every,
                       size_t hbm_budget, pty_ctx** out);
 
@@ -136,7 +138,8 @@ typedef struct {
                                 half floats (round to nearest), halving their HBM
                                 traffic; only the object gradient reads them */
   int32_t lsqml;             /* 1: also allocate the scratch of pty_lsqml_step
-                                ((S+1)*H*W + 33*N*N floats and a few sums) */
+                                ((S+1)*H*W + 33*N*N floats, a few sums, and
+                                max_batch*N*N floats for the ordered reduction) */
 } pty_options;
 
 /* pty_create with the options above; pty_create(g, b, k, budget, out) equals
@@ -189,7 +192,8 @@ pty_status pty_set_reduction(pty_ctx* ctx, int32_t mode);
  * `positions` batch entries, one chunk after the other, so that a chunk's
  * work tiles can stay in the last-level cache between passes; 0 (the
  * default) processes the whole group in every launch. Results do not depend
- * on the chunk size beyond the order of floating-point atomic additions. */
+ * on the chunk size beyond the order of floating-point additions (under the
+ * ordered reduction one chunk size always gives the same bits). */
 pty_status pty_set_chunk(pty_ctx* ctx, int32_t positions);
 
 /* Forward model (Sec. 3) for the positions batch_idx[0..batch) (device int32,
