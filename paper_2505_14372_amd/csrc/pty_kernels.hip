@@ -231,6 +231,18 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) pw[a] = 0.f;
   }
+  // Each mode's output row is stored after the next mode's input requests:
+  // vector-memory operations complete in issue order, so a wait for loads
+  // issued after the stores would also wait for the stores to be acknowledged.
+  float2 vout[E];
+  float2* out_row = nullptr;
+  auto flush = [&]() {
+    if (!out_row) return;
+#pragma unroll
+    for (int a = 0; a < E; ++a)
+      if ((omask >> a) & 1u) out_row[l + L * a] = vout[a];
+    out_row = nullptr;
+  };
   for (int m = 0; m < r.M; ++m) {
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
@@ -238,6 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
       const CT* src = static_cast<const CT*>(store.src) + (ck_tile(it, r, m, store.src_slot) * N + y) * N;
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = Ck<HALF>::load(src + l + L * a);
+      flush();
     } else {
       // the row spectrum comes from the work tile, or (spectral checkpoints)
       // from checkpoint slot i, where the column pass left it
@@ -246,6 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
                              : trow;
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = (lmask >> a) & 1u ? in[l + L * a] : make_float2(0.f, 0.f);
+      flush();
       line_fft<N, true>(v, l, tw, sx, WaveSync{});
     }
     if (store.mode == 1 && (i % r.ck_every) == 0) {
@@ -266,9 +280,10 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
     for (int a = 0; a < E; ++a) v[a] = cmul(v[a], o[a]);
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
 #pragma unroll
-    for (int a = 0; a < E; ++a)
-      if ((omask >> a) & 1u) trow[l + L * a] = v[a];
+    for (int a = 0; a < E; ++a) vout[a] = v[a];
+    out_row = trow;
   }
+  flush();
   if constexpr (EMAX) {
     float mp = 0.f, mo = 0.f;
 #pragma unroll
@@ -351,6 +366,16 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) pw[a] = 0.f;
   }
+  // each mode's output row is stored after the next mode's requests (see k_row_fwd)
+  float2 hout[E];
+  float2* out_row = nullptr;
+  auto flush = [&]() {
+    if (!out_row) return;
+#pragma unroll
+    for (int a = 0; a < E; ++a)
+      if ((omask >> a) & 1u) out_row[l + L * a] = hout[a];
+    out_row = nullptr;
+  };
   for (int m = 0; m < r.M; ++m) {
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     const CT* prow;
@@ -362,6 +387,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     float2 ps[SPEC ? E : 1];
     load_row_masked<N>(v, trow, l, gmask);
     if constexpr (SPEC) load_row_masked<N>(ps, reinterpret_cast<const float2*>(prow), l, cmask);
+    flush();
     line_fft<N, true>(v, l, tw, sx, WaveSync{});
     if constexpr (SPEC) line_fft<N, true>(ps, l, tw, sx, WaveSync{});
 #pragma unroll
@@ -375,9 +401,10 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     }
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
 #pragma unroll
-    for (int a = 0; a < E; ++a)
-      if ((omask >> a) & 1u) trow[l + L * a] = v[a];
+    for (int a = 0; a < E; ++a) hout[a] = v[a];
+    out_row = trow;
   }
+  flush();
   if (r.gobj) {
     if (cscr) {
       // ordered reduction: this position's contribution, added in batch order by k_obj_gather
