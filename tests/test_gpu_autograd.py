@@ -22,10 +22,11 @@ def ms192():
     return Case(wl, batch=[1000, 1001, 1065, 2222])
 
 
-def _run(c, budget=0):
+def _run(c, budget=0, reduction="atomic"):
     from paper_2505_14372_amd.autograd import multislice_loss
     d = c.device()
     prob = c.problem(checkpoint_every=0 if budget else 1, hbm_budget=budget)
+    prob.set_reduction(reduction)
     obj = d["obj"].clone().requires_grad_(True)
     probe = d["probe"].clone().requires_grad_(True)
     pos = d["pos"].clone().requires_grad_(True)
@@ -104,6 +105,20 @@ def test_autograd_recompute_under_budget_matches(ms192):
     assert abs(a[1] - b[1]) <= 1e-12 * abs(a[1])
     for x, y in zip(a[2:], b[2:]):
         assert rel_l2(y, x) < 1e-6
+
+
+def test_autograd_under_the_ordered_reduction_repeats_bitwise(ms192):
+    """The split forward/backward under the ordered reduction: identical
+    gradients on a repeated call, equal to the atomic ones to rounding."""
+    c = ms192
+    a = _run(c)
+    b1 = _run(c, reduction="ordered")
+    b2 = _run(c, reduction="ordered")
+    assert b1[1] == b2[1]
+    for x, y in zip(b1[2:], b2[2:]):
+        assert np.array_equal(x, y)
+    for x, y in zip(a[2:], b1[2:]):
+        assert rel_l2(y, x) < 1e-5
 
 
 def test_autograd_rejects_stale_tape(ms192):
