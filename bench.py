@@ -291,11 +291,17 @@ def main():
 
 
 def kernel_source_hash():
+    """sha256 of the kernel sources with comments and whitespace removed, so
+    that a comment edit does not orphan counters taken on the same code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in ("pty_kernels.hip", "pty_fft.hpp", "pty_internal.h"):
-        with open(os.path.join(ROOT, "paper_2505_14372_amd", "csrc", p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2505_14372_amd", "csrc", p)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

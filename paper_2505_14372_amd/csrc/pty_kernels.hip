@@ -306,10 +306,12 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 
 // Adjoint slice step, row part (slice i = S - 1 - step for each item):
 //   g = IDFT_x(tile row)                (gradient wrt phi_i, real space)
-//   grad O_i += sum_m conj(psi_i,m) g   (scatter-added into the object gradient)
+//   grad O_i += sum_m conj(psi_i,m) g   (scatter-added into the object gradient
+//                                         with atomics, or, with cscr, stored per
+//                                         position for k_obj_gather's ordered sum)
 //   h = conj(O_i) g ; tile row = DFT_x(h)
 // With WSUM the illumination sum_m |psi_i,m|^2 of the window is also scattered
-// into r.wsum (LSQML).
+// into r.wsum (LSQML), or stored in wscr for the ordered sum.
 // With SPEC the checkpoint slot holds the row spectrum F_x(psi_i) (float2),
 // and psi_i is recovered with the forward pass's own inverse row DFT.
 template <int N, bool HALF, bool WSUM = false, bool SPEC = false>
