@@ -196,6 +196,9 @@ def test_empty_and_oversized_batches_are_rejected():
     with pytest.raises(PtyError) as e:
         prob.check()
     assert e.value.status == PTY_EBOUNDS
+    # unknown strategy / reduction modes are refused on a live context
+    assert prob.lib.pty_set_reduction(prob.ctx, 2) == PTY_EINVAL
+    assert prob.lib.pty_set_strategy(prob.ctx, 9) == PTY_EINVAL
 
 
 @pytest.mark.parametrize("k", [2, 3, 7])
