@@ -20,6 +20,17 @@ TOL_I = 1e-4
 TOL_G = 1e-3
 
 
+def _widen(wl, extra, seed, shift=0.0):
+    """Append `extra` weak-phase columns to every object slice (H != W) and move
+    the windows right by `shift` pixels; returns the workload."""
+    rng = np.random.default_rng(seed)
+    pad = np.exp(1j * 0.2 * rng.random((wl.S, wl.H, extra)))
+    wl.obj = np.concatenate([wl.obj, pad], axis=2)
+    wl.W = wl.obj.shape[2]
+    wl.positions = wl.positions + np.array([0.0, shift])
+    return wl
+
+
 def _case(name):
     if name == "n64_spoa_amp":       # config 0 in miniature: one slice, one mode, amplitude, eps = 0
         return Case(synth.make_small(N=64, M=1, S=1, scan=5, step=4, seed=0, loss="amplitude", eps=0.0,
@@ -51,6 +62,10 @@ def _case(name):
         wl.bandlimit_mask = ((k[None, :] >= -10) & (k[None, :] <= 20) & (np.abs(k)[:, None] <= 18)) | \
             ((np.abs(k)[None, :] <= 3) & (np.abs(k)[:, None] <= 25))
         return Case(wl)
+    if name == "n64_wide_object":      # H != W: catches swapped object axes
+        wl = synth.make_small(N=64, M=2, S=3, scan=3, step=5, seed=8, loss="poisson", eps=0.8, phi_max=0.2,
+                              dose=1e5)
+        return Case(_widen(wl, 37, seed=8, shift=29.0))
     if name == "n64_amp_eps_nobl":
         return Case(synth.make_small(N=64, M=2, S=3, scan=3, step=5, seed=5, loss="amplitude", eps=0.5,
                                      bandlimit=0.0, amp_noise=0.1))
@@ -58,7 +73,7 @@ def _case(name):
 
 
 CASES = ["n64_spoa_amp", "n64_ms_poisson", "n128_ms_poisson", "n192_ms_anscombe", "n256_ms_gaussian",
-         "n64_amp_eps_nobl", "n128_tilt_mask_dz", "n64_offset_mask"]
+         "n64_amp_eps_nobl", "n128_tilt_mask_dz", "n64_offset_mask", "n64_wide_object"]
 
 
 @pytest.fixture(scope="module")
@@ -343,7 +358,8 @@ def test_nonfinite_flag():
     assert e.value.status == PTY_ENONFINITE
 
 
-@pytest.mark.parametrize("name", ["n64_ms_poisson", "n128_tilt_mask_dz", "n192_ms_anscombe", "n256_ms_gaussian"])
+@pytest.mark.parametrize("name", ["n64_ms_poisson", "n128_tilt_mask_dz", "n192_ms_anscombe", "n256_ms_gaussian",
+                                  "n64_wide_object"])
 def test_ordered_reduction_is_bitwise_repeatable(cache, name):
     """The ordered object-gradient reduction matches the oracle, agrees with the
     atomic one to rounding, and gives identical bits on a repeated call."""
@@ -498,7 +514,9 @@ def test_half_checkpoints_parity(cache, name, k):
 def test_regularized_step_matches_oracle():
     """reconstruct_step with every cost regularizer and every constraint (Sec. 3.4)."""
     from paper_2505_14372_amd import api
-    c = Case(synth.make_small(N=64, M=2, S=4, scan=3, step=4, seed=30, loss="poisson", eps=0.8, amp_noise=0.3))
+    # a non-square object (76 x 97) so that the in-plane stencils cannot swap their axes unnoticed
+    c = Case(_widen(synth.make_small(N=64, M=2, S=4, scan=3, step=4, seed=30, loss="poisson", eps=0.8,
+                                     amp_noise=0.3), 21, seed=30, shift=11.0))
     d = c.device()
     prob = c.problem(max_batch=9)
     k = np.fft.fftfreq(64) * 64
@@ -533,7 +551,8 @@ def test_lowpass_and_deramp_constraints_match_oracle():
     """reconstruct_step with the object low pass and the phase deramp (Sec. 3.4)
     on an odd-sized object that carries an affine phase ramp per slice."""
     from paper_2505_14372_amd import api
-    wl = synth.make_small(N=64, M=2, S=3, scan=5, step=5, seed=31, loss="amplitude", amp_noise=0.2)
+    wl = _widen(synth.make_small(N=64, M=2, S=3, scan=5, step=5, seed=31, loss="amplitude", amp_noise=0.2),
+                14, seed=31, shift=6.0)
     S, H, W = wl.obj.shape
     y, x = np.mgrid[:H, :W]
     wl.obj = wl.obj * np.exp(1j * (0.3 + 0.02 * np.arange(1, S + 1)[:, None, None] * y
