@@ -614,7 +614,8 @@ def test_epie_step_matches_oracle(N, loss, eps, ck_every, red):
     them, against the oracle (objects with amplitude below 1, so the wave
     normalisers differ from 1; recomputed segments when ck_every > 1)."""
     from paper_2505_14372_amd import api
-    c = Case(synth.make_small(N=N, M=2, S=4, scan=3, step=5, seed=40 + N, loss=loss, eps=eps, amp_noise=0.3))
+    c = Case(_widen(synth.make_small(N=N, M=2, S=4, scan=3, step=5, seed=40 + N, loss=loss, eps=eps,
+                                     amp_noise=0.3), 9, seed=40 + N, shift=4.0))
     d = c.device()
     prob = c.problem(max_batch=len(c.batch), checkpoint_every=ck_every)
     prob.set_reduction(red)
@@ -653,7 +654,8 @@ def test_lsqml_step_matches_oracle(N, loss, eps, ck_every, chunk, red):
     each step started from the GPU state and sums (first iteration with the
     running sums, then with the previous iteration's)."""
     from paper_2505_14372_amd import api
-    c = Case(synth.make_small(N=N, M=2, S=3, scan=3, step=5, seed=50 + N, loss=loss, eps=eps, amp_noise=0.3))
+    c = Case(_widen(synth.make_small(N=N, M=2, S=3, scan=3, step=5, seed=50 + N, loss=loss, eps=eps,
+                                     amp_noise=0.3), 9, seed=50 + N, shift=4.0))
     d = c.device()
     prob = c.problem(max_batch=len(c.batch), checkpoint_every=ck_every, lsqml=True)
     prob.set_chunk(chunk)
