@@ -460,6 +460,41 @@ def test_group_step_matches_single_steps(kind):
                 assert rel_l2(_np(a), _np(b)) < 1e-4
 
 
+def test_group_step_at_the_request_limit():
+    """Sixteen reconstructions (the request-table limit) of mixed modes, slices
+    and object sizes in one grouped step give, under the ordered reduction, the
+    bits of their single steps; a seventeenth is refused on the host."""
+    from paper_2505_14372_amd import api
+    from paper_2505_14372_amd._lib import PTY_EINVAL, PtyError
+    opt = api.Optimizer(kind="adam", lr_object=1e-2, lr_probe=1e-3, lr_pos=1e-2)
+    runs = []
+    for q in range(17):
+        c = Case(synth.make_small(N=64, M=1 + q % 3, S=1 + q % 4, scan=2 + q % 2, step=4 + q % 3, seed=70 + q,
+                                  loss=("poisson", "amplitude", "gaussian")[q % 3], eps=0.5))
+        d = c.device()
+        ps, pg = c.problem(max_batch=16), c.problem(max_batch=16)
+        ps.set_reduction("ordered")
+        pg.set_reduction("ordered")
+        b = torch.arange(len(c.batch), dtype=torch.int32, device="cuda")
+        single = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=True)
+        grouped = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=True)
+        runs.append((ps, pg, d, b, single, grouped))
+    grp = api.Group(64, max_items=256, max_tiles=1024, max_ckpt_tiles=4096)
+    entries = [(pg, grouped, d["pats"], b, opt, torch.zeros(1, dtype=torch.float64, device="cuda"))
+               for ps, pg, d, b, single, grouped in runs]
+    with pytest.raises(PtyError) as e:
+        grp.step(entries)
+    assert e.value.status == PTY_EINVAL
+    grp.step(entries[:16])
+    for ps, pg, d, b, single, grouped in runs[:16]:
+        ps.reconstruct_step(single, d["pats"], b, opt)
+    torch.cuda.synchronize()
+    for ps, pg, d, b, single, grouped in runs[:16]:
+        assert torch.equal(grouped.object, single.object)
+        assert torch.equal(grouped.probe, single.probe)
+        assert torch.equal(grouped.positions, single.positions)
+
+
 def test_ordered_group_step_gives_the_single_step_bits():
     """Under the ordered reduction a reconstruction's object, probe and
     positions after Adam steps have the same bits alone and in grouped steps."""
