@@ -1,0 +1,66 @@
+"""Parity on seeded random configurations: window size, modes, slices, gaps,
+noise model, band limit, beam tilt, object shape and amplitude, scan, batch
+subset and order, strategy and reduction are drawn per case, and the HIP
+path's loss and gradients are compared element by element with the FP64
+oracle on the same inputs."""
+import numpy as np
+import pytest
+
+from paper_2505_14372_amd import synth
+
+from _cases import Case, max_rel, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL_I, TOL_G = 1e-4, 1e-3
+
+
+def _draw(seed):
+    rng = np.random.default_rng(1000 + seed)
+    N = int(rng.choice([64, 128, 192]))
+    M = int(rng.integers(1, 4))
+    S = int(rng.integers(1, 5))
+    loss = str(rng.choice(["amplitude", "anscombe", "poisson", "gaussian"]))
+    eps = float(rng.choice([0.0, 0.3, 0.8])) if loss != "gaussian" else 0.0
+    bandlimit = float(rng.choice([2.0 / 3.0, 0.5, 0.0]))
+    scan, step = int(rng.integers(2, 4)), int(rng.integers(3, 9))
+    wl = synth.make_small(N=N, M=M, S=S, scan=scan, step=step, seed=2000 + seed, loss=loss, eps=eps,
+                          phi_max=float(rng.uniform(0.05, 0.3)), amp_noise=float(rng.choice([0.0, 0.2])),
+                          dose=1e5, bandlimit=bandlimit)
+    if S > 1:
+        wl.dz = [float(x) for x in rng.uniform(0.5, 4.0, S - 1)]
+    if rng.random() < 0.5:
+        wl.tilt = (float(rng.uniform(-4e-3, 4e-3)), float(rng.uniform(-4e-3, 4e-3)))
+    extra = int(rng.integers(0, 24))
+    if extra:
+        pad = np.exp(1j * 0.2 * rng.random((wl.S, wl.H, extra)))
+        wl.obj = np.concatenate([wl.obj, pad], axis=2)
+        wl.W = wl.obj.shape[2]
+        wl.positions = wl.positions + np.array([0.0, float(rng.uniform(0, extra))])
+    J = wl.positions.shape[0]
+    batch = rng.permutation(J)[: int(rng.integers(1, J + 1))].astype(np.int32)
+    strategy = str(rng.choice(["two_pass", "resident"])) if N <= 128 else "two_pass"
+    reduction = str(rng.choice(["atomic", "ordered"]))
+    return Case(wl, batch=batch), strategy, reduction
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_configuration_matches_oracle(seed):
+    c, strategy, reduction = _draw(seed)
+    print(f"seed {seed}: N={c.N} M={c.M} S={c.S} H={c.H} W={c.W} B={len(c.batch)} loss={c.geom.loss} "
+          f"bandlimit={c.geom.bandlimit} tilt={c.tilt} {strategy} {reduction}", flush=True)
+    ref = c.oracle_grad()
+    d = c.device()
+    prob = c.problem()
+    prob.set_strategy(strategy)
+    prob.set_reduction(reduction)
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    for name, got, want in (("object", gO, ref["g_object"]), ("probe", gP, ref["g_probe"]),
+                            ("positions", gX, ref["g_pos"])):
+        g = got.detach().cpu().numpy()
+        e2, einf = rel_l2(g, want), max_rel(g, want)
+        print(f"  {name}: rel L2 {e2:.2e}, max {einf:.2e}")
+        assert e2 < TOL_G and einf < TOL_G, (name, e2, einf)
