@@ -1,8 +1,8 @@
 """Parity on seeded random configurations: window size, modes, slices, gaps,
 noise model, band limit, beam tilt, object shape and amplitude, scan, batch
-subset and order, strategy and reduction are drawn per case, and the HIP
-path's loss and gradients are compared element by element with the FP64
-oracle on the same inputs."""
+subset and order, strategy, reduction, checkpoint interval and storage, and
+chunk size are drawn per case, and the HIP path's loss and gradients are
+compared element by element with the FP64 oracle on the same inputs."""
 import numpy as np
 import pytest
 
@@ -42,19 +42,22 @@ def _draw(seed):
     batch = rng.permutation(J)[: int(rng.integers(1, J + 1))].astype(np.int32)
     strategy = str(rng.choice(["two_pass", "resident"])) if N <= 128 else "two_pass"
     reduction = str(rng.choice(["atomic", "ordered"]))
-    return Case(wl, batch=batch), strategy, reduction
+    sched = dict(checkpoint_every=int(rng.choice([1, 1, 2, 3])), checkpoint_half=bool(rng.random() < 0.25),
+                 chunk=int(rng.choice([0, 0, 2, 3])))
+    return Case(wl, batch=batch), strategy, reduction, sched
 
 
 @pytest.mark.parametrize("seed", range(16))
 def test_random_configuration_matches_oracle(seed):
-    c, strategy, reduction = _draw(seed)
+    c, strategy, reduction, sched = _draw(seed)
     print(f"seed {seed}: N={c.N} M={c.M} S={c.S} H={c.H} W={c.W} B={len(c.batch)} loss={c.geom.loss} "
-          f"bandlimit={c.geom.bandlimit} tilt={c.tilt} {strategy} {reduction}", flush=True)
+          f"bandlimit={c.geom.bandlimit} tilt={c.tilt} {strategy} {reduction} {sched}", flush=True)
     ref = c.oracle_grad()
     d = c.device()
-    prob = c.problem()
+    prob = c.problem(checkpoint_every=sched["checkpoint_every"], checkpoint_half=sched["checkpoint_half"])
     prob.set_strategy(strategy)
     prob.set_reduction(reduction)
+    prob.set_chunk(sched["chunk"])
     loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
     prob.check()
     assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
