@@ -243,10 +243,12 @@ def main():
     p50, p99 = np.percentile(step_ms, 50), np.percentile(step_ms, 99)
 
     # dominant kernel class and its roofline
-    dom = max(prof, key=lambda k: prof[k][0])
+    # dominant single-kernel class ("recompute" times a whole segment's row
+    # and column passes together, so it has no per-launch byte model)
+    dom = max((k for k in prof if k != "recompute" and prof[k][1] > 0), key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_s = dom_ms / dom_n / 1000.0
-    spectral = prob.checkpoint_every == 1 and not prob.checkpoint_half and args.strategy != "resident"
+    spectral = not prob.checkpoint_half and args.strategy != "resident"
     live = live_fraction(N, wl.bandlimit, S)
     bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral, live,
                                            args.reduction == "ordered")

@@ -120,8 +120,9 @@ typedef struct pty_ctx pty_ctx;
  * during the forward pass (in float storage as its row spectrum, which the
  * forward pass produces anyway, so storing costs no extra write; the
  * backward pass recovers the wave with an inverse row DFT); k > 1 stores
- * every k-th and recomputes the others
- * segment by segment in the backward pass; 0 picks 1 if the workspace fits
+ * every k-th and recomputes the others segment by segment in the backward
+ * pass (in float storage, as row spectra too, so a recomputed segment costs
+ * one row and one column pass per slice); 0 picks 1 if the workspace fits
  * in hbm_budget bytes (0 = no limit), else the smallest k that fits.
  * Builds the propagator tables (and, when the band limit allows, their
  * separable factors) on the device, and holds max_batch x N x N complex64 of

@@ -289,9 +289,9 @@ LaunchCtx ctx_launch(pty_ctx* c, hipStream_t s, const ReqDev& r, int B) {
   L.flags = c->flags;
   L.resident = (use_resident(c->strategy, c->g.N, c->ck_every) && c->reduce != PTY_REDUCE_ORDERED) ? 1 : 0;
   L.cscr = c->reduce == PTY_REDUCE_ORDERED ? c->cscr : nullptr;
-  // every slice stored in float: the column passes write the entry waves' row
+  // float checkpoints: the column passes write the stored entry waves' row
   // spectra straight into the checkpoint slots (the resident chains ignore it)
-  L.ck_spec = (c->ck_every == 1 && !c->ck_half) ? 1 : 0;
+  L.ck_spec = c->ck_half ? 0 : 1;
   L.col_live_blocks = c->live_blocks;
   return L;
 }
@@ -377,22 +377,37 @@ void run_backward_chunk(const LaunchCtx& L, int N, int S_max, const std::vector<
         ProfScope p(P_RECOMPUTE, L.stream);
         LaunchCtx R = L;
         R.ws = ws2;
-        PsiStore st{};
-        st.mode = 0;
-        st.src = L.ck;
-        st.src_slot = i0 / k;
         R.emax = 0;
-        R.ck_spec = 0;
-        launch_rows_fwd(R, N, i0, st, true);
-        for (int s = i0 + 1; s <= i1; ++s) {
-          launch_col(R, N, COL_PROP, s - 1);
-          PsiStore ss{};
-          ss.mode = 2;
-          ss.seg = seg;
-          ss.seg_len = k - 1;
-          ss.seg_slot = s - i0 - 1;
-          ss.stop_after_store = (s == i1) ? 1 : 0;
-          launch_rows_fwd(R, N, s, ss, false);
+        if (L.ck_spec) {
+          // row spectra: the row pass of slice s reads slot i0 / k (s = i0) or
+          // segment slot s - i0 - 1, and the column pass after it leaves the
+          // next slice's row spectrum in its segment slot
+          R.seg_out = SegOut{static_cast<float2*>(seg), k - 1, i0 + 1};
+          PsiStore st{};
+          st.mode = 3;
+          st.seg = seg;
+          st.seg_len = k - 1;
+          for (int s = i0; s < i1; ++s) {
+            st.seg_slot = s - i0 - 1;
+            launch_rows_fwd(R, N, s, st, false);
+            launch_col(R, N, COL_PROP, s);
+          }
+        } else {
+          PsiStore st{};
+          st.mode = 0;
+          st.src = L.ck;
+          st.src_slot = i0 / k;
+          launch_rows_fwd(R, N, i0, st, true);
+          for (int s = i0 + 1; s <= i1; ++s) {
+            launch_col(R, N, COL_PROP, s - 1);
+            PsiStore ss{};
+            ss.mode = 2;
+            ss.seg = seg;
+            ss.seg_len = k - 1;
+            ss.seg_slot = s - i0 - 1;
+            ss.stop_after_store = (s == i1) ? 1 : 0;
+            launch_rows_fwd(R, N, s, ss, false);
+          }
         }
         seg_lo = i0 + 1;
         seg_hi = i1;

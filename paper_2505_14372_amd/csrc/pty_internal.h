@@ -85,6 +85,14 @@ struct PsiStore {
   int stop_after_store;     // skip the transmission and forward DFT
 };
 
+// Segment buffer slots a propagation column pass writes its output to while a
+// segment of entry waves is recomputed with spectral checkpoints (seg null:
+// none). Slice s goes to slot s - base of [tiles][len][N][N].
+struct SegOut {
+  float2* seg;
+  int len, base;
+};
+
 // Where the adjoint row pass reads entry waves.
 struct PsiLoad {
   int from_seg;             // 0: checkpoint slot i / ck_every, 1: segment buffer
@@ -117,9 +125,10 @@ struct LaunchCtx {
                             // null (float atomics)
   unsigned col_live_blocks; // column blocks a propagation column pass runs (bit q: columns of
                             // block q; 0: all), the union over the launch's requests
+  SegOut seg_out;           // recompute with spectral checkpoints: column-pass output slots
   int ck_spec;              // spectral checkpoints: the forward column passes write the row
-                            // spectrum F_x(psi_i) of every entry wave into checkpoint slot i
-                            // (every slice stored, float2 storage, two-pass kernels)
+                            // spectrum F_x(psi_i) of each stored entry wave into checkpoint
+                            // slot i / ck_every (float2 storage, two-pass kernels)
 };
 
 void launch_items(const LaunchCtx& L, int N);

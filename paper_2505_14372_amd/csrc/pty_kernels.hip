@@ -9,8 +9,9 @@
 //   probe spectrum (unitary):         phat[m*N*N + u_y*N + u_x]
 //   entry-wave checkpoints:           ck[(ck0(b) + m + slot * n_items * M) * N*N + ...]
 //                                     (slot-major: one slice's waves of the group are contiguous);
-//                                     with every slice stored in float they hold the row
-//                                     spectrum F_x(psi_i), written by the column passes
+//                                     stored in float they hold the row spectrum F_x(psi_i),
+//                                     written by the column passes, as do the segment buffers
+//                                     of recomputed slices
 //
 // One slice step is two passes over a tile, each a batched launch:
 //   row pass    : inverse row DFT -> entry wave psi_i (real space, optionally
@@ -252,11 +253,18 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
       for (int a = 0; a < E; ++a) v[a] = Ck<HALF>::load(src + l + L * a);
       flush();
     } else {
-      // the row spectrum comes from the work tile, or (spectral checkpoints)
-      // from checkpoint slot i, where the column pass left it
-      const float2* in = store.mode == 3
-                             ? static_cast<const float2*>(ck_) + (ck_tile(it, r, m, i) * N + y) * N
-                             : trow;
+      // the row spectrum comes from the work tile or, with spectral
+      // checkpoints, from where the column pass left it: checkpoint slot
+      // i / ck_every for a stored slice, segment slot seg_slot for a slice
+      // being recomputed
+      const float2* in = trow;
+      if (store.mode == 3) {
+        if (i % r.ck_every == 0)
+          in = static_cast<const float2*>(ck_) + (ck_tile(it, r, m, i / r.ck_every) * N + y) * N;
+        else if (store.seg)
+          in = static_cast<const float2*>(store.seg) +
+               (((size_t)(it.tile0 + m) * store.seg_len + store.seg_slot) * N + y) * N;
+      }
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = (lmask >> a) & 1u ? in[l + L * a] : make_float2(0.f, 0.f);
       flush();
@@ -506,7 +514,8 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
                                                   float2* __restrict__ ws, const float2* __restrict__ ramps,
                                                   const float2* __restrict__ twg, int step,
                                                   float* __restrict__ pos_part, int item_off,
-                                                  float2* __restrict__ ck_out, unsigned long long colmap) {
+                                                  float2* __restrict__ ck_out, unsigned long long colmap,
+                                                  SegOut seg_out) {
   constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB, T = ColPass<N>::THREADS;
   constexpr bool PROP = OP == COL_PROP || OP == COL_PROP_ADJ;
   static_assert(T >= N, "the staged tables take one entry per thread");
@@ -637,13 +646,18 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
       }
     }
   }
-  // spectral checkpoints: the entry wave's row spectrum goes to checkpoint slot
-  // 0 (COL_SHIFT) or i + 1 (COL_PROP) instead of the work tile
+  // spectral checkpoints: the row spectrum of the entry wave of slice s1 (0
+  // for COL_SHIFT, i + 1 for COL_PROP) goes to checkpoint slot s1 / ck_every
+  // when that slice is stored, to its segment slot while a segment is being
+  // recomputed, else to the work tile
   float2* dst = tile;
   if constexpr (OP == COL_SHIFT || OP == COL_PROP) {
     if (ck_out) {
-      const int slot = OP == COL_SHIFT ? 0 : i + 1;
-      dst = ck_out + ck_tile(it, r, m, slot) * N * N;
+      const int s1 = OP == COL_SHIFT ? 0 : i + 1;
+      if (s1 % r.ck_every == 0)
+        dst = ck_out + ck_tile(it, r, m, s1 / r.ck_every) * N * N;
+      else if (seg_out.seg)
+        dst = seg_out.seg + ((size_t)(it.tile0 + m) * seg_out.len + (s1 - seg_out.base)) * N * N;
     }
   }
   const TileBuf out(dst, N * N * 8);
@@ -1126,10 +1140,10 @@ struct Launch {
     dim3 g(nb, L.n_items, L.max_modes);
     float2* ck_out = L.ck_spec ? static_cast<float2*>(L.ck) : nullptr;
     switch (op) {
-      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map); break;
-      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map); break;
-      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map); break;
-      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map); break;
+      case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map, L.seg_out); break;
+      case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map, L.seg_out); break;
+      case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map, L.seg_out); break;
+      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map, L.seg_out); break;
     }
   }
   static void obj_gather(const LaunchCtx& L, int step, int max_h, int max_w) {
