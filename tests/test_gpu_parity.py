@@ -236,6 +236,25 @@ def test_checkpoint_recompute_matches_store_all(k):
     assert rel_l2(_np(b[1]), ref["g_object"]) < TOL_G
 
 
+@pytest.mark.parametrize("k", [2, 3, 7])
+def test_spectral_recompute_is_bitwise_store_all(k):
+    """With float checkpoints a recomputed segment runs the forward's own row
+    and column passes on the same row spectra, so under the ordered reduction
+    the loss and every gradient equal the store-all result bit for bit."""
+    c = Case(synth.make_small(N=64, M=2, S=7, scan=3, step=4, seed=8, loss="poisson", eps=0.8, amp_noise=0.2))
+    d = c.device()
+    out = []
+    for kk in (1, k):
+        prob = c.problem(checkpoint_every=kk)
+        prob.set_strategy("two_pass")
+        prob.set_reduction("ordered")
+        out.append(prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"]))
+        prob.check()
+    assert out[0][0].item() == out[1][0].item()
+    for name, x, y in zip(("object", "probe", "positions"), out[0][1:], out[1][1:]):
+        assert torch.equal(x, y), name
+
+
 def test_checkpoint_auto_by_budget():
     c = Case(synth.make_small(N=64, M=2, S=8, scan=2, step=4, seed=9, loss="poisson", eps=0.8))
     from paper_2505_14372_amd import api
