@@ -366,9 +366,15 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     sa = e[0] > 0.f ? 1.f / e[0] : 0.f;
     sb = e[1] > 0.f ? 1.f / e[1] : 0.f;
   }
-  float2 o[E];
+  // the object row is held in registers for all modes, except at 24 values
+  // per lane (N = 192), where that would leave one wave per SIMD: there it is
+  // read again per mode (from cache)
+  constexpr bool OREG = E <= 16;
+  float2 o[OREG ? E : 1];
+  if constexpr (OREG) {
 #pragma unroll
-  for (int a = 0; a < E; ++a) o[a] = cscale(r.obj[orow + l + L * a], sb);
+    for (int a = 0; a < E; ++a) o[a] = cscale(r.obj[orow + l + L * a], sb);
+  }
 #pragma unroll
   for (int a = 0; a < E; ++a) acc[a] = make_float2(0.f, 0.f);
   float pw[WSUM ? E : 1];
@@ -407,7 +413,8 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
       else p = Ck<HALF>::load(prow + l + L * a);
       if constexpr (WSUM) pw[a] += cabs2(p);
       acc[a] = cadd(acc[a], cjmul(p, v[a]));
-      v[a] = cjmul(o[a], v[a]);
+      if constexpr (OREG) v[a] = cjmul(o[a], v[a]);
+      else v[a] = cjmul(cscale(r.obj[orow + l + L * a], sb), v[a]);
     }
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
 #pragma unroll
