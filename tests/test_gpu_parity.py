@@ -255,6 +255,41 @@ def test_spectral_recompute_is_bitwise_store_all(k):
         assert torch.equal(x, y), name
 
 
+@pytest.mark.parametrize("k,reduction", [(1, "atomic"), (7, "ordered")])
+def test_many_modes_and_slices_match_oracle(k, reduction):
+    """Beyond the benchmark's 8 modes and 30 slices: 12 modes, 40 slices with
+    unequal gaps, stored or recomputed every 7th slice, against the oracle."""
+    wl = synth.make_small(N=64, M=12, S=40, scan=3, step=4, seed=41, loss="poisson", eps=0.8, amp_noise=0.1,
+                          phi_max=0.05)
+    wl.dz = [float(x) for x in np.random.default_rng(41).uniform(0.5, 3.0, wl.S - 1)]
+    c = Case(wl)
+    ref = c.oracle_grad()
+    d = c.device()
+    prob = c.problem(checkpoint_every=k)
+    prob.set_reduction(reduction)
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    for name, got, want in (("object", gO, ref["g_object"]), ("probe", gP, ref["g_probe"]),
+                            ("positions", gX, ref["g_pos"])):
+        g = _np(got)
+        print(f"{name}: rel L2 {rel_l2(g, want):.2e}, max {max_rel(g, want):.2e}")
+        assert rel_l2(g, want) < TOL_G and max_rel(g, want) < TOL_G, name
+
+
+def test_layer_blur_refused_beyond_its_slice_limit():
+    """The depth blur's Gaussian runs over at most 64 slices; a deeper object
+    is refused when the constraint is set, and the other constraints still are
+    accepted."""
+    from paper_2505_14372_amd._lib import PTY_EINVAL, PtyError
+    wl = synth.make_small(N=64, M=1, S=65, scan=2, step=4, seed=42, phi_max=0.02)
+    prob = Case(wl).problem()
+    with pytest.raises(PtyError) as e:
+        prob.set_regularizers(layer_sigma=0.7)
+    assert e.value.status == PTY_EINVAL
+    prob.set_regularizers(obj_lowpass_sigma=1.0)
+
+
 def test_checkpoint_auto_by_budget():
     c = Case(synth.make_small(N=64, M=2, S=8, scan=2, step=4, seed=9, loss="poisson", eps=0.8))
     from paper_2505_14372_amd import api
