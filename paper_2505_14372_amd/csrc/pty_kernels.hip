@@ -186,7 +186,7 @@ __global__ void k_items(const ReqTable reqs, int n_reqs, Item* __restrict__ item
 // Slice step of the forward model, row part (slice i = step):
 //   psi = IDFT_x(tile row) ; [checkpoint psi] ; phi = psi * O_i ; tile row = DFT_x(phi)
 // With FROM_REAL the entry wave is read from a real-space buffer (the start
-// of a recomputed segment) instead of inverse-transforming the tile. With
+// of a segment recomputed from half-precision checkpoints) instead of inverse-transforming the tile. With
 // EMAX the maxima over the window of sum_m |psi_i,m|^2 and of |O_i|^2 are
 // max-accumulated into r.emax[item][i] (non-negative floats order like their
 // bit patterns, so an unsigned atomic max is exact).
