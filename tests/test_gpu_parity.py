@@ -328,6 +328,36 @@ def test_forward_save_backward_scale_and_accumulate(cache):
     assert e.value.status == PTY_ESTATE
 
 
+def test_gradient_subsets_and_dense_positions():
+    """NULL gradient outputs skip that gradient and leave the others intact;
+    per-position (dense) position gradients add up the entries of a batch that
+    visits a position twice."""
+    c = Case(synth.make_small(N=64, M=2, S=3, scan=3, step=4, seed=43, loss="amplitude", eps=0.3),
+             batch=[4, 0, 4, 7, 2])
+    ref = c.oracle_grad()
+    d = c.device()
+    prob = c.problem()
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"], want=("probe",))
+    prob.check()
+    assert gO is None and gX is None
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    assert rel_l2(_np(gP), ref["g_probe"]) < TOL_G
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"],
+                                          want=("object", "pos"), dense_pos=True)
+    prob.check()
+    assert gP is None and gX.shape == (c.pos.shape[0], 2)
+    assert rel_l2(_np(gO), ref["g_object"]) < TOL_G
+    want = np.zeros((c.pos.shape[0], 2))
+    np.add.at(want, c.batch, ref["g_pos"])
+    assert rel_l2(_np(gX), want) < TOL_G
+    assert np.all(_np(gX)[np.setdiff1d(np.arange(c.pos.shape[0]), c.batch)] == 0)
+    # loss only
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"], want=())
+    prob.check()
+    assert gO is None and gP is None and gX is None
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+
+
 def _oracle_state(c):
     P, O, X = c.o_args()
     return dict(probe=P, object=O, positions=X)
