@@ -5,13 +5,15 @@ probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 512]
                     [--no-cpu-baseline] [--cpu-positions 16]
                     [--workload ms256_m8_s30|ms192_m6_s20|ms128_m4_s8|spoa64|serving]
-                    [--engine adam|sgd|epie|lsqml] [--regularize]
+                    [--engine adam|sgd|epie|lsqml|grad] [--regularize]
                     [--checkpoint-every k] [--checkpoint-half] [--strategy ...] [--chunk n]
                     [--reduction auto|atomic|ordered]
 
 A step is one reconstruct_step over one group of `batch` positions drawn
 from a seeded permutation of the 128 x 128 scan (16384 positions = 32 groups
-per epoch), with every input resident in HBM before the timed region.
+per epoch), with every input resident in HBM before the timed region; with
+--engine grad it is one loss_and_grad call instead (forward model, loss and
+adjoint with all three gradients, no update).
 Prints one JSON line. The headline is the default: Adam, float32
 checkpoints, no regularizers; the other options measure the conventional
 engines, the regularizers and the storage and schedule variants on the
@@ -37,7 +39,8 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
 
-ENGINES = {"adam": "Adam", "sgd": "SGD", "epie": "ePIE", "lsqml": "LSQML"}
+ENGINES = {"adam": "Adam", "sgd": "SGD", "epie": "ePIE", "lsqml": "LSQML",
+           "grad": "forward + adjoint only (loss and gradients, no update)"}
 
 
 def parse():
@@ -60,7 +63,8 @@ def parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     p.add_argument("--engine", default="adam", choices=list(ENGINES),
-                   help="group step: gradient descent with Adam (the headline) or SGD, or the ePIE / LSQML engines")
+                   help="group step: gradient descent with Adam (the headline) or SGD, the ePIE / LSQML "
+                        "engines, or grad: the loss and gradients alone")
     p.add_argument("--regularize", action="store_true",
                    help="enable every cost regularizer and constraint in the step")
     p.add_argument("--requests", type=int, default=16, help="serving stream: number of reconstructions")
@@ -191,6 +195,12 @@ def main():
             counter[0] += 1
             if counter[0] % n_groups == 0:
                 illum.end_iteration()
+    elif args.engine == "grad":
+        g_obj, g_probe = torch.empty_like(obj), torch.empty_like(probe)
+        g_pos = torch.empty((B, 2), dtype=torch.float32, device=dev)
+
+        def step(batch, loss):
+            prob.loss_and_grad(probe, obj, pos, pats, batch, g_object=g_obj, g_probe=g_probe, g_pos=g_pos, loss=loss)
     else:
         opt = {"adam": api.Optimizer(kind="adam", lr_object=1e-3, lr_probe=1e-3, lr_pos=1e-2),
                "sgd": api.Optimizer(kind="sgd", lr_object=1e-8, lr_probe=1e-10, lr_pos=1e-8),

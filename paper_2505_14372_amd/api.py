@@ -219,9 +219,10 @@ class Problem:
         return I, loss
 
     def loss_and_grad(self, probe, obj, positions, patterns, batch_idx, g_object=None, g_probe=None, g_pos=None,
-                      accumulate=False, want=("object", "probe", "pos"), dense_pos=False):
+                      accumulate=False, want=("object", "probe", "pos"), dense_pos=False, loss=None):
         """Group loss and gradients (dL/dRe + i dL/dIm) of object, probe and positions
-        (per batch entry [B][2], or per position [J][2] with dense_pos)."""
+        (per batch entry [B][2], or per position [J][2] with dense_pos); `loss`
+        is an optional float64 device tensor of one element written with the loss."""
         B = self._check_inputs(probe, obj, positions, batch_idx, patterns)
         dev = probe.device
         if "object" in want and g_object is None:
@@ -230,7 +231,8 @@ class Problem:
             g_probe = torch.empty_like(probe)
         if "pos" in want and g_pos is None:
             g_pos = torch.empty((self.J if dense_pos else B, 2), dtype=torch.float32, device=dev)
-        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        if loss is None:
+            loss = torch.zeros(1, dtype=torch.float64, device=dev)
         flags = (_lib.PTY_ACCUMULATE if accumulate else 0) | (_lib.PTY_POS_DENSE if dense_pos else 0)
         st = self.lib.pty_loss_and_grad(self.ctx, _stream(), _ptr(probe), _ptr(obj), _ptr(positions),
                                         _ptr(patterns), _ptr(batch_idx), B, _ptr(loss), _ptr(g_object),
