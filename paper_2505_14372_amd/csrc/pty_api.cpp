@@ -1265,13 +1265,15 @@ extern "C" pty_status pty_set_reduction(pty_ctx* c, int32_t mode) {
 }
 
 extern "C" pty_status pty_set_chunk(pty_ctx* c, int32_t positions) {
-  if (!c || positions < 0) return PTY_EINVAL;
+  if (!c) return PTY_EINVAL;
+  if (positions < 0) { c->err = "chunk must be >= 0 (0: the whole group)"; return PTY_EINVAL; }
   c->chunk = positions;
   return PTY_OK;
 }
 
 extern "C" pty_status pty_set_strategy(pty_ctx* c, int32_t strategy) {
-  if (!c || strategy < PTY_STRATEGY_AUTO || strategy > PTY_STRATEGY_RESIDENT) return PTY_EINVAL;
+  if (!c) return PTY_EINVAL;
+  if (strategy < PTY_STRATEGY_AUTO || strategy > PTY_STRATEGY_RESIDENT) { c->err = "unknown strategy"; return PTY_EINVAL; }
   if (strategy == PTY_STRATEGY_RESIDENT && !resident_supported(c->g.N)) {
     c->err = "the LDS-resident chain needs N = 64 or 128";
     return PTY_EUNSUPPORTED;

@@ -213,7 +213,11 @@ def test_empty_and_oversized_batches_are_rejected():
     assert e.value.status == PTY_EBOUNDS
     # unknown strategy / reduction modes are refused on a live context
     assert prob.lib.pty_set_reduction(prob.ctx, 2) == PTY_EINVAL
+    assert prob.lib.pty_last_error(prob.ctx) == b"unknown reduction mode"
     assert prob.lib.pty_set_strategy(prob.ctx, 9) == PTY_EINVAL
+    assert prob.lib.pty_last_error(prob.ctx) == b"unknown strategy"
+    assert prob.lib.pty_set_chunk(prob.ctx, -1) == PTY_EINVAL
+    assert b"chunk" in prob.lib.pty_last_error(prob.ctx)
 
 
 @pytest.mark.parametrize("k", [2, 3, 7])
