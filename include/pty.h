@@ -116,7 +116,7 @@ typedef struct {
 typedef struct pty_ctx pty_ctx;
 
 /* Create a context for one geometry with workspace for groups of up to
- * max_batch positions. checkpoint_every = 1 stores every slice's entry wave
+ * max_batch positions (at most 65535: PTY_EINVAL beyond). checkpoint_every = 1 stores every slice's entry wave
  * during the forward pass (in float storage as its row spectrum, which the
  * forward pass produces anyway, so storing costs no extra write; the
  * backward pass recovers the wave with an inverse row DFT); k > 1 stores
@@ -378,8 +378,8 @@ typedef struct {
   double* loss;               /* device double or NULL */
 } pty_group_item;
 
-/* max_tiles bounds sum(batch * M) over the items of one call; max_ckpt_tiles
- * bounds sum(batch * M * S). */
+/* max_items bounds sum(batch) over the items of one call (at most 65535),
+ * max_tiles bounds sum(batch * M), max_ckpt_tiles bounds sum(batch * M * S). */
 pty_status pty_group_create(int32_t N, int32_t max_items, int32_t max_tiles, int64_t max_ckpt_tiles,
                             pty_group** out);
 pty_status pty_group_workspace_bytes(int32_t N, int32_t max_items, int32_t max_tiles,

@@ -490,7 +490,7 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
   if (st != PTY_OK) return st;
   const int max_batch = o->max_batch, checkpoint_every = o->checkpoint_every;
   const size_t hbm_budget = o->hbm_budget;
-  if (max_batch < 0 || checkpoint_every < 0) return PTY_EINVAL;
+  if (max_batch < 0 || checkpoint_every < 0 || max_batch > kMaxItems) return PTY_EINVAL;
   const int ck_elem = o->checkpoint_half ? 4 : 8;
   const int S = g->n_slices;
   int k = checkpoint_every;
@@ -1084,7 +1084,7 @@ pty_status pty_group_create(int32_t N, int32_t max_items, int32_t max_tiles, int
   if (!out) return PTY_EINVAL;
   *out = nullptr;
   if (!supported_N(N)) return PTY_EUNSUPPORTED;
-  if (max_items < 1 || max_tiles < 1 || max_ckpt_tiles < 1) return PTY_EINVAL;
+  if (max_items < 1 || max_items > kMaxItems || max_tiles < 1 || max_ckpt_tiles < 1) return PTY_EINVAL;
   pty_group* G = new pty_group();
   G->N = N;
   G->max_items = max_items;

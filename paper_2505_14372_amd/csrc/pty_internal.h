@@ -14,6 +14,7 @@ namespace pty {
 constexpr int kFlagBounds = 1;
 constexpr int kFlagNonFinite = 2;
 constexpr int kMaxReqs = 16;   // reconstructions per shared launch
+constexpr int kMaxItems = 65535;   // positions per launch (one grid dimension holds them)
 
 // One batch entry (probe position) of a launch; filled on the device.
 struct Item {

@@ -196,10 +196,12 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
                                                       float2* __restrict__ ws, void* __restrict__ ck_,
                                                       const float2* __restrict__ twg, int step,
                                                       PsiStore store, int item_off) {
+  // items in reverse order (the column passes run them forward; see Launch::col)
+  const int by = gridDim.y - 1 - blockIdx.y;
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
   __shared__ float2 tw[N];
   __shared__ float2 xch[LINES * Xch<N>::ROW_STRIDE];
-  const Item it = items[item_off + blockIdx.y];
+  const Item it = items[item_off + by];
   const ReqDev& r = reqs.r[it.req];
   const int i = step;
   if (!it.valid || i >= r.S) return;
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
       mo = fmaxf(mo, __shfl_xor(mo, off));
     }
     if ((threadIdx.x & 63) == 0 && r.emax) {
-      unsigned* e = reinterpret_cast<unsigned*>(r.emax + ((size_t)(item_off + blockIdx.y - r.item0) * r.S + i) * 2);
+      unsigned* e = reinterpret_cast<unsigned*>(r.emax + ((size_t)(item_off + by - r.item0) * r.S + i) * 2);
       atomicMax(e, __float_as_uint(mp));
       atomicMax(e + 1, __float_as_uint(mo));
     }
@@ -329,10 +331,12 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
                                                       const float2* __restrict__ twg, int step,
                                                       PsiLoad psi, float scale, int item_off,
                                                       float2* __restrict__ cscr, float* __restrict__ wscr) {
+  // items in reverse order (the column passes run them forward; see Launch::col)
+  const int by = gridDim.y - 1 - blockIdx.y;
   constexpr int L = Pass<N>::L, E = Pass<N>::E, LINES = Pass<N>::LINES;
   __shared__ float2 tw[N];
   __shared__ float2 xch[LINES * Xch<N>::ROW_STRIDE];
-  const Item it = items[item_off + blockIdx.y];
+  const Item it = items[item_off + by];
   const ReqDev& r = reqs.r[it.req];
   const int i = r.S - 1 - step;
   if (!it.valid || i < 0) return;
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   // ePIE: object step divided by max sum_m |psi_i|^2, wave step by max |O_i|^2
   float sa = 1.f, sb = 1.f;
   if (r.emax) {
-    const float* e = r.emax + ((size_t)(item_off + blockIdx.y - r.item0) * r.S + i) * 2;
+    const float* e = r.emax + ((size_t)(item_off + by - r.item0) * r.S + i) * 2;
     sa = e[0] > 0.f ? 1.f / e[0] : 0.f;
     sb = e[1] > 0.f ? 1.f / e[1] : 0.f;
   }
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   if (r.gobj) {
     if (cscr) {
       // ordered reduction: this position's contribution, added in batch order by k_obj_gather
-      float2* dst = cscr + ((size_t)(item_off + blockIdx.y) * N + y) * N;
+      float2* dst = cscr + ((size_t)(item_off + by) * N + y) * N;
 #pragma unroll
       for (int a = 0; a < E; ++a) dst[l + L * a] = cscale(acc[a], scale * sa);
     } else {
@@ -440,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   if constexpr (WSUM) {
     if (r.wsum && wscr) {
       // ordered reduction: stored per position, added in batch order by k_obj_gather
-      float* dst = wscr + ((size_t)(item_off + blockIdx.y) * N + y) * N;
+      float* dst = wscr + ((size_t)(item_off + by) * N + y) * N;
 #pragma unroll
       for (int a = 0; a < E; ++a) dst[l + L * a] = pw[a];
     } else if (r.wsum) {
@@ -533,7 +537,8 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   __shared__ float4 hy[PROP ? N : 1];
   __shared__ float2 xch[CB * ColMap<N>::STRIDE];
   __shared__ float red[2][T / 64];
-  const int b = item_off + blockIdx.y, m = blockIdx.z;
+  // grid (column blocks, modes, items): dispatched item by item, in item order
+  const int b = item_off + blockIdx.z, m = blockIdx.y;
   const Item it = items[b];
   const ReqDev& r = reqs.r[it.req];
   if (!it.valid || m >= r.M) return;
@@ -1144,7 +1149,10 @@ struct Launch {
     for (int q = 0; q < ColPass<N>::NBLK; ++q)
       if (!live || ((live >> q) & 1u)) map |= (unsigned long long)q << (8 * nb++);
     if (nb == 0) return;
-    dim3 g(nb, L.n_items, L.max_modes);
+    // item by item (all modes of an item together), in item order, the
+    // reverse of the row passes around it: each pass starts on the tiles
+    // the previous pass wrote last, which the memory-side cache still holds
+    dim3 g(nb, L.max_modes, L.n_items);
     float2* ck_out = L.ck_spec ? static_cast<float2*>(L.ck) : nullptr;
     switch (op) {
       case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map, L.seg_out); break;

@@ -77,6 +77,10 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     ctx = C.c_void_p()
     assert lib.pty_create(C.byref(g), 8, 1, 0, C.byref(ctx)) == _lib.PTY_EINVAL  # dz missing
     assert lib.pty_create(None, 8, 1, 0, C.byref(ctx)) == _lib.PTY_EINVAL
+    # one grid dimension holds a launch's positions: at most 65535 per group
+    g3 = _lib.Geometry(64, 1, 1, 128, 128, 4, 0.2, 0.02, None, 2 / 3, 2, 0.0, 1.0)
+    assert lib.pty_create(C.byref(g3), 65536, 1, 0, C.byref(ctx)) == _lib.PTY_EINVAL
+    assert lib.pty_group_create(64, 65536, 1, 1, C.byref(ctx)) == _lib.PTY_EINVAL
     assert lib.pty_backward(None, None, 1.0, None, None, None, 0) == _lib.PTY_EINVAL
     assert lib.pty_group_create(100, 1, 1, 1, C.byref(ctx)) == _lib.PTY_EUNSUPPORTED
     assert lib.pty_group_reconstruct_step(None, None, None, 0) == _lib.PTY_EINVAL
