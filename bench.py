@@ -358,6 +358,8 @@ def bench_serving(args):
     print(f"[bench] one-at-a-time done in {t_fifo:.1f}s", file=sys.stderr, flush=True)
     p50, p99 = serving.latency_stats(served)
     f50, f99 = serving.latency_stats(fifo)
+    q50, q99 = serving.request_latency_stats(served, reqs)
+    g50, g99 = serving.request_latency_stats(fifo, reqs)
     diff = 0.0
     for r in reqs:
         a, b = served[r.rid].obj, fifo[r.rid].obj
@@ -371,8 +373,10 @@ def bench_serving(args):
                                f"1-16 slices, 16^2-48^2 scans, {args.iters} Adam iterations each",
                    "reduction": args.reduction},
         "iteration_latency_p50_s": round(p50, 4), "iteration_latency_p99_s": round(p99, 4),
+        "request_latency_p50_s": round(q50, 3), "request_latency_p99_s": round(q99, 3),
         "one_at_a_time": {"value": round(work / t_fifo, 1), "iteration_latency_p50_s": round(f50, 4),
-                          "iteration_latency_p99_s": round(f99, 4), "wall_s": round(t_fifo, 2)},
+                          "iteration_latency_p99_s": round(f99, 4), "request_latency_p50_s": round(g50, 3),
+                          "request_latency_p99_s": round(g99, 3), "wall_s": round(t_fifo, 2)},
         "served_over_one_at_a_time": round(t_fifo / t_served, 3),
         "max_rel_object_diff_served_vs_alone": diff, "rounds": srv.rounds,
     }

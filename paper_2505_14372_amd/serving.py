@@ -345,5 +345,13 @@ def make_request_stream(n: int, seed: int = 0, rate_per_s: float = 2.0, n_iters:
 
 
 def latency_stats(results: Dict[int, Result]):
+    """p50 and p99 of the per-iteration latencies of every request."""
     lat = np.array([x for r in results.values() for x in r.iter_latency_s])
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+
+def request_latency_stats(results: Dict[int, Result], requests: List[ReconRequest]):
+    """p50 and p99 of each request's time from arrival to completion (both on
+    the clock of the run that produced `results`)."""
+    lat = np.array([results[r.rid].finished_at - r.arrival for r in requests])
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
