@@ -3,10 +3,11 @@ gradient iteration (forward model, noise-model loss, exact adjoint to object,
 probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 512]
-                    [--no-cpu-baseline] [--cpu-positions 16]
+                    [--no-cpu-baseline] [--cpu-positions n]
                     [--workload ms256_m8_s30|ms192_m6_s20|ms128_m4_s8|spoa64|serving]
                     [--engine adam|sgd|epie|lsqml|grad] [--regularize]
-                    [--checkpoint-every k] [--checkpoint-half] [--strategy ...] [--chunk n]
+                    [--checkpoint-every k] [--checkpoint-half] [--strategy ...] [--chunk n] [--streams k]
+                    [--profile-steps n]
                     [--reduction auto|atomic|ordered]
 
 A step is one reconstruct_step over one group of `batch` positions drawn
@@ -51,9 +52,14 @@ def parse():
     p.add_argument("--batch", type=int, default=0, help="positions per group (0: the workload's)")
     p.add_argument("--workload", default="ms256_m8_s30")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-positions", type=int, default=16)
+    p.add_argument("--cpu-positions", type=int, default=0,
+                   help="positions in the oracle's CPU sample (0: 8 per host core)")
     p.add_argument("--checkpoint-every", type=int, default=1)
     p.add_argument("--chunk", type=int, default=0)
+    p.add_argument("--streams", type=int, default=1,
+                   help="run the chunks of a chunked schedule concurrently on this many streams")
+    p.add_argument("--profile-steps", type=int, default=4,
+                   help="steps of the separate per-kernel timing pass after the timed region (0: none)")
     p.add_argument("--strategy", default="auto", choices=["auto", "two_pass", "resident"])
     p.add_argument("--reduction", default="auto", choices=["auto", "atomic", "ordered"],
                    help="object-gradient accumulation: float atomics or the bit-reproducible ordered sum; "
@@ -67,7 +73,8 @@ def parse():
                         "engines, or grad: the loss and gradients alone")
     p.add_argument("--regularize", action="store_true",
                    help="enable every cost regularizer and constraint in the step")
-    p.add_argument("--requests", type=int, default=16, help="serving stream: number of reconstructions")
+    p.add_argument("--requests", type=int, default=64, help="serving stream: number of reconstructions")
+    p.add_argument("--max-scan", type=int, default=64, help="serving stream: largest scan side (16..max)")
     p.add_argument("--iters", type=int, default=50, help="serving stream: iterations per reconstruction")
     return p.parse_args()
 
@@ -126,6 +133,29 @@ def kernel_flops_per_launch(name, N, M, B, S, spectral=False):
     return n_fft * lines * per_line
 
 
+def method_flops_per_launch(name, N, M, B):
+    """The method's own FFT flops in one launch (5 n log2 n per 1D line
+    transform): each slice step is a 2D DFT and an inverse 2D DFT per mode,
+    whose row halves run in the row passes and column halves in the column
+    passes. Work a kernel does beyond that (the adjoint row pass recovering
+    the entry wave from its spectral checkpoint, the far-field pass
+    recomputing the far field) is design overhead and not counted."""
+    per_line = 5 * N * np.log2(N)
+    lines = B * M * N
+    n_fft = {"row_fwd": 2, "row_adj": 2, "col_prop": 2, "col_prop_adj": 2, "far_loss": 2,
+             "col_shift": 1, "col_final": 1}.get(name, 0)
+    return n_fft * lines * per_line
+
+
+def method_bytes_per_launch(name, N, B):
+    """The method's own HBM bytes in one launch: the object patch of the slice
+    (read in the forward and again in the adjoint), the object-gradient
+    read-modify-write in the adjoint and the pattern read by the loss; tiles
+    are taken to stay on chip."""
+    T = 8 * N * N
+    return {"row_fwd": B * T, "row_adj": 3 * B * T, "far_loss": B * 4 * N * N}.get(name, 0)
+
+
 # Object-gradient reduction measured faster per workload on one MI355X: the
 # ordered sum pays one extra pass over the group's contributions and wins
 # where atomics contend (a whole dense scan in one group, 128^2) or where the
@@ -175,6 +205,7 @@ def main():
                        max_batch=B, checkpoint_every=args.checkpoint_every, checkpoint_half=args.checkpoint_half,
                        lsqml=args.engine == "lsqml")
     prob.set_chunk(args.chunk)
+    prob.set_streams(args.streams)
     prob.set_strategy(args.strategy)
     prob.set_reduction(args.reduction)
     if args.regularize:
@@ -226,8 +257,6 @@ def main():
     torch.cuda.synchronize()
 
     lib = _lib.load()
-    lib.pty_profile_enable(1)
-    lib.pty_profile_collect(None, 0, None, None, 0)   # drop anything recorded before
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -240,48 +269,88 @@ def main():
             print(f"[bench] timed step {k + 1}/{args.steps} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    lib.pty_profile_enable(0)
-    names = C.create_string_buffer(4096)
-    tot = (C.c_double * 64)()
-    cnt = (C.c_int64 * 64)()
-    n_cls = lib.pty_profile_collect(names, 4096, tot, cnt, 64)
-    prof = {nm: (tot[i], cnt[i]) for i, nm in enumerate(names.value.decode().split("\n")[:n_cls])}
     prob.check()
     step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ms_per_step = t_total * 1000.0 / args.steps
     value = B * args.steps / t_total
     p50, p99 = np.percentile(step_ms, 50), np.percentile(step_ms, 99)
 
-    # dominant kernel class and its roofline
-    # dominant single-kernel class ("recompute" times a whole segment's row
-    # and column passes together, so it has no per-launch byte model)
-    dom = max((k for k in prof if k != "recompute" and prof[k][1] > 0), key=lambda k: prof[k][0])
-    dom_ms, dom_n = prof[dom]
-    avg_s = dom_ms / dom_n / 1000.0
-    spectral = not prob.checkpoint_half and args.strategy != "resident"
-    live = live_fraction(N, wl.bandlimit, S)
-    bytes_launch = kernel_bytes_per_launch(dom, N, M, B, S, prob.checkpoint_half, args.engine, spectral, live,
-                                           args.reduction == "ordered")
-    flops_launch = kernel_flops_per_launch(dom, N, M, B, S, spectral)
-    gbs = bytes_launch / avg_s / 1e9
-    tfl = flops_launch / avg_s / 1e12
-    if gbs / HBM_PEAK_GBS >= tfl / FP32_PEAK_TFLOPS:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    else:
-        roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
-    # the counters were taken on the default configuration only
-    # the committed counter summary covers the default configuration only
-    default_cfg = (args.workload == "ms256_m8_s30" and B == 512 and prob.checkpoint_every == 1 and
-                   not prob.checkpoint_half and args.engine == "adam" and not args.regularize and
-                   args.strategy != "resident" and args.chunk == 0 and args.reduction == "atomic")
-    traffic = measured_traffic(dom) if default_cfg else None
-    roof.update({"kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4),
-                 "traffic": traffic, "algorithmic_bytes": bytes_launch, "algorithmic_flops": flops_launch})
-    kernels = {k: {"total_ms": round(v[0], 3), "launches": int(v[1]), "avg_ms": round(v[0] / v[1], 4),
-                   "share": round(v[0] / sum(x[0] for x in prof.values()), 4)} for k, v in prof.items()}
+    # Per-kernel times come from a separate pass over the same groups with
+    # every launch bracketed by two HIP events on the stream it runs on (the
+    # events are kept out of the timed region above).
+    prof = {}
+    prof_ms_per_step = None
+    n_prof = min(args.profile_steps, args.steps)
+    if n_prof > 0:
+        lib.pty_profile_enable(1)
+        lib.pty_profile_collect(None, 0, None, None, 0)   # drop anything recorded before
+        torch.cuda.synchronize()
+        t_p = time.perf_counter()
+        for k in range(n_prof):
+            step(batches[args.warmup + k], loss)
+        torch.cuda.synchronize()
+        prof_ms_per_step = (time.perf_counter() - t_p) * 1000.0 / n_prof
+        lib.pty_profile_enable(0)
+        names = C.create_string_buffer(4096)
+        tot = (C.c_double * 64)()
+        cnt = (C.c_int64 * 64)()
+        n_cls = lib.pty_profile_collect(names, 4096, tot, cnt, 64)
+        prof = {nm: (tot[i] / n_prof, cnt[i] / n_prof)
+                for i, nm in enumerate(names.value.decode().split("\n")[:n_cls])}
+        prob.check()
+        print(f"[bench] profiled pass: {n_prof} steps, {prof_ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # Roofline of the method's own work (the per-position counts of the
+    # measurement plan): flops = 4 S M 2D FFTs of 5 N^2 log2 N^2 each, bytes =
+    # the pattern plus the object patch read in the forward and again in the
+    # adjoint plus the object-gradient read-modify-write. T_roof = max(bytes /
+    # HBM peak, flops / FP32 peak); the step's fraction is T_roof / T_measured.
     flop_pos = 4 * S * M * 5 * N * N * np.log2(N * N)
+    bytes_pos = N * N * 4 + 4 * S * N * N * 8
+    t_roof_pos = max(bytes_pos / (HBM_PEAK_GBS * 1e9), flop_pos / (FP32_PEAK_TFLOPS * 1e12))
+    t_meas_pos = ms_per_step / 1000.0 / B
+    step_roof = {"bound": "alu" if flop_pos / (FP32_PEAK_TFLOPS * 1e12) >= bytes_pos / (HBM_PEAK_GBS * 1e9) else "hbm",
+                 "flops_per_position": flop_pos, "bytes_per_position": bytes_pos,
+                 "t_roof_us_per_position": round(t_roof_pos * 1e6, 3),
+                 "t_measured_us_per_position": round(t_meas_pos * 1e6, 3),
+                 "frac": round(t_roof_pos / t_meas_pos, 4),
+                 "achieved_tflops": round(flop_pos * value / 1e12, 2),
+                 "achieved_alg_GBps": round(bytes_pos * value / 1e9, 1)}
+    roof = None
+    kernels = {}
+    if prof:
+        # dominant single-kernel class ("recompute" times a whole segment's row
+        # and column passes together, so it has no per-launch model)
+        dom = max((k for k in prof if k != "recompute" and prof[k][1] > 0), key=lambda k: prof[k][0])
+        dom_ms, dom_n = prof[dom]
+        avg_s = dom_ms / dom_n / 1000.0
+        spectral = not prob.checkpoint_half and args.strategy != "resident"
+        live = live_fraction(N, wl.bandlimit, S)
+        n_launch = B if args.chunk <= 0 else min(args.chunk, B)   # positions one launch processes
+        alg_flops = method_flops_per_launch(dom, N, M, n_launch)
+        alg_bytes = method_bytes_per_launch(dom, N, n_launch)
+        design_bytes = kernel_bytes_per_launch(dom, N, M, n_launch, S, prob.checkpoint_half, args.engine, spectral,
+                                               live, args.reduction == "ordered")
+        tfl = alg_flops / avg_s / 1e12
+        gbs = alg_bytes / avg_s / 1e9
+        if alg_flops / (FP32_PEAK_TFLOPS * 1e12) >= alg_bytes / (HBM_PEAK_GBS * 1e9):
+            roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
+        else:
+            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        # the committed counter summary covers the default configuration only
+        default_cfg = (args.workload == "ms256_m8_s30" and B == 512 and prob.checkpoint_every == 1 and
+                       not prob.checkpoint_half and args.engine == "adam" and not args.regularize and
+                       args.strategy != "resident" and args.chunk == 0 and args.reduction == "atomic")
+        traffic = measured_traffic(dom) if default_cfg else None
+        roof.update({"traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4),
+                     "positions_per_launch": n_launch, "algorithmic_flops": alg_flops,
+                     "algorithmic_bytes": alg_bytes, "achieved_alg_GBps": round(gbs, 1),
+                     "design_bytes": design_bytes, "stream_GBps": round(design_bytes / avg_s / 1e9, 1)})
+        kernels = {k: {"ms_per_step": round(v[0], 3), "launches_per_step": round(v[1], 2),
+                       "avg_ms": round(v[0] / v[1], 4), "share": round(v[0] / sum(x[0] for x in prof.values()), 4)}
+                   for k, v in prof.items()}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -295,7 +364,8 @@ def main():
         "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
         "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
         "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),
-        "roofline": roof, "kernels": kernels,
+        "roofline": roof, "step_roofline": step_roof, "kernels": kernels,
+        "profiled_pass_ms_per_step": round(prof_ms_per_step, 3) if prof_ms_per_step else None,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_positions)
@@ -340,7 +410,7 @@ def bench_serving(args):
     from paper_2505_14372_amd import serving
     t0 = time.time()
     reqs = serving.make_request_stream(args.requests, seed=0, rate_per_s=2.0, n_iters=args.iters,
-                                       scans=(16, 48))
+                                       scans=(16, args.max_scan))
     work = sum(r.J * r.n_iters for r in reqs)
     print(f"[bench] {len(reqs)} requests built in {time.time() - t0:.1f}s, "
           f"{work} position-iterations", file=sys.stderr, flush=True)
@@ -370,7 +440,7 @@ def bench_serving(args):
         "warmup": 0, "ms_per_step": round(1000 * t_served / len(reqs), 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"serving: {len(reqs)} Poisson arrivals (2/s), probe 64-256, 1-6 modes, "
-                               f"1-16 slices, 16^2-48^2 scans, {args.iters} Adam iterations each",
+                               f"1-16 slices, 16^2-{args.max_scan}^2 scans, {args.iters} Adam iterations each",
                    "reduction": args.reduction},
         "iteration_latency_p50_s": round(p50, 4), "iteration_latency_p99_s": round(p99, 4),
         "request_latency_p50_s": round(q50, 3), "request_latency_p99_s": round(q99, 3),
@@ -384,22 +454,32 @@ def bench_serving(args):
 
 
 def cpu_baseline(wl, n_pos):
-    """The FP64 oracle on the host: loss and gradients of a small group of the same workload."""
+    """The FP64 oracle on the host: loss and gradients of a small group of the
+    same workload, one oracle call per position on a thread pool over every
+    core this process may run on (numpy's FFTs release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle as orc
     geom = orc.Geometry(N=wl.N, dx=wl.dx, wavelength=wl.wavelength, dz=list(wl.dz), bandlimit=wl.bandlimit,
                         loss=wl.loss, eps=wl.eps, sigma=wl.sigma)
+    cores = len(os.sched_getaffinity(0))
+    if n_pos <= 0:
+        n_pos = 8 * cores
     idx = list(range(0, wl.J, max(1, wl.J // n_pos)))[:n_pos]
+    parts = [idx[k::cores] for k in range(cores) if idx[k::cores]]
     P = wl.probe.astype(np.complex64).astype(np.complex128)
     O = wl.obj.astype(np.complex64).astype(np.complex128)
     X = wl.positions.astype(np.float32).astype(np.float64)
     pats = {j: wl.patterns[j].astype(np.float64) for j in idx}
     patt = _PatternView(pats)
     t0 = time.perf_counter()
-    orc.loss_and_grad(P, O, X, patt, idx, geom)
+    with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        list(ex.map(lambda part: orc.loss_and_grad(P, O, X, patt, part, geom), parts))
     dt = time.perf_counter() - t0
-    return {"value": round(len(idx) / dt, 3), "unit": "positions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(idx)} positions of the same workload (all {wl.M} modes, {wl.S} slices), one "
-                      f"loss_and_grad group, numpy FP64 single-threaded, {dt:.1f} s"}
+    return {"value": round(len(idx) / dt, 3), "unit": "positions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(idx)} positions of the same workload (all {wl.M} modes, {wl.S} slices) split "
+                      f"over {len(parts)} threads, one oracle loss_and_grad call per thread, numpy FP64, "
+                      f"{dt:.1f} s"}
 
 
 class _PatternView:

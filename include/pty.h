@@ -197,6 +197,17 @@ pty_status pty_set_reduction(pty_ctx* ctx, int32_t mode);
  * ordered reduction one chunk size always gives the same bits). */
 pty_status pty_set_chunk(pty_ctx* ctx, int32_t positions);
 
+/* Concurrency of a chunked schedule (pty_set_chunk): with n > 1 the chunks of
+ * pty_loss_and_grad and pty_reconstruct_step run on n internal streams of
+ * the context (chunk q on stream q mod n, forked from and joined back into the
+ * caller's stream, so the call stays stream-ordered for the caller), so that
+ * the launches of several chunks overlap while each chunk's tiles stay in the
+ * last-level cache. Falls back to one stream under the ordered reduction
+ * (its gather writes the gradient without atomics) and with checkpoint
+ * intervals k > 1 (the recompute buffers are shared). n in [1, 8]; creates
+ * the streams on first use (PTY_EHIP if that fails). */
+pty_status pty_set_streams(pty_ctx* ctx, int32_t n);
+
 /* Forward model (Sec. 3) for the positions batch_idx[0..batch) (device int32,
  * values in [0, J)). probe [M][N][N], object [S][H][W], positions [J][2]
  * float32 (row, col). Writes intensities [batch][N][N] (FFT order) if not
@@ -227,6 +238,13 @@ pty_status pty_forward_save(pty_ctx* ctx, void* stream, const pty_c64* probe,
                             double* loss);
 pty_status pty_backward(pty_ctx* ctx, void* stream, double grad_scale, pty_c64* g_object,
                         pty_c64* g_probe, float* g_pos, uint32_t flags);
+/* pty_backward with the scale read on the device: grad_scale points to one
+ * device double (the gradient of the caller's objective with respect to the
+ * loss, e.g. the incoming gradient of an autograd backward), read by the
+ * kernels in stream order, so no value travels to the host and the call never
+ * waits for the device. PTY_EINVAL if grad_scale is NULL. */
+pty_status pty_backward_dev(pty_ctx* ctx, void* stream, const double* grad_scale, pty_c64* g_object,
+                            pty_c64* g_probe, float* g_pos, uint32_t flags);
 
 /* Resident reconstruction state (device pointers). Moments (m_*, v_*) are
  * float32 arrays with the real-component shape of their variable; they are

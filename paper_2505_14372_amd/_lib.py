@@ -29,7 +29,8 @@ EXPORTS = (
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
-    "pty_set_regularizers", "pty_set_strategy", "pty_set_reduction", "pty_lsqml_step",
+    "pty_set_regularizers", "pty_set_strategy", "pty_set_reduction", "pty_lsqml_step", "pty_set_streams",
+    "pty_backward_dev",
 )
 
 
@@ -110,10 +111,12 @@ def load():
         "pty_checkpoint_half": ([vp], i32),
         "pty_checkpoint_every": ([vp], i32),
         "pty_set_chunk": ([vp, i32], i32),
+        "pty_set_streams": ([vp, i32], i32),
         "pty_forward": ([vp, vp, vp, vp, vp, vp, i32, vp, vp, vp], i32),
         "pty_loss_and_grad": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, u32], i32),
         "pty_forward_save": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp], i32),
         "pty_backward": ([vp, vp, f64, vp, vp, vp, u32], i32),
+        "pty_backward_dev": ([vp, vp, vp, vp, vp, vp, u32], i32),
         "pty_reconstruct_step": ([vp, vp, C.POINTER(State), vp, vp, i32, C.POINTER(Optim), vp], i32),
         "pty_check": ([vp, vp], i32),
         "pty_last_error": ([vp], C.c_char_p),

@@ -192,6 +192,13 @@ class Problem:
         if st:
             self._err(st, "pty_set_chunk")
 
+    def set_streams(self, n: int):
+        """Run the chunks of a chunked schedule (set_chunk) concurrently on n
+        internal streams of the context (1: one after the other)."""
+        st = self.lib.pty_set_streams(self.ctx, int(n))
+        if st:
+            self._err(st, "pty_set_streams")
+
     def _err(self, st, what):
         msg = self.lib.pty_last_error(self.ctx).decode() if self.ctx else ""
         raise PtyError(st, f"{what}: {msg}")
@@ -253,9 +260,19 @@ class Problem:
         return loss, I
 
     def backward(self, grad_scale, g_object=None, g_probe=None, g_pos=None, accumulate=False, dense_pos=False):
+        """Adjoint from the tape of forward_save, every gradient scaled by
+        grad_scale: a Python number, or a one-element float64 device tensor
+        that the kernels read on the device (no host synchronisation)."""
         flags = (_lib.PTY_ACCUMULATE if accumulate else 0) | (_lib.PTY_POS_DENSE if dense_pos else 0)
-        st = self.lib.pty_backward(self.ctx, _stream(), float(grad_scale), _ptr(g_object), _ptr(g_probe),
-                                   _ptr(g_pos), flags)
+        if isinstance(grad_scale, torch.Tensor):
+            _need(grad_scale, torch.float64, None, "grad_scale")
+            if grad_scale.numel() != 1:
+                raise ValueError("grad_scale must hold one value")
+            st = self.lib.pty_backward_dev(self.ctx, _stream(), _ptr(grad_scale), _ptr(g_object), _ptr(g_probe),
+                                           _ptr(g_pos), flags)
+        else:
+            st = self.lib.pty_backward(self.ctx, _stream(), float(grad_scale), _ptr(g_object), _ptr(g_probe),
+                                       _ptr(g_pos), flags)
         if st:
             self._err(st, "pty_backward")
 

@@ -40,8 +40,10 @@ class MultisliceLoss(torch.autograd.Function):
         g_o = torch.empty_like(obj) if need_o else None
         g_p = torch.empty_like(probe) if need_p else None
         g_x = torch.empty_like(positions) if need_x else None
-        # the adjoint is linear in the incoming gradient: the library scales every output by it
-        ctx.problem.backward(float(grad_loss), g_o, g_p, g_x, dense_pos=True)
+        # the adjoint is linear in the incoming gradient: the kernels scale every
+        # output by it, reading it on the device (no host synchronisation)
+        scale = grad_loss.detach().reshape(1).to(device=obj.device, dtype=torch.float64).contiguous()
+        ctx.problem.backward(scale, g_o, g_p, g_x, dense_pos=True)
         return g_o, g_p, g_x, None, None, None
 
 

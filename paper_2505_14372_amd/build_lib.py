@@ -4,6 +4,7 @@ Usage: python -m paper_2505_14372_amd.build_lib [--verbose]
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -14,6 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpty.so")
+BUILD_DIR = os.path.join(PKG, "_build")   # object files (git-ignored)
 
 SOURCES = ["pty_kernels.hip", "pty_api.cpp"]
 
@@ -41,9 +43,11 @@ def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB) -> s
     cc = hipcc()
     objs = []
     procs = []
-    tag = str(abs(hash((tuple(defines), out))))
+    # a stable tag per (defines, output), so concurrent builds of variants do not collide
+    tag = hashlib.sha256(repr((tuple(defines), os.path.abspath(out))).encode()).hexdigest()[:16]
+    os.makedirs(BUILD_DIR, exist_ok=True)
     for src in SOURCES:
-        obj = os.path.join(CSRC, f"{src}.{tag}.o")
+        obj = os.path.join(BUILD_DIR, f"{src}.{tag}.o")
         cmd = [cc, *HIP_FLAGS, *[f"-D{d}" for d in defines], "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:

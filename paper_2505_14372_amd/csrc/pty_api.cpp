@@ -23,6 +23,8 @@ constexpr double kPiD = 3.141592653589793238462643383279502884;
 
 bool supported_N(int N) { return N == 64 || N == 128 || N == 192 || N == 256; }
 
+constexpr int kMaxStreams = 8;   // concurrent chunk streams per context
+
 template <typename T>
 pty_status dmalloc(T** p, size_t count, std::string& err) {
   *p = nullptr;
@@ -173,6 +175,11 @@ struct pty_ctx {
   std::vector<double> dz;
   int max_batch = 0, ck_every = 1, n_ck = 1;
   int chunk = 0;              // positions per launch in fused loss-and-gradient calls (0: all)
+  // chunks run concurrently on these streams (created by pty_set_streams, default priority)
+  int n_streams = 1;
+  hipStream_t streams[kMaxStreams] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kMaxStreams] = {};
   int strategy = PTY_STRATEGY_AUTO;
   int reduce = PTY_REDUCE_ATOMIC;
   Sizes sz;
@@ -457,10 +464,29 @@ pty_status check_call(pty_ctx* c, const void* probe, const void* object, const v
 void run_fused(pty_ctx* c, const LaunchCtx& L, float scale) {
   const int N = c->g.N, S = c->g.n_slices;
   run_prepare(L, N);
-  for (auto& ch : split_chunks(L.n_items, c->chunk)) {
-    LaunchCtx C = sub(L, ch.first, ch.second);
+  const auto chunks = split_chunks(L.n_items, c->chunk);
+  // Chunks touch disjoint work tiles, checkpoints and partial sums, so they
+  // may run concurrently, chunk q on stream q mod n, except where two chunks
+  // write the same words without atomics: the ordered object-gradient gather
+  // and the recompute buffers (ws2, seg) shared by every chunk.
+  int ns = 1;
+  if (c->n_streams > 1 && chunks.size() > 1 && !L.cscr && c->ck_every == 1 && !L.resident)
+    ns = std::min<int>(c->n_streams, (int)chunks.size());
+  if (ns > 1) {
+    (void)hipEventRecord(c->ev_fork, L.stream);
+    for (int k = 0; k < ns; ++k) (void)hipStreamWaitEvent(c->streams[k], c->ev_fork, 0);
+  }
+  for (size_t q = 0; q < chunks.size(); ++q) {
+    LaunchCtx C = sub(L, chunks[q].first, chunks[q].second);
+    if (ns > 1) C.stream = c->streams[q % ns];
     run_forward_chunk(C, N, S, {S - 1}, true);
     run_backward_chunk(C, N, S, {S - 1}, scale, c->ck_every, c->ws2, c->seg);
+  }
+  if (ns > 1) {
+    for (int k = 0; k < ns; ++k) {
+      (void)hipEventRecord(c->ev_join[k], c->streams[k]);
+      (void)hipStreamWaitEvent(L.stream, c->ev_join[k], 0);
+    }
   }
   if (L.reqs.r[0].loss_out) run_finish_forward(L, N);
   run_finish_backward(L, N, scale);
@@ -621,6 +647,11 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
   dfree(c->prop_y); dfree(c->prop_x); dfree(c->cscr);
   dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums); dfree(c->lsq_tau); dfree(c->lsq_wscr);
+  for (int k = 0; k < kMaxStreams; ++k) {
+    if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+    if (c->streams[k]) (void)hipStreamDestroy(c->streams[k]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   delete c;
 }
 
@@ -688,8 +719,27 @@ pty_status pty_forward_save(pty_ctx* c, void* stream, const pty_c64* probe, cons
   return PTY_OK;
 }
 
+namespace {
+pty_status backward_impl(pty_ctx* c, void* stream, double grad_scale, const double* scale_dev, pty_c64* g_object,
+                         pty_c64* g_probe, float* g_pos, uint32_t flags);
+}
+
 pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_object, pty_c64* g_probe,
                         float* g_pos, uint32_t flags) {
+  return backward_impl(c, stream, grad_scale, nullptr, g_object, g_probe, g_pos, flags);
+}
+
+pty_status pty_backward_dev(pty_ctx* c, void* stream, const double* grad_scale, pty_c64* g_object,
+                            pty_c64* g_probe, float* g_pos, uint32_t flags) {
+  if (c && !grad_scale) { c->err = "grad_scale is NULL"; return PTY_EINVAL; }
+  return backward_impl(c, stream, 1.0, grad_scale, g_object, g_probe, g_pos, flags);
+}
+
+}  // extern "C"
+
+namespace {
+pty_status backward_impl(pty_ctx* c, void* stream, double grad_scale, const double* scale_dev, pty_c64* g_object,
+                         pty_c64* g_probe, float* g_pos, uint32_t flags) {
   if (!c) return PTY_EINVAL;
   if (!c->tape_valid) { c->err = "pty_backward needs a preceding pty_forward_save"; return PTY_ESTATE; }
   hipStream_t s = (hipStream_t)stream;
@@ -710,6 +760,7 @@ pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_
   r.I_out = nullptr;
   r.loss_out = nullptr;
   r.gphat = g_probe ? c->gphat : nullptr;
+  r.scale_dev = scale_dev;
   if (g_object && !acc) {
     ProfScope p(P_FILL, s);
     launch_fill(s, (float*)g_object, (size_t)S * c->g.obj_h * c->g.obj_w * 2, 0.f);
@@ -723,6 +774,9 @@ pty_status pty_backward(pty_ctx* c, void* stream, double grad_scale, pty_c64* g_
   HIPCHECK(c, hipGetLastError());
   return PTY_OK;
 }
+}  // namespace
+
+extern "C" {
 
 pty_status pty_loss_and_grad(pty_ctx* c, void* stream, const pty_c64* probe, const pty_c64* object,
                              const float* positions, const float* patterns, const int32_t* batch_idx, int32_t B,
@@ -1268,6 +1322,18 @@ extern "C" pty_status pty_set_chunk(pty_ctx* c, int32_t positions) {
   if (!c) return PTY_EINVAL;
   if (positions < 0) { c->err = "chunk must be >= 0 (0: the whole group)"; return PTY_EINVAL; }
   c->chunk = positions;
+  return PTY_OK;
+}
+
+extern "C" pty_status pty_set_streams(pty_ctx* c, int32_t n) {
+  if (!c) return PTY_EINVAL;
+  if (n < 1 || n > kMaxStreams) { c->err = "streams must be in [1, 8]"; return PTY_EINVAL; }
+  if (!c->ev_fork) HIPCHECK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  for (int k = 0; k < n; ++k) {
+    if (!c->streams[k]) HIPCHECK(c, hipStreamCreateWithFlags(&c->streams[k], hipStreamNonBlocking));
+    if (!c->ev_join[k]) HIPCHECK(c, hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
+  }
+  c->n_streams = n;
   return PTY_OK;
 }
 

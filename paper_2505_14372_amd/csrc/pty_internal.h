@@ -59,7 +59,15 @@ struct ReqDev {
   int live_k;               // >= 0: the live columns are exactly |k_x| <= live_k (no table lookup)
   const float4* prop_y;     // [S-1][N] (Hy / N^2, K_y bits, 0): H = [|k_x| <= K_y] Hy Hx, or null
   const float2* prop_x;     // [S-1][N] Hx
+  const double* scale_dev;  // device double multiplying the adjoint's outputs (gradient of the
+                            // caller's objective with respect to the loss), or null (1)
 };
+
+// Scale of the adjoint outputs: the launch's host factor times the request's
+// device factor, read by each workgroup once.
+__device__ __forceinline__ float adj_scale(const ReqDev& r, float scale) {
+  return r.scale_dev ? scale * (float)(*r.scale_dev) : scale;
+}
 
 struct ReqTable {
   ReqDev r[kMaxReqs];

@@ -427,17 +427,18 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   }
   flush();
   if (r.gobj) {
+    const float sc = adj_scale(r, scale) * sa;
     if (cscr) {
       // ordered reduction: this position's contribution, added in batch order by k_obj_gather
       float2* dst = cscr + ((size_t)(item_off + by) * N + y) * N;
 #pragma unroll
-      for (int a = 0; a < E; ++a) dst[l + L * a] = cscale(acc[a], scale * sa);
+      for (int a = 0; a < E; ++a) dst[l + L * a] = cscale(acc[a], sc);
     } else {
       float* g = reinterpret_cast<float*>(r.gobj + orow);
 #pragma unroll
       for (int a = 0; a < E; ++a) {
-        unsafeAtomicAdd(g + 2 * (l + L * a), scale * sa * acc[a].x);
-        unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * sa * acc[a].y);
+        unsafeAtomicAdd(g + 2 * (l + L * a), sc * acc[a].x);
+        unsafeAtomicAdd(g + 2 * (l + L * a) + 1, sc * acc[a].y);
       }
     }
   }
@@ -1015,7 +1016,7 @@ __global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restri
     float2 t = part[0];
 #pragma unroll
     for (int q = 1; q < kProbeSplit; ++q) t = cadd(t, part[q]);
-    r.gphat[(size_t)m * N * N + p] = cscale(t, scale);
+    r.gphat[(size_t)m * N * N + p] = cscale(t, adj_scale(r, scale));
   } else {
     static_assert(SPLIT == kProbeSplit, "the split form takes kProbeSplit interleaved partial sums");
     float2 acc = make_float2(0.f, 0.f);
@@ -1026,7 +1027,7 @@ __global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restri
     if (s == 0) {
       float2 t = red[px];
       for (int q = 1; q < split; ++q) t = cadd(t, red[q * pix + px]);
-      r.gphat[(size_t)m * N * N + p] = cscale(t, scale);
+      r.gphat[(size_t)m * N * N + p] = cscale(t, adj_scale(r, scale));
     }
   }
 }
@@ -1048,7 +1049,7 @@ __global__ void k_pos_reduce(const Item* __restrict__ items, const ReqTable reqs
         g1 += p[1];
       }
   }
-  const float f = 6.283185307179586f * scale;
+  const float f = 6.283185307179586f * adj_scale(r, scale);
   g0 *= f;
   g1 *= f;
   int local = b - r.item0;
@@ -1965,6 +1966,7 @@ __global__ __launch_bounds__(Res<N>::THREADS) void k_res_adj(const Item* __restr
   __syncthreads();
   const int l = threadIdx.x % L;
   float2* wtile = ws + (size_t)(it.tile0 + m) * N * N;
+  const float sc = adj_scale(r, scale);
   for (int i = r.S - 1; i >= 0; --i) {
     for (int y = threadIdx.x / L; y < N; y += LINES) {
       float2 v[E];
@@ -1984,8 +1986,8 @@ __global__ __launch_bounds__(Res<N>::THREADS) void k_res_adj(const Item* __restr
         const float2 o = r.obj[orow + l + L * a];
         if (g) {
           const float2 d = cjmul(p, v[a]);
-          unsafeAtomicAdd(g + 2 * (l + L * a), scale * d.x);
-          unsafeAtomicAdd(g + 2 * (l + L * a) + 1, scale * d.y);
+          unsafeAtomicAdd(g + 2 * (l + L * a), sc * d.x);
+          unsafeAtomicAdd(g + 2 * (l + L * a) + 1, sc * d.y);
         }
         v[a] = cjmul(o, v[a]);
       }

@@ -16,9 +16,16 @@ server runs many jobs (Sec. 2.3), but sharing the GPU instead of queueing:
   launches (pty_group_reconstruct_step: up to 16 reconstructions per launch,
   mixed M, S, object size and loss); groups of different N run on separate
   HIP streams, so their work overlaps on the device;
+* pipelining: the state is resident and every step is stream-ordered, so the
+  next round of a size class is enqueued before the previous one has
+  finished (up to `depth` rounds in flight per size); the host polls only to
+  account for completed rounds, so the device never idles for a host
+  round trip between rounds;
 * accounting: per-iteration latency (one iteration = one pass over all of a
-  request's positions) is recorded for p50/p99, next to positions x
-  iterations per second.
+  request's positions, from the launch of its first round to the observed
+  completion of its last) is recorded for p50/p99, next to positions x
+  iterations per second; iteration losses are summed on the device and read
+  when a request finishes.
 
 `run_fifo` serves the same requests one at a time (single-request
 reconstruct_step, same minibatch order), the baseline the server is compared
@@ -116,30 +123,64 @@ class _Running:
                                     t(req.positions, np.float32), adam=req.opt.kind == "adam")
         self.patterns = t(req.patterns, np.float32)
         n_steps = -(-req.J // req.batch)
-        self.loss_slots = torch.zeros(n_steps, dtype=torch.float64, device=dev)   # one per step of an iteration
-        self.iteration = 0
-        self.batches: List[torch.Tensor] = []
-        self.cursor = 0
-        self.iter_start: Optional[float] = None
-        self.losses: List[float] = []
+        # per-step losses of an iteration and the per-iteration sums, both written
+        # on the device: an iteration's sum is taken on N's stream right after its
+        # last step, so the next iteration's steps (later on that stream) cannot
+        # overwrite the slots before they are summed
+        self.loss_slots = torch.zeros(n_steps, dtype=torch.float64, device=dev)
+        self.iter_losses = torch.zeros(req.n_iters, dtype=torch.float64, device=dev)
+        # every iteration's minibatches copied to the device once, at admission
+        # (no host-to-device copy between rounds)
+        plan = [req.minibatches(it) for it in range(req.n_iters)]
+        flat = torch.from_numpy(np.concatenate([b for bs in plan for b in bs]).astype(np.int32)).to(dev)
+        self.plan: List[List[torch.Tensor]] = []
+        off = 0
+        for bs in plan:
+            row = []
+            for b in bs:
+                row.append(flat[off:off + len(b)])
+                off += len(b)
+            self.plan.append(row)
+        self.launch_iter = 0          # iteration of the next step to launch
+        self.batches: List[torch.Tensor] = self.plan[0]
+        self.cursor = 0               # next minibatch of launch_iter
+        self.iter_start: Dict[int, float] = {}
+        self.iterations_done = 0
         self.latency: List[float] = []
         self.admitted_at = now
-        self._next_iteration(dev)
 
-    def _next_iteration(self, dev):
-        self.batches = [torch.from_numpy(b).to(dev) for b in self.req.minibatches(self.iteration)]
+    def _load_batches(self):
+        self.batches = self.plan[self.launch_iter]
         self.cursor = 0
-        self.iter_start = None
+
+    def has_work(self):
+        return self.launch_iter < self.req.n_iters
+
+    def next_step(self, now):
+        """(iteration, minibatch, loss slot, last step of the iteration) of the next
+        step to launch; advances the launch cursor."""
+        it, k = self.launch_iter, self.cursor
+        if k == 0:
+            self.iter_start[it] = now
+        b = self.batches[k]
+        slot = self.loss_slots[k:k + 1]
+        last = k == len(self.batches) - 1
+        self.cursor += 1
+        if last:
+            self.launch_iter += 1
+            if self.has_work():
+                self._load_batches()
+        return it, b, slot, last
 
     def done(self):
-        return self.iteration >= self.req.n_iters
+        return self.iterations_done >= self.req.n_iters
 
 
 class Server:
     """Admits, batches and runs reconstructions; see the module docstring."""
 
     def __init__(self, hbm_budget: int, group_tiles: Optional[Dict[int, int]] = None, device="cuda",
-                 max_per_launch: int = 16, reduction: str = "atomic"):
+                 max_per_launch: int = 16, reduction: str = "atomic", depth: int = 2):
         self.dev = torch.device(device)
         self.reduction = reduction   # object-gradient accumulation of every reconstruction
         self.budget = int(hbm_budget)
@@ -152,7 +193,8 @@ class Server:
         self.results: Dict[int, Result] = {}
         self.used = 0
         self.rounds = 0
-        self.inflight: Dict[int, tuple] = {}   # N -> (event, requests stepped)
+        self.depth = max(1, int(depth))        # rounds in flight per size class
+        self.inflight: Dict[int, List[tuple]] = {}   # N -> [(event, steps launched)], oldest first
 
     # workspace of the shared launches of one N (allocated on first use, counted in the budget)
     def _group(self, N):
@@ -195,7 +237,8 @@ class Server:
         return admitted
 
     def _launch_round(self, N, runs, now):
-        """One step of every running request of size N, in shared launches on N's stream."""
+        """One step of every running request of size N that has work left, in
+        shared launches on N's stream; returns (event, steps launched)."""
         grp = self.groups[N]
         cap = self.group_tiles[N]
         stream = self.streams[N]
@@ -203,61 +246,62 @@ class Server:
         with torch.cuda.stream(stream):
             launch, tiles, cks = [], 0, 0
             for r in runs:
-                b = r.batches[r.cursor]
-                need_t = b.numel() * r.req.M
+                if not r.has_work():
+                    continue
+                need_t = r.batches[r.cursor].numel() * r.req.M
                 need_c = need_t * r.req.S
                 if launch and (len(launch) == self.max_per_launch or tiles + need_t > cap
                                or cks + need_c > cap * MAX_SLICES):
                     grp.step(launch)
                     launch, tiles, cks = [], 0, 0
-                if r.iter_start is None:
-                    r.iter_start = now
-                launch.append((r.prob, r.state, r.patterns, b, r.req.opt, r.loss_slots[r.cursor:r.cursor + 1]))
+                it, b, slot, last = r.next_step(now)
+                launch.append((r.prob, r.state, r.patterns, b, r.req.opt, slot))
                 tiles += need_t
                 cks += need_c
-                stepped.append(r)
+                stepped.append((r, it, last))
             if launch:
                 grp.step(launch)
+            # iteration losses summed on the device, in stream order after their steps
+            for r, it, last in stepped:
+                if last:
+                    r.iter_losses[it:it + 1].copy_(r.loss_slots.sum().reshape(1))
             ev = torch.cuda.Event()
             ev.record(stream)
         self.rounds += 1
         return ev, stepped
 
     def _complete(self, stepped, now, log):
-        for r in stepped:
-            r.cursor += 1
-            if r.cursor == len(r.batches):
-                r.latency.append(now - r.iter_start)
-                r.losses.append(float(r.loss_slots.sum().item()))
-                r.iteration += 1
-                if r.done():
-                    self._finish(r, now)
-                    if log:
-                        log(f"request {r.req.rid} done at {now:.2f}s")
-                else:
-                    r._next_iteration(self.dev)
+        for r, it, last in stepped:
+            if not last:
+                continue
+            r.latency.append(now - r.iter_start.pop(it))
+            r.iterations_done += 1
+            if r.done():
+                self._finish(r, now)
+                if log:
+                    log(f"request {r.req.rid} done at {now:.2f}s")
 
     def run(self, clock=time.perf_counter, log=None) -> Dict[int, Result]:
         """Serve until every submitted request has finished. Each probe size
-        advances on its own stream: a new round of size N is launched as soon
-        as N's previous round has completed, independently of other sizes."""
+        advances on its own stream with up to `depth` rounds in flight: a round
+        is enqueued as soon as fewer are in flight (the steps are stream-ordered
+        on device-resident state), and completed rounds are accounted for in
+        launch order."""
         t0 = clock()
-        while self.pending or self.running or self.inflight:
+        while self.pending or self.running or any(self.inflight.values()):
             now = clock() - t0
             self._admit(now)
             busy = False
             for N in sorted({r.req.N for r in self.running} | set(self.inflight)):
-                if N in self.inflight:
-                    ev, stepped = self.inflight[N]
-                    if not ev.query():
-                        busy = True
-                        continue
-                    del self.inflight[N]
+                q = self.inflight.setdefault(N, [])
+                while q and q[0][0].query():
+                    _, stepped = q.pop(0)
                     self._complete(stepped, clock() - t0, log)
-                runs = [r for r in self.running if r.req.N == N]
-                if runs:
-                    self.inflight[N] = self._launch_round(N, runs, clock() - t0)
-                    busy = True
+                runs = [r for r in self.running if r.req.N == N and r.has_work()]
+                while runs and len(q) < self.depth:
+                    q.append(self._launch_round(N, runs, clock() - t0))
+                    runs = [r for r in runs if r.has_work()]
+                busy = busy or bool(q)
             if not busy:
                 if self.pending and not self.running:
                     wait = self.pending[0].arrival - (clock() - t0)
@@ -269,9 +313,10 @@ class Server:
 
     def _finish(self, r: _Running, now):
         st = r.state
+        # every round of this request has completed (its last one was just observed)
         self.results[r.req.rid] = Result(
             rid=r.req.rid, probe=st.probe.cpu().numpy(), obj=st.object.cpu().numpy(),
-            positions=st.positions.cpu().numpy(), losses=r.losses, iter_latency_s=r.latency,
+            positions=st.positions.cpu().numpy(), losses=r.iter_losses.cpu().tolist(), iter_latency_s=r.latency,
             admitted_at=r.admitted_at, finished_at=now)
         self.running.remove(r)
         self.used -= r.req.resident_bytes()
@@ -299,14 +344,18 @@ def run_fifo(requests: List[ReconRequest], device="cuda", clock=time.perf_counte
         st = api.ReconState(t(req.probe, np.complex64), t(req.obj, np.complex64), t(req.positions, np.float32),
                             adam=req.opt.kind == "adam")
         pats = t(req.patterns, np.float32)
-        slots = torch.zeros(-(-req.J // req.batch), dtype=torch.float64, device=dev)
-        losses, lat = [], []
+        n_steps = -(-req.J // req.batch)
+        slots = torch.zeros((req.n_iters, n_steps), dtype=torch.float64, device=dev)
+        # iterations are enqueued back to back (nothing waits for the host);
+        # their latencies come from device events at their boundaries
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(req.n_iters + 1)]
+        evs[0].record()
         for it in range(req.n_iters):
-            ts = clock()
             for k, b in enumerate(req.minibatches(it)):
-                prob.reconstruct_step(st, pats, torch.from_numpy(b).to(dev), req.opt, slots[k:k + 1])
-            losses.append(float(slots.sum().item()))
-            lat.append(clock() - ts)
+                prob.reconstruct_step(st, pats, torch.from_numpy(b).to(dev), req.opt, slots[it, k:k + 1])
+            evs[it + 1].record()
+        losses = slots.sum(dim=1).cpu().tolist()   # waits for the request's last step
+        lat = [evs[i].elapsed_time(evs[i + 1]) / 1000.0 for i in range(req.n_iters)]
         results[req.rid] = Result(rid=req.rid, probe=st.probe.cpu().numpy(), obj=st.object.cpu().numpy(),
                                   positions=st.positions.cpu().numpy(), losses=losses, iter_latency_s=lat,
                                   admitted_at=admitted, finished_at=clock() - t0)

@@ -150,3 +150,33 @@ def test_torch_optimizer_step_decreases_loss(ms192):
         opt.step()
         losses.append(loss.item())
     assert losses[-1] < losses[0]
+
+
+def test_autograd_backward_does_not_synchronise():
+    """The backward reads the incoming gradient on the device: under torch's
+    synchronisation debug mode ("error": any device-to-host copy or stream
+    synchronisation raises) the whole backward runs, and the gradients equal
+    the scalar entry point's with the same scale."""
+    from paper_2505_14372_amd.autograd import multislice_loss
+    c = Case(synth.make_small(N=64, M=2, S=3, scan=3, step=4, seed=31, loss="poisson", eps=0.8))
+    d = c.device()
+    prob = c.problem()
+    prob.set_reduction("ordered")
+    obj = d["obj"].clone().requires_grad_(True)
+    probe = d["probe"].clone().requires_grad_(True)
+    pos = d["pos"].clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    loss = multislice_loss(obj, probe, pos, prob, d["pats"], d["batch"])
+    torch.cuda.set_sync_debug_mode("error")
+    try:
+        (3.0 * loss).backward()
+    finally:
+        torch.cuda.set_sync_debug_mode("default")
+    # the same tape through the host-scalar entry point
+    prob.forward_save(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    gO, gP, gX = torch.empty_like(obj), torch.empty_like(probe), torch.empty_like(pos)
+    prob.backward(3.0, gO, gP, gX, dense_pos=True)
+    prob.check()
+    assert torch.equal(obj.grad, gO) and torch.equal(probe.grad, gP) and torch.equal(pos.grad, gX)
+    ref = c.oracle_grad()
+    assert rel_l2(gO.cpu().numpy(), 3 * ref["g_object"]) < 1e-3

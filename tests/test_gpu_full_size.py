@@ -1,16 +1,20 @@
 """Parity at the full size of the headline workload (probe 256 x 256, 8 modes,
 30 slices of 1 A, object 1280 x 1280 x 30, a group of 512 positions), in the
 launch configuration the benchmark times. The oracle computes sampled
-positions one by one; whole-group quantities are checked through properties
-that hold at any size (additivity over sub-groups, the loss of the returned
-intensities)."""
+positions one by one, and the whole group's object gradient on a region of
+the object from exactly the positions whose windows cover it; whole-group
+quantities are also checked through properties that hold at any size
+(additivity over sub-groups, the loss of the returned intensities)."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
 import oracle as orc
 from paper_2505_14372_amd import synth
 
-from _cases import Case, rel_l2
+from _cases import Case, max_rel, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -118,3 +122,62 @@ def test_full_size_ordered_reduction_is_bitwise_repeatable(full):
     print(rel_l2(_np(gO1), _np(gO_at)), rel_l2(_np(gP1), _np(gP_at)), flush=True)
     assert rel_l2(_np(gO1), _np(gO_at)) < 1e-5
     assert rel_l2(_np(gP1), _np(gP_at)) < 1e-5
+
+
+class _Patterns:
+    """Patterns of a few positions in float64, indexed like the full stack."""
+
+    def __init__(self, pats, idx):
+        self.d = {int(j): pats[int(j)].astype(np.float64) for j in idx}
+
+    def __getitem__(self, j):
+        return self.d[int(j)]
+
+
+REGION = 16
+
+
+@pytest.fixture(scope="module")
+def region_ref(full):
+    """Oracle object gradient of the whole group on a REGION x REGION pixel
+    column through all slices in the middle of the object, summed over exactly
+    the group's positions whose windows cover it (every other position adds
+    nothing there), on a thread pool over the host cores."""
+    c = full
+    R = REGION
+    y0, x0 = c.H // 2 - R // 2, c.W // 2 - R // 2
+    n = np.floor(c.pos[c.batch].astype(np.float64) + 0.5).astype(np.int64)
+    cover = [int(c.batch[b]) for b in range(B)
+             if n[b, 0] < y0 + R and n[b, 0] + c.N > y0 and n[b, 1] < x0 + R and n[b, 1] + c.N > x0]
+    print(f"region {R}x{R} at ({y0}, {x0}): {len(cover)} covering positions", flush=True)
+    assert 10 <= len(cover) < B
+    P, O, X = c.o_args()
+    pats = _Patterns(c.pats, cover)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    parts = [cover[k::workers] for k in range(workers) if cover[k::workers]]
+
+    def run(part):
+        return orc.loss_and_grad(P, O, X, pats, part, c.geom)["g_object"][:, y0:y0 + R, x0:x0 + R].copy()
+
+    with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        ref = sum(ex.map(run, parts))
+    return (y0, x0), ref
+
+
+@pytest.mark.parametrize("reduction", ["atomic", "ordered"])
+def test_full_size_object_gradient_region(full, region_ref, reduction):
+    """The 512-position group's object gradient, element by element against the
+    oracle on a region of the object, under both reductions."""
+    c = full
+    (y0, x0), ref = region_ref
+    R = REGION
+    d = c.device()
+    prob = c.problem(max_batch=B)
+    prob.set_reduction(reduction)
+    print(f"full-size object-gradient region, {reduction} reduction", flush=True)
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    got = _np(gO[:, y0:y0 + R, x0:x0 + R]).astype(np.complex128)
+    e2, einf = rel_l2(got, ref), max_rel(got, ref)
+    print(f"{reduction}: rel L2 {e2:.2e}, max {einf:.2e}", flush=True)
+    assert e2 < 1e-3 and einf < 1e-3

@@ -417,6 +417,107 @@ def test_reconstruct_step_adam():
         assert rel_l2(du_g, du_o) < 2e-2, (key, rel_l2(du_g, du_o))
 
 
+def test_adam_update_matches_oracle_on_the_gpu_gradient():
+    """The optimiser alone, to tight bounds: at each of three Adam steps the
+    gradient the GPU computes at its current state (ordered reduction, so the
+    step's own gradient has the same bits) is fed with the GPU's moments to the
+    oracle's Adam in FP64; the GPU state and moments after reconstruct_step must
+    agree element by element to 1e-5 of each component's update (plus one
+    float32 rounding of the state) and the moments to 1e-6."""
+    from paper_2505_14372_amd import api
+    c = Case(synth.make_small(N=64, M=2, S=3, scan=3, step=4, seed=11, loss="poisson", eps=0.8, amp_noise=0.1))
+    d = c.device()
+    prob = c.problem()
+    prob.set_reduction("ordered")
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=True)
+    lr = dict(object=2e-2, probe=1e-3, positions=1e-2)
+    opt = api.Optimizer(kind="adam", lr_object=lr["object"], lr_probe=lr["probe"], lr_pos=lr["positions"])
+    batches = [[0, 4, 8], [1, 2, 3, 5], [6, 7, 0]]
+    f64 = lambda t: _np(t).astype(np.complex128 if t.is_complex() else np.float64)  # noqa: E731
+    for k, b in enumerate(batches):
+        bt = torch.tensor(b, dtype=torch.int32, device="cuda")
+        _, gO, gP, gX = prob.loss_and_grad(st.probe, st.object, st.positions, d["pats"], bt, dense_pos=True)
+        before = {key: (f64(getattr(st, key)), _np(getattr(st, "m_" + mk)).astype(np.float64),
+                        _np(getattr(st, "v_" + mk)).astype(np.float64))
+                  for key, mk in (("object", "object"), ("probe", "probe"), ("positions", "pos"))}
+        grads = dict(object=f64(gO), probe=f64(gP), positions=f64(gX))
+        prob.reconstruct_step(st, d["pats"], bt, opt)
+        prob.check()
+        assert st.step == k + 1
+        for key, mk in (("object", "object"), ("probe", "probe"), ("positions", "pos")):
+            th0, m0, v0 = before[key]
+            th_o, m_o, v_o = orc.adam_update(th0, grads[key], m0, v0, k + 1, lr[key])
+            th_g = f64(getattr(st, key))
+            m_g = _np(getattr(st, "m_" + mk)).astype(np.float64)
+            v_g = _np(getattr(st, "v_" + mk)).astype(np.float64)
+            # compare per real component; the oracle's state rounded to float32 as the GPU stores it
+            th_o32 = orc._as_real(th_o).astype(np.float32)
+            got, want, init = orc._as_real(th_g), th_o32.astype(np.float64), orc._as_real(th0)
+            ulp = np.spacing(np.abs(th_o32)).astype(np.float64)
+            du = np.abs(orc._as_real(th_o) - init)
+            bad = np.abs(got - want) > 1e-5 * du + ulp
+            assert not bad.any(), (k, key, int(bad.sum()), float(np.max(np.abs(got - want))))
+            assert np.all(np.abs(m_g - m_o) <= 1e-6 * np.abs(m_o) + 1e-30), (k, key, "m")
+            assert np.all(np.abs(v_g - v_o) <= 1e-6 * np.abs(v_o) + 1e-37), (k, key, "v")
+            moved = float(np.max(du))
+            print(f"step {k + 1} {key}: max update {moved:.3e}, max diff {float(np.max(np.abs(got - want))):.3e}")
+            assert moved > 0.5 * lr[key]
+
+
+@pytest.mark.parametrize("N", [192, 256])
+@pytest.mark.parametrize("kind", ["adam", "sgd"])
+def test_group_step_large_windows(N, kind):
+    """Grouped steps at N = 192 and 256 (the 24-values-per-lane adjoint row pass
+    that re-reads the object row, and the 16 x 16 line split): two
+    reconstructions with different modes, slices, object sizes and losses in
+    shared launches give, under the ordered reduction, the bits of their single
+    steps; an SGD step also matches the oracle's step."""
+    from paper_2505_14372_amd import api
+    step_px = 11 if N == 192 else 8
+    cases = [Case(synth.make_small(N=N, M=2, S=3, scan=2, step=step_px, seed=90 + N, loss="poisson", eps=0.8,
+                                   phi_max=0.1, dose=1e5)),
+             Case(synth.make_small(N=N, M=1, S=2, scan=3, step=step_px - 3, seed=91 + N, loss="amplitude",
+                                   eps=0.3, phi_max=0.1, dose=1e5))]
+    batches = [[0, 3, 1], [4, 0, 8, 2, 6]]
+    if kind == "adam":
+        opt = api.Optimizer(kind="adam", lr_object=1e-2, lr_probe=1e-3, lr_pos=1e-2)
+    else:
+        opt = api.Optimizer(kind="sgd", lr_object=1e-4, lr_probe=1e-6, lr_pos=1e-5)
+    runs = []
+    for q, c in enumerate(cases):
+        d = c.device()
+        ps, pg = c.problem(max_batch=16), c.problem(max_batch=16)
+        ps.set_reduction("ordered")
+        pg.set_reduction("ordered")
+        single = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=kind == "adam")
+        grouped = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=kind == "adam")
+        runs.append((c, ps, pg, d, single, grouped, torch.tensor(batches[q], dtype=torch.int32, device="cuda")))
+    print(f"grouped N={N} {kind}: " + ", ".join(f"M={c.M} S={c.S} H={c.H} B={len(b)}" for c, *_, b in runs),
+          flush=True)
+    grp = api.Group(N, max_items=16, max_tiles=32, max_ckpt_tiles=64)
+    n_steps = 2 if kind == "adam" else 1
+    for _ in range(n_steps):
+        entries = []
+        for c, ps, pg, d, single, grouped, b in runs:
+            ps.reconstruct_step(single, d["pats"], b, opt)
+            entries.append((pg, grouped, d["pats"], b, opt, torch.zeros(1, dtype=torch.float64, device="cuda")))
+        grp.step(entries)
+    torch.cuda.synchronize()
+    for c, ps, pg, d, single, grouped, b in runs:
+        assert torch.equal(grouped.object, single.object)
+        assert torch.equal(grouped.probe, single.probe)
+        assert torch.equal(grouped.positions, single.positions)
+        if kind == "sgd":
+            P0, O0, X0 = c.o_args()
+            ost, _ = orc.reconstruct_step(dict(probe=P0, object=O0, positions=X0), c.pats.astype(np.float64),
+                                          list(_np(b)), c.geom, dict(kind="sgd", lr_object=opt.lr_object,
+                                                                      lr_probe=opt.lr_probe, lr_pos=opt.lr_pos))
+            for got, init, want in ((grouped.object, O0, ost["object"]), (grouped.probe, P0, ost["probe"]),
+                                    (grouped.positions, X0, ost["positions"])):
+                du_g = _np(got).astype(np.complex128 if np.iscomplexobj(init) else np.float64) - init
+                assert rel_l2(du_g, want - init) < TOL_G, rel_l2(du_g, want - init)
+
+
 def test_bounds_flag_skips_the_window():
     c = Case(synth.make_small(N=64, M=1, S=2, scan=2, step=4, seed=12, loss="gaussian"))
     c.pos[1] = [c.H - 40.0, 3.0]      # window leaves the object

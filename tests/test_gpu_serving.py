@@ -76,3 +76,23 @@ def test_request_over_budget_is_refused():
     srv.submit(reqs[0])
     with pytest.raises(MemoryError):
         srv.run()
+
+
+def test_served_large_windows_give_the_alone_bits():
+    """Shared launches at N = 192 and 256 with mixed modes and slices: under the
+    ordered reduction every served reconstruction has the bits of its run alone."""
+    from paper_2505_14372_amd import serving
+    reqs = serving.make_request_stream(4, seed=7, rate_per_s=50.0, n_iters=2, sizes=(192, 256), max_modes=3,
+                                       max_slices=4, scans=(2, 3), steps=(4, 8), batch=8)
+    print([(r.rid, r.N, r.M, r.S, r.J) for r in reqs], flush=True)
+    assert {r.N for r in reqs} == {192, 256}
+    srv = serving.Server(hbm_budget=64 << 30, reduction="ordered")
+    for r in reqs:
+        srv.submit(r)
+    mixed = srv.run()
+    alone = serving.run_fifo(reqs, reduction="ordered")
+    for r in reqs:
+        a, b = mixed[r.rid], alone[r.rid]
+        assert np.allclose(a.losses, b.losses, rtol=1e-12, atol=0)
+        for x, y in ((a.obj, b.obj), (a.probe, b.probe), (a.positions, b.positions)):
+            assert np.array_equal(x, y)
