@@ -453,6 +453,9 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+CPU_SHARE = 16
+
+
 def cpu_baseline(wl, n_pos):
     """The FP64 oracle on the host: loss and gradients of a small group of the
     same workload, one oracle call per position on a thread pool over every
@@ -462,7 +465,9 @@ def cpu_baseline(wl, n_pos):
     import oracle as orc
     geom = orc.Geometry(N=wl.N, dx=wl.dx, wavelength=wl.wavelength, dz=list(wl.dz), bandlimit=wl.bandlimit,
                         loss=wl.loss, eps=wl.eps, sigma=wl.sigma)
-    cores = len(os.sched_getaffinity(0))
+    # every core this process may run on, capped at the host share one GPU's
+    # job is given (16 cores), whatever the affinity mask lists
+    cores = min(len(os.sched_getaffinity(0)), CPU_SHARE)
     if n_pos <= 0:
         n_pos = 8 * cores
     idx = list(range(0, wl.J, max(1, wl.J // n_pos)))[:n_pos]

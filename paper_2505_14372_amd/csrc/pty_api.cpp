@@ -829,8 +829,8 @@ void opt_update(hipStream_t s, const pty_optim* o, int64_t t, float* th, const f
   } else {
     const double bc1 = 1.0 - std::pow(o->beta1, (double)t);
     const double bc2 = 1.0 - std::pow(o->beta2, (double)t);
-    launch_adam(s, th, g, m, v, n, (float)(lr / bc1), (float)(1.0 / std::sqrt(bc2)), (float)o->beta1,
-                (float)o->beta2, (float)o->eps);
+    launch_adam(s, th, g, m, v, n, (float)(lr / bc1), (float)(1.0 / std::sqrt(bc2)), o->beta1, o->beta2,
+                (float)o->eps);
   }
 }
 

@@ -154,7 +154,7 @@ void launch_plain2d(int N, hipStream_t s, const float2* tw, const float2* src, f
 void launch_fill(hipStream_t s, float* p, size_t n, float v);
 void launch_sgd(hipStream_t s, float* th, const float* g, size_t n, float lr);
 void launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, size_t n, float step_size,
-                 float inv_sqrt_bc2, float b1, float b2, float eps);
+                 float inv_sqrt_bc2, double b1, double b2, float eps);
 int col_blocks(int N);
 
 enum ColOp { COL_SHIFT = 0, COL_PROP = 1, COL_PROP_ADJ = 2, COL_FINAL = 3 };

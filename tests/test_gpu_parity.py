@@ -88,6 +88,14 @@ def _get(cache, name):
     return cache[name]
 
 
+def _real_components(a):
+    """Real components of an array (complex entries split into (re, im) pairs)."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        return np.stack([a.real, a.imag], axis=-1)
+    return a.astype(np.float64)
+
+
 def _np(t):
     return t.detach().cpu().numpy()
 
@@ -421,9 +429,10 @@ def test_adam_update_matches_oracle_on_the_gpu_gradient():
     """The optimiser alone, to tight bounds: at each of three Adam steps the
     gradient the GPU computes at its current state (ordered reduction, so the
     step's own gradient has the same bits) is fed with the GPU's moments to the
-    oracle's Adam in FP64; the GPU state and moments after reconstruct_step must
-    agree element by element to 1e-5 of each component's update (plus one
-    float32 rounding of the state) and the moments to 1e-6."""
+    oracle's Adam in FP64; the GPU state after reconstruct_step must agree
+    element by element to 1e-5 of each component's update (plus one float32
+    rounding of the state) and the moments to the float rounding bound of
+    their update."""
     from paper_2505_14372_amd import api
     c = Case(synth.make_small(N=64, M=2, S=3, scan=3, step=4, seed=11, loss="poisson", eps=0.8, amp_noise=0.1))
     d = c.device()
@@ -451,14 +460,22 @@ def test_adam_update_matches_oracle_on_the_gpu_gradient():
             m_g = _np(getattr(st, "m_" + mk)).astype(np.float64)
             v_g = _np(getattr(st, "v_" + mk)).astype(np.float64)
             # compare per real component; the oracle's state rounded to float32 as the GPU stores it
-            th_o32 = orc._as_real(th_o).astype(np.float32)
-            got, want, init = orc._as_real(th_g), th_o32.astype(np.float64), orc._as_real(th0)
+            th_o32 = _real_components(th_o).astype(np.float32)
+            got, want, init = _real_components(th_g), th_o32.astype(np.float64), _real_components(th0)
             ulp = np.spacing(np.abs(th_o32)).astype(np.float64)
-            du = np.abs(orc._as_real(th_o) - init)
+            du = np.abs(_real_components(th_o) - init)
             bad = np.abs(got - want) > 1e-5 * du + ulp
             assert not bad.any(), (k, key, int(bad.sum()), float(np.max(np.abs(got - want))))
-            assert np.all(np.abs(m_g - m_o) <= 1e-6 * np.abs(m_o) + 1e-30), (k, key, "m")
-            assert np.all(np.abs(v_g - v_o) <= 1e-6 * np.abs(v_o) + 1e-37), (k, key, "v")
+            # the moments to the rounding of their float update: every operation of
+            # b m + (1 - b) g (and of the constants) errs by at most the unit
+            # roundoff u = 2^-24 of the magnitudes it adds, so |error| <= 4 u
+            # (|b1 m0| + |c1 g|) however much the two terms cancel
+            u = 2.0 ** -24
+            g_re = _real_components(grads[key])
+            m_tol = 4 * u * (0.9 * np.abs(m0) + 0.1 * np.abs(g_re)) + 1e-30
+            v_tol = 4 * u * (0.999 * np.abs(v0) + 0.001 * g_re * g_re) + 1e-37
+            assert np.all(np.abs(m_g - m_o) <= m_tol), (k, key, "m", float(np.max(np.abs(m_g - m_o) / m_tol)))
+            assert np.all(np.abs(v_g - v_o) <= v_tol), (k, key, "v", float(np.max(np.abs(v_g - v_o) / v_tol)))
             moved = float(np.max(du))
             print(f"step {k + 1} {key}: max update {moved:.3e}, max diff {float(np.max(np.abs(got - want))):.3e}")
             assert moved > 0.5 * lr[key]
@@ -515,7 +532,13 @@ def test_group_step_large_windows(N, kind):
             for got, init, want in ((grouped.object, O0, ost["object"]), (grouped.probe, P0, ost["probe"]),
                                     (grouped.positions, X0, ost["positions"])):
                 du_g = _np(got).astype(np.complex128 if np.iscomplexobj(init) else np.float64) - init
-                assert rel_l2(du_g, want - init) < TOL_G, rel_l2(du_g, want - init)
+                # the state is stored in float32, so each component of the update is
+                # resolved to one float32 spacing of the new value: the bar is the
+                # gradient tolerance on the update plus that resolution
+                res = np.linalg.norm(np.spacing(_real_components(want).astype(np.float32)).astype(np.float64))
+                err = np.linalg.norm(_real_components(du_g) - _real_components(want - init))
+                assert err <= TOL_G * np.linalg.norm(_real_components(want - init)) + res, \
+                    (rel_l2(du_g, want - init), err, res)
 
 
 def test_bounds_flag_skips_the_window():
