@@ -217,6 +217,31 @@ pty_status pty_forward(pty_ctx* ctx, void* stream, const pty_c64* probe, const p
                        const float* positions, const int32_t* batch_idx, int32_t batch,
                        const float* patterns, float* intensities, double* loss);
 
+/* Bytes of the static device array that backs pty_forward_static (one copy
+ * per GPU the library runs on, held until the process ends). */
+#define PTY_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* pty_forward for callers that cannot allocate device memory at call time
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results and errors, but every per-call
+ * buffer -- the probe spectrum, the item descriptors and shift ramps, the
+ * work tiles and the loss partial sums -- is carved from one static device
+ * array of PTY_STATIC_SCRATCH_BYTES per GPU instead of the context's
+ * workspace, so the context may be created with max_batch = 0 (tables only).
+ * The call takes, each piece rounded up to 256 bytes: the probe spectrum (M
+ * N^2 complex64) and, per position, a 40-byte descriptor, two shift ramps of
+ * N complex64, N / 32 float loss partials and M work tiles of N^2 complex64
+ * (about 8 batch M N^2 bytes in all); PTY_EINVAL (with the bytes needed in
+ * pty_last_error) if that exceeds the array, or for batch < 1. Nothing in
+ * the array needs to start at zero: every piece is written before it is read
+ * in the same call. Every call on a GPU shares that GPU's array and leaves
+ * its contents behind: calls that overlap on one GPU (other streams, threads
+ * or contexts) race and must be serialised by the caller. Calls no
+ * allocation routine. */
+pty_status pty_forward_static(pty_ctx* ctx, void* stream, const pty_c64* probe, const pty_c64* object,
+                              const float* positions, const int32_t* batch_idx, int32_t batch,
+                              const float* patterns, float* intensities, double* loss);
+
 /* Loss of the group and its gradients (Sec. 3.1-3.2): g_object [S][H][W],
  * g_probe [M][N][N], g_pos [batch][2] (per batch entry, dL/dX; with
  * PTY_POS_DENSE [J][2] per position). loss may be NULL.

@@ -30,8 +30,10 @@ EXPORTS = (
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
     "pty_set_regularizers", "pty_set_strategy", "pty_set_reduction", "pty_lsqml_step", "pty_set_streams",
-    "pty_backward_dev",
+    "pty_backward_dev", "pty_forward_static",
 )
+# bytes of the static device array behind pty_forward_static (PTY_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 32 << 20
 
 
 class Geometry(C.Structure):
@@ -113,6 +115,7 @@ def load():
         "pty_set_chunk": ([vp, i32], i32),
         "pty_set_streams": ([vp, i32], i32),
         "pty_forward": ([vp, vp, vp, vp, vp, vp, i32, vp, vp, vp], i32),
+        "pty_forward_static": ([vp, vp, vp, vp, vp, vp, i32, vp, vp, vp], i32),
         "pty_loss_and_grad": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, u32], i32),
         "pty_forward_save": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp], i32),
         "pty_backward": ([vp, vp, f64, vp, vp, vp, u32], i32),

@@ -17,6 +17,40 @@
 
 using namespace pty;
 
+// Working memory of pty_forward_static: one array per GPU in this library's
+// code object, so that entry point calls no allocation routine. In host code
+// the name `scratch` is only a host-side stand-in for the array; kernels are
+// given the device address that hipGetSymbolAddress returns for the current
+// device (scratch_address below), never the name itself.
+static __device__ __align__(256) unsigned char scratch[PTY_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` per device, set once
+
+// Device address of `scratch` on the current device, looked up once per
+// device (at context creation, with the context's device current).
+hipError_t scratch_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 namespace {
 
 constexpr double kPiD = 3.141592653589793238462643383279502884;
@@ -612,6 +646,13 @@ pty_status pty_create_ex(const pty_geometry* g, const pty_options* o, pty_ctx** 
         if (live[x]) c->live_blocks |= 1u << q;
   }
   if (hipMemset(c->flags, 0, 4 * sizeof(int)) != hipSuccess) return fail(PTY_EHIP);
+  // this device's copy of the static scratch array (pty_forward_static)
+  void* sp = nullptr;
+  const hipError_t se = scratch_address(&sp);
+  if (se != hipSuccess) {
+    c->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(se);
+    return fail(PTY_EHIP);
+  }
   *out = c;
   return PTY_OK;
 }
@@ -685,6 +726,62 @@ pty_status pty_forward(pty_ctx* c, void* stream, const pty_c64* probe, const pty
   r.I_out = intensities;
   r.loss_out = (patterns && loss) ? loss : nullptr;
   LaunchCtx L = ctx_launch(c, s, r, B);
+  run_prepare(L, N);
+  for (auto& ch : split_chunks(B, c->chunk)) run_forward_chunk(sub(L, ch.first, ch.second), N, S, {S - 1}, false);
+  if (r.loss_out) run_finish_forward(L, N);
+  HIPCHECK(c, hipGetLastError());
+  return PTY_OK;
+}
+
+static_assert(sizeof(Item) == 40, "pty_forward_static documents 40-byte item descriptors");
+
+pty_status pty_forward_static(pty_ctx* c, void* stream, const pty_c64* probe, const pty_c64* object,
+                              const float* positions, const int32_t* batch_idx, int32_t B, const float* patterns,
+                              float* intensities, double* loss) {
+  if (!c) return PTY_EINVAL;
+  if (!probe || !object || !positions || !batch_idx) { c->err = "NULL input pointer"; return PTY_EINVAL; }
+  const int N = c->g.N, S = c->g.n_slices, M = c->g.n_modes;
+  const size_t N2 = (size_t)N * N;
+  if (B < 1 || B > kMaxItems) {
+    c->err = "batch " + std::to_string(B) + " outside [1, " + std::to_string(kMaxItems) + "]";
+    return PTY_EINVAL;
+  }
+  // pieces of the static array, each 256-byte aligned
+  const size_t o_phat = 0;
+  const size_t o_items = o_phat + align256((size_t)M * N2 * sizeof(float2));
+  const size_t o_ramps = o_items + align256((size_t)B * sizeof(Item));
+  const size_t o_loss = o_ramps + align256((size_t)B * 2 * N * sizeof(float2));
+  const size_t o_ws = o_loss + align256((size_t)B * col_blocks(N) * sizeof(float));
+  const size_t need = o_ws + align256((size_t)B * M * N2 * sizeof(float2));
+  if (need > PTY_STATIC_SCRATCH_BYTES) {
+    c->err = "the call needs " + std::to_string(need) + " bytes of static scratch, more than the " +
+             std::to_string((size_t)PTY_STATIC_SCRATCH_BYTES) + " it has";
+    return PTY_EINVAL;
+  }
+  void* sp = nullptr;
+  HIPCHECK(c, scratch_address(&sp));
+  unsigned char* base = static_cast<unsigned char*>(sp);
+  float2* phat = reinterpret_cast<float2*>(base + o_phat);
+  hipStream_t s = (hipStream_t)stream;
+  c->tape_valid = false;
+  { ProfScope p(P_PLAIN2D, s); launch_plain2d(N, s, c->tw, (const float2*)probe, phat, M, false, 1.f / N, false); }
+  ReqDev r = base_req(c);
+  r.phat = phat;
+  r.gphat = nullptr;
+  r.obj = (const float2*)object;
+  r.positions = positions;
+  r.batch_idx = batch_idx;
+  r.patterns = patterns;
+  r.I_out = intensities;
+  r.loss_out = (patterns && loss) ? loss : nullptr;
+  LaunchCtx L = ctx_launch(c, s, r, B);
+  L.items = reinterpret_cast<Item*>(base + o_items);
+  L.ramps = reinterpret_cast<float2*>(base + o_ramps);
+  L.loss_part = reinterpret_cast<float*>(base + o_loss);
+  L.ws = reinterpret_cast<float2*>(base + o_ws);
+  L.ck = nullptr;
+  L.pos_part = nullptr;
+  L.cscr = nullptr;
   run_prepare(L, N);
   for (auto& ch : split_chunks(B, c->chunk)) run_forward_chunk(sub(L, ch.first, ch.second), N, S, {S - 1}, false);
   if (r.loss_out) run_finish_forward(L, N);
