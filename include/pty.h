@@ -316,6 +316,14 @@ typedef struct {
  *   obj_tv          sum over slices of phi(D_y O) + phi(D_x O), phi(z) = sqrt(|z|^2 + tv_delta^2)
  *   layers_tikhonov sum |O_{i+1} - O_i|^2
  *   layers_tv       sum phi(O_{i+1} - O_i)
+ *   obj_phase_l1    sum |arg O| (arg in (-pi, pi]; gradient 0 where arg O = 0)
+ *   obj_spectrum_l1 sum over slices and over every frequency but zero of |F2(O_i)(k)|, F2 the
+ *                   unitary 2D DFT of the H x W slice (transformed with hipFFT; the call that
+ *                   sets it allocates the plan and an object-sized spectrum buffer)
+ *   probe_phase_tikhonov, probe_phase_tv  the phase plate of each mode, the phase of its unitary
+ *                   spectrum P^ = F(P) taken centred (zero frequency at N/2): for every pair of
+ *                   neighbours (a, b) along either axis, z = a conj(b) = |z| e^{it}, t in (-pi, pi],
+ *                   costs |z| t^2 (Tikhonov) or |z| sqrt(t^2 + tv_delta^2) (TV)
  * Constraint regularizers are applied to the state after the optimiser:
  *   amp_clamp       object amplitude limited to [amp_min, amp_max] (phase kept)
  *   probe_support   host [N][N] reciprocal-space mask (FFT order) or NULL: P <- F^-1(mask F(P))
@@ -327,7 +335,9 @@ typedef struct {
  *   phase_deramp    nonzero: per slice, remove the affine phase theta_0 + theta_y y + theta_x x,
  *                   theta_x = arg sum O(y, x+1) conj O(y, x), theta_y likewise along y, theta_0 =
  *                   arg of the sum of the de-ramped slice
- * Order: amplitude range, depth blur, low pass, deramp (object); support (probe).
+ *   probe_support_real  host [N][N] real-space mask or NULL: P <- mask P
+ * Order: amplitude range, depth blur, low pass, deramp (object); reciprocal-space
+ * support, then real-space support (probe).
  * A NULL argument turns all regularization off. */
 typedef struct {
   double obj_l2, probe_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta;
@@ -337,6 +347,9 @@ typedef struct {
   double layer_sigma;
   double obj_lowpass_sigma;
   int32_t phase_deramp;
+  double obj_phase_l1, obj_spectrum_l1;
+  double probe_phase_tikhonov, probe_phase_tv;
+  const uint8_t* probe_support_real;
 } pty_regularizers;
 
 pty_status pty_set_regularizers(pty_ctx* ctx, const pty_regularizers* reg);

@@ -562,14 +562,34 @@ def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
 #   obj_tikhonov: sum over slices of |D_y O|^2 + |D_x O|^2 (in-plane)
 #   obj_tv:       sum over slices of phi(D_y O) + phi(D_x O)
 #   layers_tikhonov: sum |O_{i+1} - O_i|^2      layers_tv: sum phi(O_{i+1} - O_i)
+#   obj_phase_l1: sum |arg O|, arg in (-pi, pi] (gradient 0 where arg O = 0)
+#   obj_spectrum_l1: sum over slices and over every frequency but the zero
+#                 one of |F2(O_i)(k)|, F2 the unitary 2D DFT of the slice: an
+#                 L1 norm on the object's spectral amplitudes, which favours a
+#                 sparse (periodic) spectrum; the zero frequency is the mean
+#                 transmission and is left free (penalising it would pull the
+#                 vacuum level towards 0)
+#   probe_phase_tikhonov / probe_phase_tv: the phase plate of mode m is the
+#                 phase of its spectrum P^_m = F2(P_m), taken centred (zero
+#                 frequency in the middle, so that neighbouring entries are
+#                 neighbouring frequencies); for each pair of neighbours
+#                 (a, b) along either axis, z = a conj(b) = |z| e^{i t} with t
+#                 the phase step in (-pi, pi] (no unwrapping needed), and the
+#                 cost is |z| t^2 (Tikhonov) or |z| sqrt(t^2 + delta^2) (TV):
+#                 the squared or absolute phase step weighted by the
+#                 amplitudes, so that the phase where the aperture is dark
+#                 costs nothing and the gradient stays bounded
 # Constraint regularizers are applied to the state after each group step:
 #   amplitude range: O <- O * clip(|O|, a_min, a_max) / |O|
-#   probe support:   P <- F^-1(mask * F(P)) with a reciprocal-space mask
+#   probe support:   P <- F^-1(mask * F(P)) with a reciprocal-space mask,
+#                    then P <- mask_r * P with a real-space mask
 #   layer blur:      O_i <- sum_j g(i - j) O_j / sum_j g(i - j), g Gaussian in
 #                    depth (sigma in slices), truncated at 3 sigma, real space
 #                    (no periodic wrap between the top and bottom slices).
 
-REG_KEYS = ("obj_l2", "probe_l2", "obj_l1", "obj_tikhonov", "obj_tv", "layers_tikhonov", "layers_tv")
+REG_KEYS = ("obj_l2", "probe_l2", "obj_l1", "obj_tikhonov", "obj_tv", "layers_tikhonov", "layers_tv",
+            "obj_phase_l1", "obj_spectrum_l1", "probe_phase_tikhonov", "probe_phase_tv")
+PROBE_REG_KEYS = ("probe_l2", "probe_phase_tikhonov", "probe_phase_tv")
 
 
 def _phi(z, delta):
@@ -632,6 +652,46 @@ def regularization(obj, probe, reg):
             g[tuple(hi)] += gd
             g[tuple(lo)] -= gd
             gO += w * g
+    w = reg.get("obj_phase_l1", 0.0)
+    if w:
+        ph = np.angle(O)
+        a2 = np.abs(O) ** 2
+        cost += w * np.sum(np.abs(ph))
+        # d arg(O) / d(Re, Im) combined as dRe + i dIm is i O / |O|^2
+        gO += w * np.where(a2 > 0, np.sign(ph) * 1j * O / np.where(a2 > 0, a2, 1), 0)
+    w = reg.get("obj_spectrum_l1", 0.0)
+    if w:
+        F = fft2u(O)
+        a = np.abs(F)
+        keep = a > 0
+        keep[:, 0, 0] = False
+        cost += w * np.sum(a[keep])
+        gO += w * ifft2u(np.where(keep, F / np.where(keep, a, 1), 0))
+    for key in ("probe_phase_tikhonov", "probe_phase_tv"):
+        w = reg.get(key, 0.0)
+        if not w:
+            continue
+        C = np.fft.fftshift(fft2u(P), axes=(-2, -1))
+        gC = np.zeros_like(C)
+        for ax in (-2, -1):
+            n = C.shape[ax]
+            hi = [slice(None)] * C.ndim
+            lo = [slice(None)] * C.ndim
+            hi[ax] = slice(1, n)
+            lo[ax] = slice(0, n - 1)
+            a, b = C[tuple(hi)], C[tuple(lo)]
+            z = a * np.conj(b)
+            r, t = np.abs(z), np.angle(z)
+            if key == "probe_phase_tikhonov":
+                cost += w * np.sum(r * t * t)
+                G = np.exp(1j * t) * (t * t + 2j * t)          # d(r t^2): e^{it} (d/dr + i/r d/dt)
+            else:
+                q = np.sqrt(t * t + d * d)
+                cost += w * np.sum(r * q)
+                G = np.exp(1j * t) * (q + 1j * t / q)
+            gC[tuple(hi)] += w * G * b                         # z = a conj(b)
+            gC[tuple(lo)] += w * np.conj(G) * a
+        gP += ifft2u(np.fft.ifftshift(gC, axes=(-2, -1)))
     return float(cost), gO, gP
 
 
@@ -683,7 +743,8 @@ def apply_constraints(obj, probe, con):
     object amplitude range (amp_min, amp_max), Gaussian depth blur
     (layer_sigma, slices), in-plane Gaussian low pass (obj_lowpass_sigma,
     pixels), phase deramp (phase_deramp), probe support (probe_support,
-    reciprocal-space mask [N][N] in FFT order)."""
+    reciprocal-space mask [N][N] in FFT order, then probe_support_real, a
+    real-space mask [N][N])."""
     O = np.array(obj, dtype=np.complex128)
     P = np.array(probe, dtype=np.complex128)
     if "amp_min" in con or "amp_max" in con:
@@ -711,4 +772,6 @@ def apply_constraints(obj, probe, con):
         O = deramp_object(O)
     if con.get("probe_support") is not None:
         P = ifft2u(fft2u(P) * (np.asarray(con["probe_support"]) != 0))
+    if con.get("probe_support_real") is not None:
+        P = P * (np.asarray(con["probe_support_real"]) != 0)
     return O, P

@@ -56,7 +56,10 @@ class Regularizers(C.Structure):
                 ("obj_tikhonov", C.c_double), ("obj_tv", C.c_double), ("layers_tikhonov", C.c_double),
                 ("layers_tv", C.c_double), ("tv_delta", C.c_double), ("amp_clamp", C.c_int32),
                 ("amp_min", C.c_double), ("amp_max", C.c_double), ("probe_support", C.POINTER(C.c_uint8)),
-                ("layer_sigma", C.c_double), ("obj_lowpass_sigma", C.c_double), ("phase_deramp", C.c_int32)]
+                ("layer_sigma", C.c_double), ("obj_lowpass_sigma", C.c_double), ("phase_deramp", C.c_int32),
+                ("obj_phase_l1", C.c_double), ("obj_spectrum_l1", C.c_double),
+                ("probe_phase_tikhonov", C.c_double), ("probe_phase_tv", C.c_double),
+                ("probe_support_real", C.POINTER(C.c_uint8))]
 
 
 class Illum(C.Structure):

@@ -157,19 +157,26 @@ class Problem:
 
     def set_regularizers(self, obj_l2=0.0, probe_l2=0.0, obj_l1=0.0, obj_tikhonov=0.0, obj_tv=0.0,
                          layers_tikhonov=0.0, layers_tv=0.0, tv_delta=1e-3, amp_range=None, probe_support=None,
-                         layer_sigma=0.0, obj_lowpass_sigma=0.0, phase_deramp=False):
+                         layer_sigma=0.0, obj_lowpass_sigma=0.0, phase_deramp=False, obj_phase_l1=0.0,
+                         obj_spectrum_l1=0.0, probe_phase_tikhonov=0.0, probe_phase_tv=0.0,
+                         probe_support_real=None):
         """Cost and constraint regularizers applied by reconstruct_step (see include/pty.h)."""
-        mask = None
-        if probe_support is not None:
-            m = np.ascontiguousarray(np.asarray(probe_support) != 0, dtype=np.uint8)
+        def mask_of(a, name):
+            if a is None:
+                return None
+            m = np.ascontiguousarray(np.asarray(a) != 0, dtype=np.uint8)
             if m.shape != (self.N, self.N):
-                raise ValueError(f"probe_support must be {self.N}x{self.N}")
-            mask = (C.c_uint8 * (self.N * self.N)).from_buffer_copy(m.tobytes())
+                raise ValueError(f"{name} must be {self.N}x{self.N}")
+            return (C.c_uint8 * (self.N * self.N)).from_buffer_copy(m.tobytes())
+
+        mask = mask_of(probe_support, "probe_support")
+        mask_r = mask_of(probe_support_real, "probe_support_real")
+        as_ptr = lambda m: C.cast(m, C.POINTER(C.c_uint8)) if m is not None else None  # noqa: E731
         lo, hi = amp_range if amp_range is not None else (0.0, 0.0)
         r = _lib.Regularizers(obj_l2, probe_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta,
-                              1 if amp_range is not None else 0, lo, hi,
-                              C.cast(mask, C.POINTER(C.c_uint8)) if mask is not None else None, layer_sigma,
-                              obj_lowpass_sigma, 1 if phase_deramp else 0)
+                              1 if amp_range is not None else 0, lo, hi, as_ptr(mask), layer_sigma,
+                              obj_lowpass_sigma, 1 if phase_deramp else 0, obj_phase_l1, obj_spectrum_l1,
+                              probe_phase_tikhonov, probe_phase_tv, as_ptr(mask_r))
         st = self.lib.pty_set_regularizers(self.ctx, C.byref(r))
         if st:
             self._err(st, "pty_set_regularizers")

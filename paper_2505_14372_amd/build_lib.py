@@ -59,7 +59,7 @@ def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB) -> s
     for p in procs:
         _wait(p, verbose)
     tmp = out + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lhipfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

@@ -2,6 +2,7 @@
 // and the launch sequences of forward, loss-and-gradient and one optimiser
 // step (arXiv 2505.14372, Sec. 2.2 engine loop, Sec. 3 - 3.2).
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -234,6 +235,14 @@ struct pty_ctx {
   int amp_clamp = 0;
   float amp_min = 0.f, amp_max = 0.f;
   uint8_t* support = nullptr;      // device [N][N] or null
+  uint8_t* support_real = nullptr; // device [N][N] real-space probe support, or null
+  float probe_phase_tik = 0.f, probe_phase_tv = 0.f;
+  // object spectral L1: weight, batched 2D FFT plan of the slices (in place),
+  // spectrum buffer [S][H][W]
+  float obj_spec_l1 = 0.f;
+  hipfftHandle spec_plan = 0;
+  bool spec_plan_ok = false;
+  float2* spec = nullptr;
   float* blur = nullptr;           // device Gaussian weights [r + 1]
   int blur_r = 0;
   float* lowpass = nullptr;        // device in-plane Gaussian weights [r + 1], normalised over 2r + 1 taps
@@ -685,7 +694,9 @@ void pty_destroy(pty_ctx* c) {
   dfree(c->tw); dfree(c->prop); dfree(c->phat); dfree(c->gphat); dfree(c->gprobe); dfree(c->gobj);
   dfree(c->gpos); dfree(c->flags); dfree(c->ws); dfree(c->ws2); dfree(c->ck); dfree(c->seg);
   dfree(c->items); dfree(c->ramps); dfree(c->loss_part); dfree(c->pos_part);
-  dfree(c->support); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
+  if (c->spec_plan_ok) (void)hipfftDestroy(c->spec_plan);
+  dfree(c->spec);
+  dfree(c->support); dfree(c->support_real); dfree(c->blur); dfree(c->lowpass); dfree(c->deramp); dfree(c->reg_part); dfree(c->emax); dfree(c->live);
   dfree(c->prop_y); dfree(c->prop_x); dfree(c->cscr);
   dfree(c->lsq_w); dfree(c->lsq_part); dfree(c->lsq_wp); dfree(c->lsq_sums); dfree(c->lsq_tau); dfree(c->lsq_wscr);
   for (int k = 0; k < kMaxStreams; ++k) {
@@ -970,15 +981,39 @@ void apply_cost_regularizers(pty_ctx* c, hipStream_t s, const pty_state* st, dou
   const pty_geometry& g = c->g;
   int nb = 0;
   if (c->rg.obj_l2 != 0.f || c->rg.obj_l1 != 0.f || c->rg.obj_tikhonov != 0.f || c->rg.obj_tv != 0.f ||
-      c->rg.layers_tikhonov != 0.f || c->rg.layers_tv != 0.f)
+      c->rg.layers_tikhonov != 0.f || c->rg.layers_tv != 0.f || c->rg.obj_phase_l1 != 0.f)
     nb = launch_reg_object(s, (const float2*)st->object, c->gobj, g.n_slices, g.obj_h, g.obj_w, c->rg, c->reg_part);
   int np = 0;
   if (c->probe_l2 != 0.f)
     np = launch_reg_probe(s, (const float2*)st->probe, c->gprobe, (size_t)g.n_modes * g.N * g.N, c->probe_l2,
                           c->reg_part + 4096);
+  int ns = 0;
+  if (c->obj_spec_l1 != 0.f && c->spec_plan_ok) {
+    // |F2 O|: forward FFT of a copy of the slices, the L1 step, inverse FFT,
+    // added into the object gradient (every transform in place, one plan)
+    const size_t HW = (size_t)g.obj_h * g.obj_w, n = HW * g.n_slices;
+    (void)hipMemcpyAsync(c->spec, st->object, n * sizeof(float2), hipMemcpyDeviceToDevice, s);
+    (void)hipfftSetStream(c->spec_plan, s);
+    (void)hipfftExecC2C(c->spec_plan, (hipfftComplex*)c->spec, (hipfftComplex*)c->spec, HIPFFT_FORWARD);
+    ns = launch_spec_l1(s, c->spec, n, HW, c->obj_spec_l1, c->reg_part + 3 * 4096);
+    (void)hipfftExecC2C(c->spec_plan, (hipfftComplex*)c->spec, (hipfftComplex*)c->spec, HIPFFT_BACKWARD);
+    launch_cadd_inplace(s, c->gobj, c->spec, n);
+  }
+  int nq = 0;
+  if (c->probe_phase_tik != 0.f || c->probe_phase_tv != 0.f) {
+    // the phase plate acts on the step's probe spectrum (phat, from the state
+    // before the update); its gradient, taken with respect to that spectrum in
+    // the free gphat buffer, reaches the probe through the adjoint of the
+    // unitary DFT
+    nq = launch_reg_probe_phase(s, c->phat, c->gphat, g.n_modes, g.N, c->probe_phase_tik, c->probe_phase_tv,
+                                c->rg.tv_delta, c->reg_part + 8192);
+    launch_plain2d(g.N, s, c->tw, c->gphat, c->gprobe, g.n_modes, true, 1.f / g.N, true);
+  }
   if (loss) {
     if (nb) launch_add_cost(s, c->reg_part, nb, loss);
     if (np) launch_add_cost(s, c->reg_part + 4096, np, loss);
+    if (nq) launch_add_cost(s, c->reg_part + 8192, nq, loss);
+    if (ns) launch_add_cost(s, c->reg_part + 3 * 4096, ns, loss);
   }
 }
 
@@ -999,6 +1034,8 @@ void apply_constraints(pty_ctx* c, hipStream_t s, pty_state* st) {
     launch_mask_tiles(s, c->gphat, c->support, (size_t)M * N * N, N * N);
     launch_plain2d(N, s, c->tw, c->gphat, (float2*)st->probe, M, true, 1.f / N, false);
   }
+  if (c->support_real)
+    launch_mask_tiles(s, (float2*)st->probe, c->support_real, (size_t)g.n_modes * g.N * g.N, g.N * g.N);
 }
 
 }  // namespace
@@ -1006,17 +1043,27 @@ void apply_constraints(pty_ctx* c, hipStream_t s, pty_state* st) {
 extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r) {
   if (!c) return PTY_EINVAL;
   dfree(c->support);
+  dfree(c->support_real);
   dfree(c->blur);
   dfree(c->lowpass);
   dfree(c->deramp);
+  if (c->spec_plan_ok) (void)hipfftDestroy(c->spec_plan);
+  c->spec_plan_ok = false;
+  dfree(c->spec);
   c->reg_on = c->con_on = false;
+  c->probe_phase_tik = c->probe_phase_tv = c->obj_spec_l1 = 0.f;
   c->amp_clamp = 0;
   c->blur_r = c->lowpass_r = 0;
   if (!r) return PTY_OK;
-  const double w[7] = {r->obj_l2, r->probe_l2, r->obj_l1, r->obj_tikhonov, r->obj_tv, r->layers_tikhonov, r->layers_tv};
+  const double w[11] = {r->obj_l2, r->probe_l2, r->obj_l1, r->obj_tikhonov, r->obj_tv, r->layers_tikhonov,
+                        r->layers_tv, r->obj_phase_l1, r->obj_spectrum_l1, r->probe_phase_tikhonov,
+                        r->probe_phase_tv};
   for (double x : w)
     if (!(x >= 0.0) || !std::isfinite(x)) { c->err = "regularizer weights must be finite and >= 0"; return PTY_EINVAL; }
-  if ((r->obj_tv > 0 || r->layers_tv > 0) && !(r->tv_delta > 0)) { c->err = "tv_delta must be > 0"; return PTY_EINVAL; }
+  if ((r->obj_tv > 0 || r->layers_tv > 0 || r->probe_phase_tv > 0) && !(r->tv_delta > 0)) {
+    c->err = "tv_delta must be > 0";
+    return PTY_EINVAL;
+  }
   if (r->amp_clamp && !(r->amp_min >= 0 && r->amp_max >= r->amp_min)) { c->err = "need 0 <= amp_min <= amp_max"; return PTY_EINVAL; }
   if (r->layer_sigma < 0 || (r->layer_sigma > 0 && c->g.n_slices > kMaxBlurSlices)) {
     c->err = "layer blur needs sigma >= 0 and at most 64 slices";
@@ -1027,11 +1074,25 @@ extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r
     return PTY_EINVAL;
   }
   c->rg = RegDev{(float)r->obj_l2, (float)r->obj_l1, (float)r->obj_tikhonov, (float)r->obj_tv,
-                 (float)r->layers_tikhonov, (float)r->layers_tv, (float)r->tv_delta};
+                 (float)r->layers_tikhonov, (float)r->layers_tv, (float)r->tv_delta, (float)r->obj_phase_l1};
   c->probe_l2 = (float)r->probe_l2;
+  c->probe_phase_tik = (float)r->probe_phase_tikhonov;
+  c->probe_phase_tv = (float)r->probe_phase_tv;
   for (double x : w) c->reg_on = c->reg_on || x > 0;
   pty_status st;
-  if (!c->reg_part && (st = dmalloc(&c->reg_part, 8192, c->err))) return st;
+  // cost partial sums: object terms, probe L2, probe phase plate, object spectrum (4096 each)
+  if (!c->reg_part && (st = dmalloc(&c->reg_part, 4 * 4096, c->err))) return st;
+  if (r->obj_spectrum_l1 > 0) {
+    const int S = c->g.n_slices, H = c->g.obj_h, W = c->g.obj_w;
+    if ((st = dmalloc(&c->spec, (size_t)S * H * W, c->err))) return st;
+    int dims[2] = {H, W};
+    if (hipfftPlanMany(&c->spec_plan, 2, dims, nullptr, 1, H * W, nullptr, 1, H * W, HIPFFT_C2C, S) != HIPFFT_SUCCESS) {
+      c->err = "hipfftPlanMany failed for the object spectrum";
+      return PTY_EHIP;
+    }
+    c->spec_plan_ok = true;
+    c->obj_spec_l1 = (float)r->obj_spectrum_l1;
+  }
   c->amp_clamp = r->amp_clamp ? 1 : 0;
   c->amp_min = (float)r->amp_min;
   c->amp_max = (float)r->amp_max;
@@ -1041,6 +1102,12 @@ extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r
     std::vector<uint8_t> m(r->probe_support, r->probe_support + N2);
     for (auto& v : m) v = v ? 1 : 0;
     if (hipMemcpy(c->support, m.data(), N2, hipMemcpyHostToDevice) != hipSuccess) return PTY_EHIP;
+  }
+  if (r->probe_support_real) {
+    if ((st = dmalloc(&c->support_real, N2, c->err))) return st;
+    std::vector<uint8_t> m(r->probe_support_real, r->probe_support_real + N2);
+    for (auto& v : m) v = v ? 1 : 0;
+    if (hipMemcpy(c->support_real, m.data(), N2, hipMemcpyHostToDevice) != hipSuccess) return PTY_EHIP;
   }
   if (r->layer_sigma > 0 && c->g.n_slices > 1) {
     c->blur_r = (int)std::ceil(3.0 * r->layer_sigma);
@@ -1067,7 +1134,7 @@ extern "C" pty_status pty_set_regularizers(pty_ctx* c, const pty_regularizers* r
     const size_t n = 3 * (size_t)c->g.n_slices + (size_t)c->g.n_slices * deramp_blocks(c->g.obj_h, c->g.obj_w) * 4;
     if ((st = dmalloc(&c->deramp, n, c->err))) return st;
   }
-  c->con_on = c->amp_clamp || c->support || c->blur || c->lowpass || c->deramp;
+  c->con_on = c->amp_clamp || c->support || c->support_real || c->blur || c->lowpass || c->deramp;
   return PTY_OK;
 }
 

@@ -161,13 +161,22 @@ enum ColOp { COL_SHIFT = 0, COL_PROP = 1, COL_PROP_ADJ = 2, COL_FINAL = 3 };
 
 // Cost-regularizer weights on the device side (float).
 struct RegDev {
-  float obj_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta;
+  float obj_l2, obj_l1, obj_tikhonov, obj_tv, layers_tikhonov, layers_tv, tv_delta, obj_phase_l1;
 };
 constexpr int kMaxBlurSlices = 64;
 
 int launch_reg_object(hipStream_t s, const float2* O, float2* g, int S, int H, int W, const RegDev& rg,
                       float* cost_part);
 int launch_reg_probe(hipStream_t s, const float2* P, float2* g, size_t n, float w, float* cost_part);
+// Probe phase-plate Tikhonov (wt) / TV (wv) on the unitary spectra phat [M][N][N]
+// (FFT order): writes the gradient with respect to phat into gphat and cost
+// partials; returns the number of partials.
+// Spectral L1 step between the forward and inverse FFTs of the object slices
+// (see k_spec_l1); returns the number of cost partials.
+int launch_spec_l1(hipStream_t s, float2* spec, size_t n, size_t HW, float w, float* cost_part);
+void launch_cadd_inplace(hipStream_t s, float2* g, const float2* a, size_t n);
+int launch_reg_probe_phase(hipStream_t s, const float2* phat, float2* gphat, int M, int N, float wt, float wv,
+                           float delta, float* cost_part);
 void launch_add_cost(hipStream_t s, const float* part, int n, double* loss);
 void launch_amp_clamp(hipStream_t s, float2* O, size_t n, float lo, float hi);
 void launch_layer_blur(hipStream_t s, float2* O, int S, size_t HW, const float* g, int r);

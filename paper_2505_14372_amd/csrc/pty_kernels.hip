@@ -27,6 +27,8 @@
 
 #include <hip/hip_fp16.h>
 
+#include <cmath>
+
 #include "pty_fft.hpp"
 #include "pty_internal.h"
 
@@ -1300,6 +1302,16 @@ __global__ void k_reg_object(const float2* __restrict__ O, float2* __restrict__ 
       if (a > 0.f) gr = cadd(gr, cscale(d, rg.obj_l1 / a));
       cost += rg.obj_l1 * a;
     }
+    if (rg.obj_phase_l1 != 0.f) {
+      // |arg O|: d arg O / d(Re, Im), combined as dRe + i dIm, is i O / |O|^2
+      const float ph = atan2f(o.y, o.x);
+      const float a2 = cabs2(o);
+      cost += rg.obj_phase_l1 * fabsf(ph);
+      if (ph != 0.f && a2 > 0.f) {
+        const float sc = (ph > 0.f ? rg.obj_phase_l1 : -rg.obj_phase_l1) / a2;
+        gr = cadd(gr, make_float2(-o.y * sc, o.x * sc));
+      }
+    }
     const bool in_tik = rg.obj_tikhonov != 0.f, in_tv = rg.obj_tv != 0.f;
     const bool z_tik = rg.layers_tikhonov != 0.f, z_tv = rg.layers_tv != 0.f;
     // neighbours along each axis: (stride, has_prev, has_next, weight_tik, weight_tv)
@@ -1354,6 +1366,115 @@ __global__ void k_reg_probe(const float2* __restrict__ P, float2* __restrict__ g
     for (int w2 = 0; w2 < kThreads / 64; ++w2) t += red[w2];
     cost_part[blockIdx.x] = t;
   }
+}
+
+// Probe phase plate (Tikhonov weight wt, TV weight wv) on the unitary spectra
+// phat [M][N][N] in FFT order. Centred, frequency index u sits at c = (u + N/2)
+// mod N, so the centred neighbours of u are u - 1 and u + 1 (mod N) except
+// across the centred array's ends (u = N/2 has no lower neighbour, u = N/2 - 1
+// no upper one). A pair (a, b) of neighbours, a the upper one, has
+// z = a conj(b) = r e^{it} and cost r t^2 (Tikhonov) or r sqrt(t^2 + d^2)
+// (TV), whose gradient with respect to z is G = e^{it} (dC/dr + i/r dC/dt):
+// e^{it} (t^2 + 2it) and e^{it} (q + it/q), q = sqrt(t^2 + d^2); then
+// dC/da = G b and dC/db = conj(G) a. One thread per pixel gathers the terms
+// of its (up to four) pairs into gphat and counts the cost of the pairs where
+// it is the upper element, so each pair is counted once.
+__device__ __forceinline__ float2 phase_pair_grad(float2 z, float wt, float wv, float d2, float& cost) {
+  const float r = sqrtf(cabs2(z));
+  const float t = atan2f(z.y, z.x);
+  const float2 e = r > 0.f ? cscale(z, 1.f / r) : make_float2(1.f, 0.f);
+  float2 G = make_float2(0.f, 0.f);
+  if (wt != 0.f) {
+    cost += wt * r * t * t;
+    G = cadd(G, cscale(cmul(e, make_float2(t * t, 2.f * t)), wt));
+  }
+  if (wv != 0.f) {
+    const float q = sqrtf(t * t + d2);
+    cost += wv * r * q;
+    G = cadd(G, cscale(cmul(e, make_float2(q, t / q)), wv));
+  }
+  return G;
+}
+
+__global__ void k_reg_probe_phase(const float2* __restrict__ phat, float2* __restrict__ gphat, int M, int N,
+                                  float wt, float wv, float d2, float* __restrict__ cost_part) {
+  __shared__ float red[kThreads / 64];
+  const size_t N2 = (size_t)N * N, n = (size_t)M * N2;
+  float cost = 0.f;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t base = e - e % N2;
+    const int uy = (int)((e % N2) / N), ux = (int)(e % N);
+    const float2 a = phat[e];
+    float2 g = make_float2(0.f, 0.f);
+    float c_own = 0.f, c_other = 0.f;
+    const int h = N / 2;
+    // neighbours along y then x: lower (this pixel is the upper element), upper
+    const int lo_y = (uy + N - 1) % N, hi_y = (uy + 1) % N, lo_x = (ux + N - 1) % N, hi_x = (ux + 1) % N;
+    if (uy != h) {
+      const float2 b = phat[base + (size_t)lo_y * N + ux];
+      g = cadd(g, cmul(phase_pair_grad(cjmul(b, a), wt, wv, d2, c_own), b));
+    }
+    if (uy != h - 1) {
+      const float2 c = phat[base + (size_t)hi_y * N + ux];
+      g = cadd(g, cmul(cconj(phase_pair_grad(cjmul(a, c), wt, wv, d2, c_other)), c));
+    }
+    if (ux != h) {
+      const float2 b = phat[base + (size_t)uy * N + lo_x];
+      g = cadd(g, cmul(phase_pair_grad(cjmul(b, a), wt, wv, d2, c_own), b));
+    }
+    if (ux != h - 1) {
+      const float2 c = phat[base + (size_t)uy * N + hi_x];
+      g = cadd(g, cmul(cconj(phase_pair_grad(cjmul(a, c), wt, wv, d2, c_other)), c));
+    }
+    gphat[e] = g;
+    cost += c_own;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cost;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int w2 = 0; w2 < kThreads / 64; ++w2) t += red[w2];
+    cost_part[blockIdx.x] = t;
+  }
+}
+
+// Spectral L1 of the object, between the two FFTs of the slices: spec holds
+// the unnormalised DFT of every H x W slice; with the unitary spectrum
+// F = spec / sqrt(HW), the cost is w |F| summed over every frequency but the
+// zero one, and spec is replaced by w F / |F| / sqrt(HW) (0 at the zero
+// frequency and where F = 0), whose unnormalised inverse DFT is the
+// gradient w F2^H(F / |F|).
+__global__ void k_spec_l1(float2* __restrict__ spec, size_t n, size_t HW, float w, float inv_sqrt,
+                          float* __restrict__ cost_part) {
+  __shared__ float red[kThreads / 64];
+  float cost = 0.f;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const float2 F = cscale(spec[e], inv_sqrt);
+    const float a = sqrtf(cabs2(F));
+    float2 g = make_float2(0.f, 0.f);
+    if (e % HW != 0 && a > 0.f) {
+      cost += w * a;
+      g = cscale(F, w * inv_sqrt / a);
+    }
+    spec[e] = g;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cost;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int w2 = 0; w2 < kThreads / 64; ++w2) t += red[w2];
+    cost_part[blockIdx.x] = t;
+  }
+}
+
+// g += a (complex, n values).
+__global__ void k_cadd_inplace(float2* __restrict__ g, const float2* __restrict__ a, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    g[e] = cadd(g[e], a[e]);
 }
 
 // loss += sum of the cost partials (double), one block.
@@ -1758,6 +1879,22 @@ int launch_reg_probe(hipStream_t s, const float2* P, float2* g, size_t n, float 
   const int nb = reg_blocks(n);
   hipLaunchKernelGGL(k_reg_probe, dim3(nb), dim3(kThreads), 0, s, P, g, n, w, cost_part);
   return nb;
+}
+int launch_reg_probe_phase(hipStream_t s, const float2* phat, float2* gphat, int M, int N, float wt, float wv,
+                           float delta, float* cost_part) {
+  const int nb = reg_blocks((size_t)M * N * N);
+  hipLaunchKernelGGL(k_reg_probe_phase, dim3(nb), dim3(kThreads), 0, s, phat, gphat, M, N, wt, wv, delta * delta,
+                     cost_part);
+  return nb;
+}
+int launch_spec_l1(hipStream_t s, float2* spec, size_t n, size_t HW, float w, float* cost_part) {
+  const int nb = reg_blocks(n);
+  hipLaunchKernelGGL(k_spec_l1, dim3(nb), dim3(kThreads), 0, s, spec, n, HW, w, (float)(1.0 / std::sqrt((double)HW)),
+                     cost_part);
+  return nb;
+}
+void launch_cadd_inplace(hipStream_t s, float2* g, const float2* a, size_t n) {
+  hipLaunchKernelGGL(k_cadd_inplace, dim3(reg_blocks(n)), dim3(kThreads), 0, s, g, a, n);
 }
 void launch_add_cost(hipStream_t s, const float* part, int n, double* loss) {
   hipLaunchKernelGGL(k_add_cost, dim3(1), dim3(kThreads), 0, s, part, n, loss);

@@ -794,6 +794,78 @@ def test_regularized_step_matches_oracle():
     assert np.max(np.abs(spec[:, ~support])) < 1e-4 * np.max(np.abs(spec))
 
 
+def test_phase_regularizers_match_oracle():
+    """reconstruct_step with the object-phase L1, the probe phase-plate
+    Tikhonov and TV costs and the real-space probe support (Sec. 3.4): the
+    group loss (detector plus costs) to 1e-4 and the SGD updates of object and
+    probe to the gradient bar (plus the float32 resolution of the state)."""
+    from paper_2505_14372_amd import api
+    c = Case(synth.make_small(N=64, M=2, S=3, scan=3, step=4, seed=33, loss="poisson", eps=0.8, amp_noise=0.2))
+    d = c.device()
+    prob = c.problem(max_batch=9)
+    yy, xx = np.mgrid[:64, :64]
+    mask_r = ((yy - 32) ** 2 + (xx - 32) ** 2 <= 26 ** 2) | ((yy < 20) & (xx < 20))
+    reg = dict(obj_phase_l1=4.0, probe_phase_tikhonov=0.3, probe_phase_tv=0.2, tv_delta=0.05)
+    con = dict(probe_support_real=mask_r)
+    prob.set_regularizers(**reg, probe_support_real=mask_r)
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    lr = dict(object=2e-3, probe=2e-4, pos=0.0)
+    opt = api.Optimizer(kind="sgd", lr_object=lr["object"], lr_probe=lr["probe"], lr_pos=lr["pos"])
+    P0, O0, X0 = c.o_args()
+    ost = dict(probe=P0, object=O0, positions=X0)
+    oopt = dict(kind="sgd", lr_object=lr["object"], lr_probe=lr["probe"], lr_pos=lr["pos"], reg=reg, con=con)
+    b = [0, 2, 4, 5, 8]
+    loss = prob.reconstruct_step(st, d["pats"], torch.tensor(b, dtype=torch.int32, device="cuda"), opt)
+    prob.check()
+    ost, oloss = orc.reconstruct_step(ost, c.pats.astype(np.float64), b, c.geom, oopt)
+    creg, _, _ = orc.regularization(O0, P0, reg)
+    print(f"loss {loss.item():.6e} oracle {oloss:.6e} (costs {creg:.4e})")
+    assert creg > 1e-3 * abs(oloss)
+    assert abs(loss.item() - oloss) < 1e-4 * abs(oloss), (loss.item(), oloss)
+    for key, got, init in (("object", st.object, O0), ("probe", st.probe, P0)):
+        want = ost[key]
+        du_g = _np(got).astype(np.complex128) - init
+        res = np.linalg.norm(np.spacing(_real_components(want).astype(np.float32)).astype(np.float64))
+        err = np.linalg.norm(_real_components(du_g) - _real_components(want - init))
+        print(key, rel_l2(du_g, want - init), err, res)
+        assert err <= TOL_G * np.linalg.norm(_real_components(want - init)) + res, (key, err, res)
+    # the real-space support holds exactly on the GPU state
+    assert np.all(_np(st.probe)[:, ~mask_r] == 0)
+
+
+def test_object_spectrum_l1_matches_oracle():
+    """reconstruct_step with the object spectral L1 (Sec. 3.4) on a non-square
+    object whose sides (76 x 97) are not powers of two: loss to 1e-4 and the
+    SGD update of the object to the gradient bar."""
+    from paper_2505_14372_amd import api
+    c = Case(_widen(synth.make_small(N=64, M=1, S=2, scan=3, step=4, seed=34, loss="amplitude", amp_noise=0.2),
+                    21, seed=34, shift=11.0))
+    d = c.device()
+    prob = c.problem(max_batch=9)
+    reg = dict(obj_spectrum_l1=0.5)
+    prob.set_regularizers(**reg)
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    lr = dict(object=2e-3, probe=0.0, pos=0.0)
+    opt = api.Optimizer(kind="sgd", lr_object=lr["object"], lr_probe=0.0, lr_pos=0.0)
+    P0, O0, X0 = c.o_args()
+    oopt = dict(kind="sgd", lr_object=lr["object"], lr_probe=0.0, lr_pos=0.0, reg=reg)
+    b = [0, 1, 4, 7]
+    loss = prob.reconstruct_step(st, d["pats"], torch.tensor(b, dtype=torch.int32, device="cuda"), opt)
+    prob.check()
+    ost, oloss = orc.reconstruct_step(dict(probe=P0, object=O0, positions=X0), c.pats.astype(np.float64), b,
+                                      c.geom, oopt)
+    creg, gR, _ = orc.regularization(O0, P0, reg)
+    print(f"loss {loss.item():.6e} oracle {oloss:.6e} (cost {creg:.4e})")
+    assert creg > 1e-2 * abs(oloss)
+    assert abs(loss.item() - oloss) < 1e-4 * abs(oloss), (loss.item(), oloss)
+    want = ost["object"]
+    du_g = _np(st.object).astype(np.complex128) - O0
+    res = np.linalg.norm(np.spacing(_real_components(want).astype(np.float32)).astype(np.float64))
+    err = np.linalg.norm(_real_components(du_g) - _real_components(want - O0))
+    print(rel_l2(du_g, want - O0), err, res)
+    assert err <= TOL_G * np.linalg.norm(_real_components(want - O0)) + res, (err, res)
+
+
 def test_lowpass_and_deramp_constraints_match_oracle():
     """reconstruct_step with the object low pass and the phase deramp (Sec. 3.4)
     on an odd-sized object that carries an affine phase ramp per slice."""

@@ -20,7 +20,7 @@ def test_regularizer_gradient_matches_finite_differences(key):
     _, gO, gP = orc.regularization(O, P, reg)
     h = 1e-6
     for _ in range(12):
-        if key == "probe_l2":
+        if key in orc.PROBE_REG_KEYS:
             idx = (rng.integers(2), rng.integers(5), rng.integers(5))
             base, g = P, gP
         else:
@@ -30,7 +30,7 @@ def test_regularizer_gradient_matches_finite_differences(key):
             a, b = base.copy(), base.copy()
             a[idx] += h * part
             b[idx] -= h * part
-            if key == "probe_l2":
+            if key in orc.PROBE_REG_KEYS:
                 fd = (orc.regularization(O, a, reg)[0] - orc.regularization(O, b, reg)[0]) / (2 * h)
             else:
                 fd = (orc.regularization(a, P, reg)[0] - orc.regularization(b, P, reg)[0]) / (2 * h)
@@ -68,6 +68,53 @@ def test_vacuum_and_closed_forms():
     assert abs(orc.regularization(vac, P, {"probe_l2": 1.0})[0] - np.sum(np.abs(P) ** 2)) < 1e-12
 
 
+def test_phase_and_spectrum_l1_closed_forms():
+    """Object-phase L1 is the summed |phase| whatever the amplitude; the
+    spectral L1 of 1 + c * (one Fourier mode) is |c| sqrt(H W) per slice (the
+    unitary DFT puts sqrt(H W) c on that frequency and the free zero frequency
+    costs nothing), and a conjugate pair of modes costs twice that."""
+    rng = np.random.default_rng(11)
+    S, H, W = 2, 6, 10
+    ph = rng.uniform(-3.0, 3.0, (S, H, W))
+    amp = 0.3 + 2 * rng.random((S, H, W))
+    P = np.zeros((1, 4, 4), complex)
+    c, gO, _ = orc.regularization(amp * np.exp(1j * ph), P, {"obj_phase_l1": 1.0})
+    assert abs(c - np.sum(np.abs(ph))) < 1e-10
+    # the gradient is tangential (changes the phase only): Re(conj(g) O) = 0
+    assert np.max(np.abs(np.real(np.conj(gO) * amp * np.exp(1j * ph)))) < 1e-12
+    y, x = np.mgrid[:H, :W]
+    mode = np.exp(2j * np.pi * (2 * y / H + 3 * x / W))
+    cc = 0.2 - 0.7j
+    O = 1 + cc * np.stack([mode, mode])
+    c, _, _ = orc.regularization(O, P, {"obj_spectrum_l1": 1.0})
+    assert abs(c - S * abs(cc) * np.sqrt(H * W)) < 1e-10
+    O = 3.0 + cc * np.stack([mode + np.conj(mode)] * S)
+    c, _, _ = orc.regularization(O, P, {"obj_spectrum_l1": 1.0})
+    assert abs(c - 2 * S * abs(cc) * np.sqrt(H * W)) < 1e-10
+
+
+def test_probe_phase_plate_closed_forms():
+    """Phase-plate Tikhonov / TV of a probe whose centred spectrum is
+    A exp(i alpha k_y): every step along k_y has phase alpha and weight A^2,
+    every step along k_x phase 0; a global phase and the amplitude pattern's
+    sign conventions leave it unchanged; a uniform phase plate costs nothing
+    (Tikhonov) or delta per step (TV)."""
+    N, A, al, d = 7, 1.3, 0.4, 0.05
+    k = np.arange(N)[:, None] * np.ones((1, N))
+    C = A * np.exp(1j * al * k)
+    P = orc.ifft2u(np.fft.ifftshift(C))[None]
+    vac = np.ones((1, 8, 8), complex)
+    c, _, _ = orc.regularization(vac, P, {"probe_phase_tikhonov": 1.0})
+    assert abs(c - N * (N - 1) * A * A * al * al) < 1e-10
+    c, _, _ = orc.regularization(vac, P, {"probe_phase_tv": 1.0, "tv_delta": d})
+    assert abs(c - N * (N - 1) * A * A * (np.sqrt(al * al + d * d) + d)) < 1e-10
+    c2, _, _ = orc.regularization(vac, P * np.exp(0.9j), {"probe_phase_tikhonov": 1.0})
+    assert abs(c2 - N * (N - 1) * A * A * al * al) < 1e-10
+    flat = orc.ifft2u(np.fft.ifftshift(A * np.exp(0.7j) * np.ones((N, N))))[None]
+    c, g, gP = orc.regularization(vac, flat, {"probe_phase_tikhonov": 1.0})
+    assert abs(c) < 1e-20 and np.max(np.abs(gP)) < 1e-12
+
+
 def test_constraints():
     rng = np.random.default_rng(2)
     O = (0.2 + 2 * rng.random((4, 5, 6))) * np.exp(1j * rng.random((4, 5, 6)))
@@ -84,6 +131,13 @@ def test_constraints():
     m[:3, :3] = 1
     _, P4 = orc.apply_constraints(O, P, {"probe_support": m})
     assert np.allclose(orc.fft2u(P4) * (1 - m), 0) and np.allclose(orc.fft2u(P4) * m, orc.fft2u(P) * m)
+    # real-space probe support: zero outside the mask, unchanged inside, after the reciprocal one
+    mr = np.zeros((8, 8))
+    mr[2:6, 1:7] = 1
+    _, P5 = orc.apply_constraints(O, P, {"probe_support_real": mr})
+    assert np.array_equal(P5 * (1 - mr), 0 * P5) and np.array_equal(P5 * mr, P * mr)
+    _, P6 = orc.apply_constraints(O, P, {"probe_support": m, "probe_support_real": mr})
+    assert np.allclose(P6, P4 * mr)
     # layer blur: identical slices unchanged; one bright slice spreads as normalised Gaussian weights
     same = np.repeat(O[:1], 4, axis=0)
     assert np.allclose(orc.apply_constraints(same, P, {"layer_sigma": 1.3})[0], same)
