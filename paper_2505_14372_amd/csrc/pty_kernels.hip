@@ -53,32 +53,13 @@ __device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw_g
 }
 
 
-#ifndef PTY_NT_CKPT
-#define PTY_NT_CKPT 0
-#endif
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-
 // Entry-wave checkpoint storage: complex64 (float2) or two IEEE halves
-// (__half2, round to nearest). Stores/loads bypass the caches when
-// PTY_NT_CKPT is set.
+// (__half2, round to nearest).
 template <bool HALF> struct Ck;
 template <> struct Ck<false> {
   using T = float2;
-  __device__ __forceinline__ static void store(T* p, float2 v) {
-    if (PTY_NT_CKPT) {
-      f32x2 w = {v.x, v.y};
-      __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p));
-    } else {
-      *p = v;
-    }
-  }
-  __device__ __forceinline__ static float2 load(const T* p) {
-    if (PTY_NT_CKPT) {
-      f32x2 w = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
-      return make_float2(w.x, w.y);
-    }
-    return *p;
-  }
+  __device__ __forceinline__ static void store(T* p, float2 v) { *p = v; }
+  __device__ __forceinline__ static float2 load(const T* p) { return *p; }
 };
 template <> struct Ck<true> {
   using T = __half2;
