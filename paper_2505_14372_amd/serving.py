@@ -10,12 +10,14 @@ server runs many jobs (Sec. 2.3), but sharing the GPU instead of queueing:
   already running, in arrival order;
 * residency: an admitted request keeps its whole state on the device until
   its last iteration, then its result is copied out and its memory freed;
-* shared launches: in every round, each running request contributes its next
-  minibatch of positions (one stochastic-gradient step, Sec. 3.2), and the
-  minibatches of all requests with the same N go into shared kernel
-  launches (pty_group_reconstruct_step: up to 16 reconstructions per launch,
-  mixed M, S, object size and loss); groups of different N run on separate
-  HIP streams, so their work overlaps on the device;
+* shared launches: a round of size N is one shared kernel launch
+  (pty_group_reconstruct_step: up to 16 reconstructions, mixed M, S, object
+  size and loss) filled in arrival order with the next minibatch (one
+  stochastic-gradient step, Sec. 3.2) of each running request of that size
+  until its workspace is full: the oldest requests step in every round, as
+  they would alone, and the small ones behind them share the launch instead
+  of waiting for a GPU they would leave mostly idle; groups of different N
+  run on separate HIP streams, so their work overlaps on the device;
 * pipelining: the state is resident and every step is stream-ordered, so the
   next round of a size class is enqueued before the previous one has
   finished (up to `depth` rounds in flight per size); the host polls only to
@@ -69,6 +71,7 @@ class ReconRequest:
                                                                      lr_probe=1e-3, lr_pos=0.0))
     arrival: float = 0.0
     seed: int = 0
+    truth: Optional[np.ndarray] = None   # true object the patterns were simulated from, if any
 
     @property
     def J(self):
@@ -180,7 +183,7 @@ class Server:
     """Admits, batches and runs reconstructions; see the module docstring."""
 
     def __init__(self, hbm_budget: int, group_tiles: Optional[Dict[int, int]] = None, device="cuda",
-                 max_per_launch: int = 16, reduction: str = "atomic", depth: int = 2):
+                 max_per_launch: int = 16, reduction: str = "atomic", depth: int = 2, fill_first: bool = True):
         self.dev = torch.device(device)
         self.reduction = reduction   # object-gradient accumulation of every reconstruction
         self.budget = int(hbm_budget)
@@ -194,6 +197,7 @@ class Server:
         self.used = 0
         self.rounds = 0
         self.depth = max(1, int(depth))        # rounds in flight per size class
+        self.fill_first = bool(fill_first)      # one launch per round, filled in arrival order
         self.inflight: Dict[int, List[tuple]] = {}   # N -> [(event, steps launched)], oldest first
 
     # workspace of the shared launches of one N (allocated on first use, counted in the budget)
@@ -237,8 +241,12 @@ class Server:
         return admitted
 
     def _launch_round(self, N, runs, now):
-        """One step of every running request of size N that has work left, in
-        shared launches on N's stream; returns (event, steps launched)."""
+        """One step of the running requests of size N that have work left, in
+        shared launches on N's stream; returns (event, steps launched). With
+        fill_first, a round is one shared launch filled in arrival order: the
+        oldest requests step every round, as they would alone, and younger
+        ones take the room they leave; otherwise every request steps in every
+        round (several launches when one does not hold them)."""
         grp = self.groups[N]
         cap = self.group_tiles[N]
         stream = self.streams[N]
@@ -252,6 +260,8 @@ class Server:
                 need_c = need_t * r.req.S
                 if launch and (len(launch) == self.max_per_launch or tiles + need_t > cap
                                or cks + need_c > cap * MAX_SLICES):
+                    if self.fill_first:
+                        break
                     grp.step(launch)
                     launch, tiles, cks = [], 0, 0
                 it, b, slot, last = r.next_step(now)
@@ -363,11 +373,68 @@ def run_fifo(requests: List[ReconRequest], device="cuda", clock=time.perf_counte
     return results
 
 
+def simulate_patterns(req: ReconRequest, obj: np.ndarray, device="cuda") -> np.ndarray:
+    """Poisson counts of the forward model's intensities (computed by the
+    library on the device) at the request's probe and positions and the object
+    `obj`, drawn on the host from the request's seed: patterns a
+    reconstruction can be scored against."""
+    dev = torch.device(device)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)  # noqa: E731
+    # positions per forward call: a context's workspace stays near 2 GiB
+    chunk = int(max(1, min(req.J, (2 << 30) // (req.M * req.N * req.N * 8 * (req.S + 2)))))
+    prob = api.Problem(req.N, req.M, req.S, req.H, req.W, req.J, dz=req.dz, dx=req.dx,
+                       wavelength=req.wavelength, loss=req.loss, eps=req.eps, max_batch=chunk)
+    P, O, X = t(req.probe, np.complex64), t(obj, np.complex64), t(req.positions, np.float32)
+    I = np.empty((req.J, req.N, req.N), dtype=np.float64)
+    for a in range(0, req.J, chunk):
+        b = torch.arange(a, min(a + chunk, req.J), dtype=torch.int32, device=dev)
+        Ib, _ = prob.forward(P, O, X, b)
+        I[a:a + len(b)] = Ib.cpu().numpy()
+    prob.check()
+    prob.close()
+    rng = np.random.default_rng(req.seed + 104729)
+    return rng.poisson(np.maximum(I, 0.0)).astype(np.float32)
+
+
+def _scanned(req: ReconRequest):
+    n = np.floor(np.asarray(req.positions, dtype=np.float64) + 0.5).astype(int)
+    y0, x0 = n.min(axis=0)
+    y1, x1 = n.max(axis=0) + req.N
+    return slice(y0, y1), slice(x0, x1)
+
+
+def object_error(obj: np.ndarray, req: ReconRequest) -> float:
+    """Relative distance of a reconstructed object from the request's truth
+    over the region its windows cover: |O - O_true| / |O_true - 1|."""
+    ys, xs = _scanned(req)
+    a = obj[:, ys, xs].astype(np.complex128)
+    b = req.truth[:, ys, xs].astype(np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b - 1.0))
+
+
+def projected_phase_error(obj: np.ndarray, req: ReconRequest) -> float:
+    """Relative distance of the projected phase (sum over slices of arg O,
+    mean removed: the part a thin specimen's data fix, free of how the phase
+    is shared among slices and of a constant offset) from the truth's, over
+    the region the windows cover."""
+    ys, xs = _scanned(req)
+    pa = np.angle(obj[:, ys, xs].astype(np.complex128)).sum(axis=0)
+    pb = np.angle(req.truth[:, ys, xs].astype(np.complex128)).sum(axis=0)
+    pa, pb = pa - pa.mean(), pb - pb.mean()
+    return float(np.linalg.norm(pa - pb) / np.linalg.norm(pb))
+
+
 def make_request_stream(n: int, seed: int = 0, rate_per_s: float = 2.0, n_iters: int = 50,
                         sizes=(64, 128, 192, 256), max_modes: int = 6, max_slices: int = 16,
-                        scans=(16, 64), steps=(4, 8), batch: int = 256) -> List[ReconRequest]:
+                        scans=(16, 64), steps=(4, 8), batch: int = 256, from_model: bool = False,
+                        device="cuda") -> List[ReconRequest]:
     """Poisson arrivals of reconstructions of mixed N, M, S and scan size, each
-    generated from its own seed like the single-reconstruction workloads."""
+    generated from its own seed like the single-reconstruction workloads.
+    With from_model, each request's patterns are Poisson counts of the forward
+    model at its true object (simulate_patterns), the request starts from the
+    vacuum object O = 1 with the true probe, and the truth is kept for
+    object_error; otherwise the patterns are synthetic bright-field disks and
+    the request starts from the true object."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -386,10 +453,15 @@ def make_request_stream(n: int, seed: int = 0, rate_per_s: float = 2.0, n_iters:
         obj = synth.make_object(S, side, side, 0.3 if simple else 0.1, rs)
         pos = synth.make_scan(scan, step, 0.0 if simple else 0.5, rs)
         pats = synth.make_patterns(N, pos.shape[0], dose, rs, pool=64)
-        out.append(ReconRequest(rid=k, N=N, M=M, S=S, probe=probe, obj=obj, positions=pos, patterns=pats,
-                                dz=[2.0] * (S - 1), loss="amplitude" if simple else "poisson",
-                                eps=0.0 if simple else 0.8, n_iters=n_iters,
-                                batch=min(batch, DEFAULT_GROUP_TILES[N] // M), arrival=t, seed=rs))
+        req = ReconRequest(rid=k, N=N, M=M, S=S, probe=probe, obj=obj, positions=pos, patterns=pats,
+                           dz=[2.0] * (S - 1), loss="amplitude" if simple else "poisson",
+                           eps=0.0 if simple else 0.8, n_iters=n_iters,
+                           batch=min(batch, DEFAULT_GROUP_TILES[N] // M), arrival=t, seed=rs)
+        if from_model:
+            req.patterns = simulate_patterns(req, obj, device)
+            req.truth = obj.astype(np.complex64)
+            req.obj = np.ones_like(obj)
+        out.append(req)
     return out
 
 
