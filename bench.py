@@ -274,6 +274,9 @@ def main():
     ms_per_step = t_total * 1000.0 / args.steps
     value = B * args.steps / t_total
     p50, p99 = np.percentile(step_ms, 50), np.percentile(step_ms, 99)
+    # per-epoch timings: n_groups consecutive groups (the whole scan once)
+    n_ep = args.steps // n_groups
+    ep_ms = np.array([starts[e * n_groups].elapsed_time(ends[(e + 1) * n_groups - 1]) for e in range(n_ep)])
 
     # Per-kernel times come from a separate pass over the same groups with
     # every launch bracketed by two HIP events on the stream it runs on (the
@@ -363,6 +366,10 @@ def main():
                    "reduction": args.reduction, "engine": args.engine, "regularizers": bool(args.regularize)},
         "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
         "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
+        "epochs_timed": int(n_ep),
+        "epoch_s_p50": round(float(np.percentile(ep_ms, 50)) / 1000.0, 4) if n_ep else None,
+        "positions_per_s_epoch_p50": round(n_groups * B / (float(np.percentile(ep_ms, 50)) / 1000.0), 1) if n_ep else None,
+        "positions_per_s_epoch_p99": round(n_groups * B / (float(np.percentile(ep_ms, 99)) / 1000.0), 1) if n_ep else None,
         "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),
         "roofline": roof, "step_roofline": step_roof, "kernels": kernels,
         "profiled_pass_ms_per_step": round(prof_ms_per_step, 3) if prof_ms_per_step else None,

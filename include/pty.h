@@ -237,7 +237,8 @@ pty_status pty_forward(pty_ctx* ctx, void* stream, const pty_c64* probe, const p
  * in the same call. Every call on a GPU shares that GPU's array and leaves
  * its contents behind: calls that overlap on one GPU (other streams, threads
  * or contexts) race and must be serialised by the caller. Calls no
- * allocation routine. */
+ * allocation routine (only per-launch timing, when pty_profile_enable turns
+ * it on, creates HIP events). */
 pty_status pty_forward_static(pty_ctx* ctx, void* stream, const pty_c64* probe, const pty_c64* object,
                               const float* positions, const int32_t* batch_idx, int32_t batch,
                               const float* patterns, float* intensities, double* loss);
