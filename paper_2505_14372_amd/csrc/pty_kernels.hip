@@ -110,6 +110,51 @@ __device__ __forceinline__ void load_row_masked(float2 (&v)[Cfg<N>::E], const fl
   }
 }
 
+// The slots set in `mask` of any lane of the wave, as a wave-uniform value:
+// the L lanes of a line hold every column residue, and every line of a wave
+// has the same residues, so an OR over the L lanes of one line suffices.
+template <int N>
+__device__ __forceinline__ unsigned wave_slots(unsigned mask) {
+#pragma unroll
+  for (int off = 1; off < Cfg<N>::L; off <<= 1) mask |= (unsigned)__shfl_xor((int)mask, off);
+  return __builtin_amdgcn_readfirstlane(mask);
+}
+
+// Row-pass load of x[l + L a] for the register slots a set in `mask`, zero in
+// the others. `any` (wave_slots(mask)) is uniform, so a slot no lane of the
+// wave needs is skipped by a scalar branch and costs no request; the other
+// slots are read by every lane from one base address with immediate offsets
+// (no per-slot address registers), and the lanes whose slot is dead take zero.
+// Dead columns of the tiles are never written, so what a dead lane reads is
+// discarded, never used.
+template <int N>
+__device__ __forceinline__ void load_row_slots(float2 (&v)[Cfg<N>::E], const float2* row, int l, unsigned mask,
+                                               unsigned any) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
+  const float2* p = row + l;
+#pragma unroll
+  for (int a = 0; a < E; ++a) {
+    v[a] = make_float2(0.f, 0.f);
+    if ((any >> a) & 1u) v[a] = p[L * a];
+  }
+  const unsigned part = any & ~mask;
+#pragma unroll
+  for (int a = 0; a < E; ++a)
+    if ((part >> a) & 1u) v[a] = make_float2(0.f, 0.f);
+}
+
+// Row-pass store of the slots set in `any` (wave-uniform): every lane of a
+// live slot stores, also a lane whose column is dead, since no consumer reads
+// dead columns.
+template <int N>
+__device__ __forceinline__ void store_row_slots(const float2 (&v)[Cfg<N>::E], float2* row, int l, unsigned any) {
+  constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
+  float2* p = row + l;
+#pragma unroll
+  for (int a = 0; a < E; ++a)
+    if ((any >> a) & 1u) p[L * a] = v[a];
+}
+
 // byte offset of element (y, x) of an N x N tile, or kOff when the lane is masked off
 template <int N>
 __device__ __forceinline__ unsigned tile_off(bool on, int y, int x) {
@@ -207,6 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
   // the output of slices i < S - 1 feeds only the propagation column pass,
   // which reads the live columns alone
   const unsigned omask = i < r.S - 1 ? live : ~0u;
+  const unsigned any_l = wave_slots<N>(lmask), any_o = wave_slots<N>(omask);
   // object patch row, shared by every mode
   float2 o[E];
   const float2* orow = r.obj + ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
@@ -217,18 +263,11 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) pw[a] = 0.f;
   }
-  // Each mode's output row is stored after the next mode's input requests:
-  // vector-memory operations complete in issue order, so a wait for loads
-  // issued after the stores would also wait for the stores to be acknowledged.
-  float2 vout[E];
-  float2* out_row = nullptr;
-  auto flush = [&]() {
-    if (!out_row) return;
-#pragma unroll
-    for (int a = 0; a < E; ++a)
-      if ((omask >> a) & 1u) out_row[l + L * a] = vout[a];
-    out_row = nullptr;
-  };
+  // Each mode's output row is stored as soon as it is transformed: with the
+  // masked loads and stores in load_row_slots / store_row_slots the pass
+  // holds few enough registers for three waves per SIMD at N = 256, which
+  // hides the memory latency better than deferring the stores behind the
+  // next mode's requests at two waves.
   for (int m = 0; m < r.M; ++m) {
     float2* trow = ws + ((size_t)(it.tile0 + m) * N + y) * N;
     float2 v[E];
@@ -236,7 +275,6 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
       const CT* src = static_cast<const CT*>(store.src) + (ck_tile(it, r, m, store.src_slot) * N + y) * N;
 #pragma unroll
       for (int a = 0; a < E; ++a) v[a] = Ck<HALF>::load(src + l + L * a);
-      flush();
     } else {
       // the row spectrum comes from the work tile or, with spectral
       // checkpoints, from where the column pass left it: checkpoint slot
@@ -250,9 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
           in = static_cast<const float2*>(store.seg) +
                (((size_t)(it.tile0 + m) * store.seg_len + store.seg_slot) * N + y) * N;
       }
-#pragma unroll
-      for (int a = 0; a < E; ++a) v[a] = (lmask >> a) & 1u ? in[l + L * a] : make_float2(0.f, 0.f);
-      flush();
+      load_row_slots<N>(v, in, l, lmask, any_l);
       line_fft<N, true>(v, l, tw, sx, WaveSync{});
     }
     if (store.mode == 1 && (i % r.ck_every) == 0) {
@@ -272,11 +308,8 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) v[a] = cmul(v[a], o[a]);
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
-#pragma unroll
-    for (int a = 0; a < E; ++a) vout[a] = v[a];
-    out_row = trow;
+    store_row_slots<N>(v, trow, l, any_o);
   }
-  flush();
   if constexpr (EMAX) {
     float mp = 0.f, mo = 0.f;
 #pragma unroll
