@@ -976,8 +976,10 @@ void apply_optimizer(pty_ctx* c, hipStream_t s, pty_state* st, const pty_optim* 
 namespace {
 
 // Cost regularizers: gradients into the dense gradients, cost added to *loss.
-void apply_cost_regularizers(pty_ctx* c, hipStream_t s, const pty_state* st, double* loss) {
-  if (!c->reg_on) return;
+// Fails (PTY_EHIP, message in c->err) when the copy or a hipFFT transform of
+// the spectral term is refused.
+pty_status apply_cost_regularizers(pty_ctx* c, hipStream_t s, const pty_state* st, double* loss) {
+  if (!c->reg_on) return PTY_OK;
   const pty_geometry& g = c->g;
   int nb = 0;
   if (c->rg.obj_l2 != 0.f || c->rg.obj_l1 != 0.f || c->rg.obj_tikhonov != 0.f || c->rg.obj_tv != 0.f ||
@@ -992,11 +994,19 @@ void apply_cost_regularizers(pty_ctx* c, hipStream_t s, const pty_state* st, dou
     // |F2 O|: forward FFT of a copy of the slices, the L1 step, inverse FFT,
     // added into the object gradient (every transform in place, one plan)
     const size_t HW = (size_t)g.obj_h * g.obj_w, n = HW * g.n_slices;
-    (void)hipMemcpyAsync(c->spec, st->object, n * sizeof(float2), hipMemcpyDeviceToDevice, s);
-    (void)hipfftSetStream(c->spec_plan, s);
-    (void)hipfftExecC2C(c->spec_plan, (hipfftComplex*)c->spec, (hipfftComplex*)c->spec, HIPFFT_FORWARD);
+    HIPCHECK(c, hipMemcpyAsync(c->spec, st->object, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    if (hipfftSetStream(c->spec_plan, s) != HIPFFT_SUCCESS ||
+        hipfftExecC2C(c->spec_plan, (hipfftComplex*)c->spec, (hipfftComplex*)c->spec, HIPFFT_FORWARD) !=
+            HIPFFT_SUCCESS) {
+      c->err = "hipFFT forward transform of the object spectrum failed";
+      return PTY_EHIP;
+    }
     ns = launch_spec_l1(s, c->spec, n, HW, c->obj_spec_l1, c->reg_part + 3 * 4096);
-    (void)hipfftExecC2C(c->spec_plan, (hipfftComplex*)c->spec, (hipfftComplex*)c->spec, HIPFFT_BACKWARD);
+    if (hipfftExecC2C(c->spec_plan, (hipfftComplex*)c->spec, (hipfftComplex*)c->spec, HIPFFT_BACKWARD) !=
+        HIPFFT_SUCCESS) {
+      c->err = "hipFFT inverse transform of the object spectrum failed";
+      return PTY_EHIP;
+    }
     launch_cadd_inplace(s, c->gobj, c->spec, n);
   }
   int nq = 0;
@@ -1015,6 +1025,7 @@ void apply_cost_regularizers(pty_ctx* c, hipStream_t s, const pty_state* st, dou
     if (nq) launch_add_cost(s, c->reg_part + 8192, nq, loss);
     if (ns) launch_add_cost(s, c->reg_part + 3 * 4096, ns, loss);
   }
+  return PTY_OK;
 }
 
 // Constraint regularizers on the updated state.
@@ -1190,7 +1201,11 @@ extern "C" pty_status pty_reconstruct_step(pty_ctx* c, void* stream, pty_state* 
     HIPCHECK(c, hipGetLastError());
     return PTY_OK;
   }
-  { ProfScope p(P_REG, s); apply_cost_regularizers(c, s, st, loss); }
+  {
+    ProfScope p(P_REG, s);
+    const pty_status rs = apply_cost_regularizers(c, s, st, loss);
+    if (rs != PTY_OK) return rs;
+  }
   apply_optimizer(c, s, st, o);
   { ProfScope p(P_REG, s); apply_constraints(c, s, st); }
   HIPCHECK(c, hipGetLastError());
@@ -1422,7 +1437,10 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   for (int q = 0; q < n; ++q) {
     pty_ctx* c = items[q].ctx;
     launch_plain2d(N, s, G->tw, c->gphat, c->gprobe, c->g.n_modes, true, 1.f / N, false);
-    apply_cost_regularizers(c, s, items[q].state, items[q].loss);
+    if (apply_cost_regularizers(c, s, items[q].state, items[q].loss) != PTY_OK) {
+      G->err = c->err;
+      return PTY_EHIP;
+    }
     apply_optimizer(c, s, items[q].state, items[q].opt);
     apply_constraints(c, s, items[q].state);
   }
