@@ -308,7 +308,15 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
 #pragma unroll
     for (int a = 0; a < E; ++a) v[a] = cmul(v[a], o[a]);
     line_fft<N, false>(v, l, tw, sx, WaveSync{});
-    store_row_slots<N>(v, trow, l, any_o);
+    // With spectral checkpoints the output of a slice whose successor is
+    // stored goes straight into that successor's checkpoint slot, where the
+    // column pass completes it in place (a column pass that writes where it
+    // read runs faster than one writing lines nothing has touched lately; the
+    // row pass pays less for such writes).
+    float2* out = trow;
+    if (store.mode == 3 && i + 1 < r.S && (i + 1) % r.ck_every == 0)
+      out = static_cast<float2*>(ck_) + (ck_tile(it, r, m, (i + 1) / r.ck_every) * N + y) * N;
+    store_row_slots<N>(v, out, l, any_o);
   }
   if constexpr (EMAX) {
     float mp = 0.f, mo = 0.f;
@@ -583,6 +591,11 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   const int ux = cb * CB + c;
   float2* sx = xch + c * ColMap<N>::STRIDE;
   float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
+  // a forward propagation whose output is a stored checkpoint runs in place
+  // in that slot, where the forward row pass left its input
+  if constexpr (OP == COL_PROP) {
+    if (ck_out && (i + 1) % r.ck_every == 0) tile = ck_out + ck_tile(it, r, m, (i + 1) / r.ck_every) * N * N;
+  }
   const bool live_col = PROP ? col_live<N>(r, ux) : true;
   // Memory requests in the order they are needed, all before the first wait:
   // the staged tables (twiddles; the y factors and row limits of a separable
@@ -677,8 +690,8 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   }
   // spectral checkpoints: the row spectrum of the entry wave of slice s1 (0
   // for COL_SHIFT, i + 1 for COL_PROP) goes to checkpoint slot s1 / ck_every
-  // when that slice is stored, to its segment slot while a segment is being
-  // recomputed, else to the work tile
+  // when that slice is stored (for COL_PROP the slot it was read from), to its
+  // segment slot while a segment is being recomputed, else to the work tile
   float2* dst = tile;
   if constexpr (OP == COL_SHIFT || OP == COL_PROP) {
     if (ck_out) {
