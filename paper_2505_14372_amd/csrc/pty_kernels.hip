@@ -1327,19 +1327,22 @@ __global__ void k_reg_object(const float2* __restrict__ O, float2* __restrict__ 
       cost += rg.obj_l2 * cabs2(d);
     }
     if (rg.obj_l1 != 0.f) {
+      // the unit vector (O - 1) / |O - 1|, formed without squaring (no underflow)
       float2 d = make_float2(o.x - 1.f, o.y);
-      float a = sqrtf(cabs2(d));
-      if (a > 0.f) gr = cadd(gr, cscale(d, rg.obj_l1 / a));
+      float a = hypotf(d.x, d.y);
+      if (a > 0.f) gr = cadd(gr, cscale(make_float2(d.x / a, d.y / a), rg.obj_l1));
       cost += rg.obj_l1 * a;
     }
     if (rg.obj_phase_l1 != 0.f) {
-      // |arg O|: d arg O / d(Re, Im), combined as dRe + i dIm, is i O / |O|^2
+      // |arg O|: d arg O / d(Re, Im), combined as dRe + i dIm, is i O / |O|^2,
+      // formed as (i O / |O|) / |O| so that it overflows only where its value
+      // exceeds the float range (|O|^2 itself underflows much earlier)
       const float ph = atan2f(o.y, o.x);
-      const float a2 = cabs2(o);
+      const float a = hypotf(o.x, o.y);
       cost += rg.obj_phase_l1 * fabsf(ph);
-      if (ph != 0.f && a2 > 0.f) {
-        const float sc = (ph > 0.f ? rg.obj_phase_l1 : -rg.obj_phase_l1) / a2;
-        gr = cadd(gr, make_float2(-o.y * sc, o.x * sc));
+      if (ph != 0.f && a > 0.f) {
+        const float sc = (ph > 0.f ? rg.obj_phase_l1 : -rg.obj_phase_l1) / a;
+        gr = cadd(gr, make_float2(-(o.y / a) * sc, (o.x / a) * sc));
       }
     }
     const bool in_tik = rg.obj_tikhonov != 0.f, in_tv = rg.obj_tv != 0.f;
@@ -1410,9 +1413,9 @@ __global__ void k_reg_probe(const float2* __restrict__ P, float2* __restrict__ g
 // of its (up to four) pairs into gphat and counts the cost of the pairs where
 // it is the upper element, so each pair is counted once.
 __device__ __forceinline__ float2 phase_pair_grad(float2 z, float wt, float wv, float d2, float& cost) {
-  const float r = sqrtf(cabs2(z));
+  const float r = hypotf(z.x, z.y);
   const float t = atan2f(z.y, z.x);
-  const float2 e = r > 0.f ? cscale(z, 1.f / r) : make_float2(1.f, 0.f);
+  const float2 e = r > 0.f ? make_float2(z.x / r, z.y / r) : make_float2(1.f, 0.f);
   float2 G = make_float2(0.f, 0.f);
   if (wt != 0.f) {
     cost += wt * r * t * t;
@@ -1482,11 +1485,11 @@ __global__ void k_spec_l1(float2* __restrict__ spec, size_t n, size_t HW, float 
   float cost = 0.f;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     const float2 F = cscale(spec[e], inv_sqrt);
-    const float a = sqrtf(cabs2(F));
+    const float a = hypotf(F.x, F.y);
     float2 g = make_float2(0.f, 0.f);
     if (e % HW != 0 && a > 0.f) {
       cost += w * a;
-      g = cscale(F, w * inv_sqrt / a);
+      g = cscale(make_float2(F.x / a, F.y / a), w * inv_sqrt);
     }
     spec[e] = g;
   }
@@ -1525,9 +1528,9 @@ __global__ void k_add_cost(const float* __restrict__ part, int n, double* __rest
 __global__ void k_amp_clamp(float2* __restrict__ O, size_t n, float lo, float hi) {
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     float2 o = O[e];
-    float a = sqrtf(cabs2(o));
+    float a = hypotf(o.x, o.y);
     float c = fminf(fmaxf(a, lo), hi);
-    O[e] = a > 0.f ? cscale(o, c / a) : make_float2(c, 0.f);
+    O[e] = a > 0.f ? cscale(make_float2(o.x / a, o.y / a), c) : make_float2(c, 0.f);
   }
 }
 

@@ -833,6 +833,62 @@ def test_phase_regularizers_match_oracle():
     assert np.all(_np(st.probe)[:, ~mask_r] == 0)
 
 
+def test_tiny_object_pixels_keep_finite_gradients_and_phases():
+    """Object pixels of amplitude 1e-20 and 1e-24, where |O|^2 underflows in
+    float: the object-phase L1 and L1 gradients (w i O / |O|^2 and
+    w (O - 1) / |O - 1|, Sec. 3.4) stay finite and match the oracle's FP64
+    values, and the amplitude clamp keeps each pixel's phase."""
+    from paper_2505_14372_amd import api
+    wl = synth.make_small(N=64, M=1, S=2, scan=2, step=4, seed=35, loss="gaussian", amp_noise=0.2)
+    c = Case(wl)
+    rng = np.random.default_rng(35)
+    ys, xs = rng.integers(0, c.H, 12), rng.integers(0, c.W, 12)
+    amp = np.where(np.arange(12) % 2 == 0, 1e-20, 1e-24)
+    ph = rng.uniform(-3.0, 3.0, 12)
+    c.obj[0, ys, xs] = (amp * np.exp(1j * ph)).astype(np.complex64)
+    d = c.device()
+    P0, O0, X0 = c.o_args()
+    b = [0, 1, 2, 3]
+    bt = torch.tensor(b, dtype=torch.int32, device="cuda")
+    # (1) the phase L1 and L1 gradients at the tiny pixels: one SGD step
+    prob = c.problem(max_batch=4)
+    reg = dict(obj_phase_l1=0.5, obj_l1=0.25)
+    prob.set_regularizers(**reg)
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    lr = 1e-3
+    prob.reconstruct_step(st, d["pats"], bt, api.Optimizer(kind="sgd", lr_object=lr, lr_probe=0.0, lr_pos=0.0))
+    prob.check()
+    ost, _ = orc.reconstruct_step(dict(probe=P0, object=O0, positions=X0), c.pats.astype(np.float64), b, c.geom,
+                                  dict(kind="sgd", lr_object=lr, lr_probe=0.0, lr_pos=0.0, reg=reg))
+    got = _np(st.object).astype(np.complex128)
+    want = ost["object"]
+    assert np.all(np.isfinite(got))
+    tiny = got[0, ys, xs], want[0, ys, xs]
+    print("tiny pixels after the step", np.abs(tiny[0]).max(), max_rel(tiny[0], tiny[1]))
+    assert np.abs(tiny[1]).min() > 1e14          # the phase-L1 step w lr / |O| dominates there
+    assert max_rel(tiny[0], tiny[1]) < 1e-5
+    rest = np.ones(got.shape, bool)
+    rest[0, ys, xs] = False
+    du_g, du_w = got[rest] - O0[rest], want[rest] - O0[rest]
+    res = np.linalg.norm(np.spacing(_real_components(want[rest]).astype(np.float32)).astype(np.float64))
+    assert np.linalg.norm(_real_components(du_g - du_w)) <= TOL_G * np.linalg.norm(_real_components(du_w)) + res
+    prob.close()
+    # (2) the amplitude clamp alone (no update): the tiny pixels become amp_min with their phase
+    prob = c.problem(max_batch=4)
+    prob.set_regularizers(amp_range=(0.5, 2.0))
+    st = api.ReconState(d["probe"].clone(), d["obj"].clone(), d["pos"].clone(), adam=False)
+    prob.reconstruct_step(st, d["pats"], bt, api.Optimizer(kind="sgd", lr_object=0.0, lr_probe=0.0, lr_pos=0.0))
+    prob.check()
+    ost, _ = orc.reconstruct_step(dict(probe=P0, object=O0, positions=X0), c.pats.astype(np.float64), b, c.geom,
+                                  dict(kind="sgd", lr_object=0.0, lr_probe=0.0, lr_pos=0.0,
+                                       con=dict(amp_min=0.5, amp_max=2.0)))
+    got = _np(st.object).astype(np.complex128)
+    assert max_rel(got, ost["object"]) < 1e-6
+    assert np.allclose(got[0, ys, xs], 0.5 * np.exp(1j * np.angle(c.obj[0, ys, xs].astype(np.complex128))),
+                       rtol=0, atol=1e-6)
+    prob.close()
+
+
 def test_object_spectrum_l1_matches_oracle():
     """reconstruct_step with the object spectral L1 (Sec. 3.4) on a non-square
     object whose sides (76 x 97) are not powers of two: loss to 1e-4 and the
