@@ -19,6 +19,12 @@ Prints one JSON line. The headline is the default: Adam, float32
 checkpoints, no regularizers; the other options measure the conventional
 engines, the regularizers and the storage and schedule variants on the
 same workload.
+
+Kernel timing: the last warmup step times every kernel class once (HIP events
+around each launch, on its own stream) to name the dominant kernel; the timed
+steps then time that class's launches alone, which gives the roofline's
+average launch duration; a separate pass after the timed region gives the
+per-class breakdown.
 """
 from __future__ import annotations
 
@@ -59,7 +65,8 @@ def parse():
     p.add_argument("--streams", type=int, default=1,
                    help="run the chunks of a chunked schedule concurrently on this many streams")
     p.add_argument("--profile-steps", type=int, default=4,
-                   help="steps of the separate per-kernel timing pass after the timed region (0: none)")
+                   help="steps of the separate per-kernel timing pass after the timed region; with 0 no "
+                        "kernel is timed at all, also not the dominant one inside the timed steps")
     p.add_argument("--strategy", default="auto", choices=["auto", "two_pass", "resident"])
     p.add_argument("--reduction", default="auto", choices=["auto", "atomic", "ordered"],
                    help="object-gradient accumulation: float atomics or the bit-reproducible ordered sum; "
@@ -250,15 +257,48 @@ def main():
     batches = [next(gen) for _ in range(args.warmup + args.steps)]
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    lib = _lib.load()
+    n_prof = min(args.profile_steps, args.steps)
+
+    def collect():
+        names = C.create_string_buffer(4096)
+        tot = (C.c_double * 64)()
+        cnt = (C.c_int64 * 64)()
+        n_cls = lib.pty_profile_collect(names, 4096, tot, cnt, 64)
+        return {nm: (tot[i], cnt[i]) for i, nm in enumerate(names.value.decode().split("\n")[:n_cls])}
+
+    def dominant(classes):
+        # the single-kernel class with the most time ("recompute" times a whole
+        # segment's row and column passes together, so it has no per-launch model)
+        cand = [k for k in classes if k != "recompute" and classes[k][1] > 0]
+        return max(cand, key=lambda k: classes[k][0]) if cand else None
+
+    dom = None
     for w in range(args.warmup):
+        # the last warmup step times every kernel class once, to name the
+        # dominant kernel whose launches the timed steps then time
+        probe_step = n_prof > 0 and w == args.warmup - 1
+        if probe_step:
+            lib.pty_profile_select(None)
+            lib.pty_profile_enable(1)
+            collect()
         step(batches[w], loss)
+        if probe_step:
+            lib.pty_profile_enable(0)
+            dom = dominant(collect())
         print(f"[bench] warmup step {w} done", file=sys.stderr, flush=True)
     prob.check()
     torch.cuda.synchronize()
 
-    lib = _lib.load()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    if dom:
+        # every launch of the dominant kernel class in the timed steps is
+        # bracketed by two HIP events on the stream it runs on (no other class)
+        if lib.pty_profile_select(dom.encode()) != 1:
+            raise RuntimeError(f"unknown kernel class {dom}")
+        lib.pty_profile_enable(1)
+        collect()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -269,6 +309,11 @@ def main():
             print(f"[bench] timed step {k + 1}/{args.steps} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    dom_timed = None
+    if dom:
+        lib.pty_profile_enable(0)
+        lib.pty_profile_select(None)
+        dom_timed = collect().get(dom)
     prob.check()
     step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ms_per_step = t_total * 1000.0 / args.steps
@@ -278,15 +323,13 @@ def main():
     n_ep = args.steps // n_groups
     ep_ms = np.array([starts[e * n_groups].elapsed_time(ends[(e + 1) * n_groups - 1]) for e in range(n_ep)])
 
-    # Per-kernel times come from a separate pass over the same groups with
-    # every launch bracketed by two HIP events on the stream it runs on (the
-    # events are kept out of the timed region above).
+    # The per-class breakdown comes from a separate pass over the same groups
+    # with every launch of every class bracketed by two HIP events.
     prof = {}
     prof_ms_per_step = None
-    n_prof = min(args.profile_steps, args.steps)
     if n_prof > 0:
         lib.pty_profile_enable(1)
-        lib.pty_profile_collect(None, 0, None, None, 0)   # drop anything recorded before
+        collect()   # drop anything recorded before
         torch.cuda.synchronize()
         t_p = time.perf_counter()
         for k in range(n_prof):
@@ -294,12 +337,7 @@ def main():
         torch.cuda.synchronize()
         prof_ms_per_step = (time.perf_counter() - t_p) * 1000.0 / n_prof
         lib.pty_profile_enable(0)
-        names = C.create_string_buffer(4096)
-        tot = (C.c_double * 64)()
-        cnt = (C.c_int64 * 64)()
-        n_cls = lib.pty_profile_collect(names, 4096, tot, cnt, 64)
-        prof = {nm: (tot[i] / n_prof, cnt[i] / n_prof)
-                for i, nm in enumerate(names.value.decode().split("\n")[:n_cls])}
+        prof = {nm: (v[0] / n_prof, v[1] / n_prof) for nm, v in collect().items()}
         prob.check()
         print(f"[bench] profiled pass: {n_prof} steps, {prof_ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
@@ -322,11 +360,15 @@ def main():
     roof = None
     kernels = {}
     if prof:
-        # dominant single-kernel class ("recompute" times a whole segment's row
-        # and column passes together, so it has no per-launch model)
-        dom = max((k for k in prof if k != "recompute" and prof[k][1] > 0), key=lambda k: prof[k][0])
-        dom_ms, dom_n = prof[dom]
-        avg_s = dom_ms / dom_n / 1000.0
+        # the dominant kernel's average launch time over the timed steps (from
+        # the separate pass only when no warmup step could name it first)
+        if dom_timed and dom_timed[1] > 0:
+            avg_s = dom_timed[0] / dom_timed[1] / 1000.0
+            avg_src = "timed steps"
+        else:
+            dom = dominant(prof)
+            avg_s = prof[dom][0] / prof[dom][1] / 1000.0
+            avg_src = "separate pass"
         spectral = not prob.checkpoint_half and args.strategy != "resident"
         live = live_fraction(N, wl.bandlimit, S)
         n_launch = B if args.chunk <= 0 else min(args.chunk, B)   # positions one launch processes
@@ -348,6 +390,8 @@ def main():
                        args.strategy != "resident" and args.chunk == 0 and args.reduction == "atomic")
         traffic = measured_traffic(dom) if default_cfg else None
         roof.update({"traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_s * 1000, 4),
+                     "avg_launch_from": avg_src,
+                     "launches_timed": int(dom_timed[1]) if dom_timed and avg_src == "timed steps" else None,
                      "positions_per_launch": n_launch, "algorithmic_flops": alg_flops,
                      "algorithmic_bytes": alg_bytes, "achieved_alg_GBps": round(gbs, 1),
                      "design_bytes": design_bytes, "stream_GBps": round(design_bytes / avg_s / 1e9, 1)})

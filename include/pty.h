@@ -454,6 +454,10 @@ void pty_group_destroy(pty_group* grp);
  * separated by '\n' into names, total milliseconds and launch counts) and
  * resets the totals; it returns the number of classes written. */
 void pty_profile_enable(int32_t on);
+/* Restricts the timing to the named classes (comma- or newline-separated,
+ * e.g. "row_adj"); NULL or "" selects every class (the default). Returns the
+ * number of classes selected, or -1 (selection unchanged) for an unknown name. */
+int32_t pty_profile_select(const char* classes);
 int32_t pty_profile_collect(char* names, size_t names_len, double* total_ms, int64_t* counts,
                             int32_t max_entries);
 

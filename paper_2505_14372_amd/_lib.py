@@ -28,7 +28,7 @@ EXPORTS = (
     "pty_checkpoint_half", "pty_set_chunk", "pty_forward", "pty_loss_and_grad",
     "pty_forward_save", "pty_backward", "pty_reconstruct_step", "pty_check", "pty_last_error",
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
-    "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_collect",
+    "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_select", "pty_profile_collect",
     "pty_set_regularizers", "pty_set_strategy", "pty_set_reduction", "pty_lsqml_step", "pty_set_streams",
     "pty_backward_dev", "pty_forward_static",
 )
@@ -133,6 +133,7 @@ def load():
         "pty_group_last_error": ([vp], C.c_char_p),
         "pty_group_destroy": ([vp], None),
         "pty_profile_enable": ([i32], None),
+        "pty_profile_select": ([C.c_char_p], i32),
         "pty_set_regularizers": ([vp, C.POINTER(Regularizers)], i32),
         "pty_set_strategy": ([vp, i32], i32),
         "pty_set_reduction": ([vp, i32], i32),

@@ -173,6 +173,7 @@ struct ProfRec { int cls; hipEvent_t a, b; };
 struct Profiler {
   std::mutex mu;
   bool on = false;
+  uint64_t mask = ~0ull;     // classes timed while on (pty_profile_select)
   std::vector<ProfRec> pending;
   std::vector<hipEvent_t> pool;
   double total_ms[P_NCLASS] = {};
@@ -191,7 +192,7 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t a = nullptr;
   ProfScope(int c, hipStream_t st) : cls(c), s(st) {
-    if (!g_prof.on) return;
+    if (!g_prof.on || !((g_prof.mask >> c) & 1ull)) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     a = g_prof.get();
     if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
@@ -1454,6 +1455,35 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
 extern "C" void pty_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = on != 0;
+}
+
+extern "C" int32_t pty_profile_select(const char* classes) {
+  static_assert(P_NCLASS <= 64, "class mask holds 64 classes");
+  uint64_t mask = 0;
+  int n = 0;
+  if (!classes || !*classes) {
+    mask = ~0ull;
+    n = P_NCLASS;
+  } else {
+    std::string all(classes);
+    size_t b = 0;
+    while (b <= all.size()) {
+      size_t e = all.find_first_of(",\n", b);
+      if (e == std::string::npos) e = all.size();
+      const std::string name = all.substr(b, e - b);
+      if (!name.empty()) {
+        int k = 0;
+        while (k < P_NCLASS && name != kProfNames[k]) ++k;
+        if (k == P_NCLASS) return -1;
+        if (!((mask >> k) & 1ull)) ++n;
+        mask |= 1ull << k;
+      }
+      b = e + 1;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.mask = mask;
+  return n;
 }
 
 extern "C" int32_t pty_profile_collect(char* names, size_t names_len, double* total_ms, int64_t* counts,

@@ -90,6 +90,17 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.pty_set_chunk(None, 4) == _lib.PTY_EINVAL
 
 
+def test_profile_class_selection(lib):
+    """pty_profile_select names kernel classes (host only: no event is recorded
+    while timing is off)."""
+    assert lib.pty_profile_select(b"row_adj") == 1
+    assert lib.pty_profile_select(b"row_adj,col_prop\nrow_adj") == 2
+    assert lib.pty_profile_select(b"no_such_kernel") == -1
+    assert lib.pty_profile_select(b"row_fwd,no_such_kernel") == -1
+    n_all = lib.pty_profile_select(None)
+    assert n_all >= 19 and lib.pty_profile_select(b"") == n_all
+
+
 @pytest.mark.parametrize("prog", ["line_fft_check", "resident_check"])
 def test_host_fft_emulation(tmp_path, prog):
     """The cross-lane line FFT of the kernels (and the in-place 2D transform of
