@@ -20,11 +20,12 @@ checkpoints, no regularizers; the other options measure the conventional
 engines, the regularizers and the storage and schedule variants on the
 same workload.
 
-Kernel timing: the last warmup step times every kernel class once (HIP events
-around each launch, on its own stream) to name the dominant kernel; the timed
-steps then time that class's launches alone, which gives the roofline's
-average launch duration; a separate pass after the timed region gives the
-per-class breakdown.
+Timing: by default 64 warmup groups (2 epochs) and 640 timed groups (20
+epochs); per-group and per-epoch p50/p99 from HIP events. The last warmup step
+times every kernel class once (HIP events around each launch, on its own
+stream) to name the dominant kernel; the first 64 timed steps then time that
+class's launches alone, which gives the roofline's average launch duration; a
+separate pass after the timed region gives the per-class breakdown.
 """
 from __future__ import annotations
 
@@ -53,8 +54,9 @@ ENGINES = {"adam": "Adam", "sgd": "SGD", "epie": "ePIE", "lsqml": "LSQML",
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=32)
-    p.add_argument("--warmup", type=int, default=3)
+    # default: 2 epochs of warmup, 20 timed epochs of the 256^2 workload (32 groups each)
+    p.add_argument("--steps", type=int, default=640)
+    p.add_argument("--warmup", type=int, default=64)
     p.add_argument("--batch", type=int, default=0, help="positions per group (0: the workload's)")
     p.add_argument("--workload", default="ms256_m8_s30")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -170,6 +172,9 @@ def method_bytes_per_launch(name, N, B):
 # becomes bit-identical to its one-at-a-time run.
 FASTER_REDUCTION = {"ms256_m8_s30": "atomic", "ms192_m6_s20": "ordered", "ms128_m4_s8": "ordered",
                     "spoa64": "atomic", "serving": "ordered"}
+
+
+DOM_STEPS = 64   # timed steps whose dominant-kernel launches are bracketed by events
 
 
 def main():
@@ -292,9 +297,11 @@ def main():
 
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    # every launch of the dominant kernel class in the first DOM_STEPS timed
+    # steps is bracketed by two HIP events on the stream it runs on (no other
+    # class; the cap bounds the number of events held until they are read)
+    dom_steps = min(args.steps, DOM_STEPS) if dom else 0
     if dom:
-        # every launch of the dominant kernel class in the timed steps is
-        # bracketed by two HIP events on the stream it runs on (no other class)
         if lib.pty_profile_select(dom.encode()) != 1:
             raise RuntimeError(f"unknown kernel class {dom}")
         lib.pty_profile_enable(1)
@@ -305,13 +312,14 @@ def main():
         starts[k].record(stream)
         step(batches[args.warmup + k], loss)
         ends[k].record(stream)
-        if (k + 1) % 8 == 0:
+        if k + 1 == dom_steps:
+            lib.pty_profile_enable(0)
+        if (k + 1) % 32 == 0 or k + 1 == args.steps:
             print(f"[bench] timed step {k + 1}/{args.steps} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     dom_timed = None
     if dom:
-        lib.pty_profile_enable(0)
         lib.pty_profile_select(None)
         dom_timed = collect().get(dom)
     prob.check()
