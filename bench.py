@@ -7,7 +7,7 @@ probe and positions, Adam step) on the 256 x 256, 8-mode, 30-slice workload.
                     [--workload ms256_m8_s30|ms192_m6_s20|ms128_m4_s8|spoa64|serving]
                     [--engine adam|sgd|epie|lsqml|grad] [--regularize]
                     [--checkpoint-every k] [--checkpoint-half] [--strategy ...] [--chunk n] [--streams k]
-                    [--profile-steps n]
+                    [--profile-steps n] [--graph]
                     [--reduction auto|atomic|ordered]
 
 A step is one reconstruct_step over one group of `batch` positions drawn
@@ -66,6 +66,8 @@ def parse():
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--streams", type=int, default=1,
                    help="run the chunks of a chunked schedule concurrently on this many streams")
+    p.add_argument("--graph", action="store_true",
+                   help="record the step once as a HIP graph and replay it (launch-bound workloads)")
     p.add_argument("--profile-steps", type=int, default=4,
                    help="steps of the separate per-kernel timing pass after the timed region; with 0 no "
                         "kernel is timed at all, also not the dominant one inside the timed steps")
@@ -226,7 +228,9 @@ def main():
                               layers_tikhonov=1e-2, layers_tv=1e-2, tv_delta=1e-2, amp_range=(0.0, 1.0),
                               probe_support=(k[:, None] ** 2 + k[None, :] ** 2) <= (N / 3) ** 2, layer_sigma=0.5,
                               obj_lowpass_sigma=0.5, phase_deramp=True)
-    state = api.ReconState(probe, obj, pos, adam=args.engine == "adam")
+    if args.graph and args.engine not in ("adam", "sgd", "epie"):
+        raise SystemExit("--graph records reconstruct_step (engines adam, sgd, epie)")
+    state = api.ReconState(probe, obj, pos, adam=args.engine == "adam", device_step=args.graph)
     rng = np.random.default_rng(12345)
     n_groups = J // B
     if args.engine == "lsqml":
@@ -251,6 +255,20 @@ def main():
 
         def step(batch, loss):
             prob.reconstruct_step(state, pats, batch, opt, loss)
+
+    step_eager = step
+    if args.graph:
+        # the step recorded once as a HIP graph; each step writes its group's
+        # indices into the recorded index buffer and replays the graph
+        g_batch = torch.empty(B, dtype=torch.int32, device=dev)
+        g_loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        recorded = []
+
+        def step(batch, loss):
+            g_batch.copy_(batch)
+            if not recorded:
+                recorded.append(prob.record_step(state, pats, g_batch, opt, g_loss))
+            recorded[0].replay()
 
     def groups():
         while True:
@@ -287,7 +305,7 @@ def main():
             lib.pty_profile_select(None)
             lib.pty_profile_enable(1)
             collect()
-        step(batches[w], loss)
+        (step_eager if probe_step else step)(batches[w], loss)
         if probe_step:
             lib.pty_profile_enable(0)
             dom = dominant(collect())
@@ -300,6 +318,8 @@ def main():
     # every launch of the dominant kernel class in the first DOM_STEPS timed
     # steps is bracketed by two HIP events on the stream it runs on (no other
     # class; the cap bounds the number of events held until they are read)
+    if args.graph:
+        dom = None   # replays record no events: the roofline takes the separate pass's timing
     dom_steps = min(args.steps, DOM_STEPS) if dom else 0
     if dom:
         if lib.pty_profile_select(dom.encode()) != 1:
@@ -341,7 +361,7 @@ def main():
         torch.cuda.synchronize()
         t_p = time.perf_counter()
         for k in range(n_prof):
-            step(batches[args.warmup + k], loss)
+            step_eager(batches[args.warmup + k], loss)
         torch.cuda.synchronize()
         prof_ms_per_step = (time.perf_counter() - t_p) * 1000.0 / n_prof
         lib.pty_profile_enable(0)
@@ -415,7 +435,8 @@ def main():
                                f"{ENGINES[args.engine]}{', all regularizers' if args.regularize else ''}",
                    "global_batch": B, "checkpoint_every": prob.checkpoint_every,
                    "checkpoint_storage": "f16" if prob.checkpoint_half else "f32", "strategy": args.strategy,
-                   "reduction": args.reduction, "engine": args.engine, "regularizers": bool(args.regularize)},
+                   "reduction": args.reduction, "engine": args.engine, "regularizers": bool(args.regularize),
+                   "graph": bool(args.graph)},
         "p50_ms_per_group": round(float(p50), 3), "p99_ms_per_group": round(float(p99), 3),
         "positions_per_s_p50": round(B / (p50 / 1000.0), 1), "positions_per_s_p99": round(B / (p99 / 1000.0), 1),
         "epochs_timed": int(n_ep),

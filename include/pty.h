@@ -274,7 +274,12 @@ pty_status pty_backward_dev(pty_ctx* ctx, void* stream, const double* grad_scale
 
 /* Resident reconstruction state (device pointers). Moments (m_*, v_*) are
  * float32 arrays with the real-component shape of their variable; they are
- * only used by Adam. step counts completed Adam steps (host-side). */
+ * only used by Adam. step counts completed Adam steps (host-side). step_dev,
+ * if not NULL, points to one device int64 that holds that count instead: the
+ * Adam kernels read it in stream order (bias corrections 1 - beta^t with
+ * t = *step_dev + 1, formed on the device) and the step advances it on the
+ * device, so no value depends on the host and a recorded step replays
+ * correctly (pty_step_graph_*); step is then left unchanged. */
 typedef struct {
   pty_c64* probe;      /* [M][N][N] */
   pty_c64* object;     /* [S][H][W] */
@@ -283,6 +288,7 @@ typedef struct {
   float* m_object; float* v_object;   /* [S][H][W][2] */
   float* m_pos; float* v_pos;         /* [J][2] */
   int64_t step;
+  int64_t* step_dev;
 } pty_state;
 
 /* PTY_OPT_EPIE is the conventional ePIE / 3PIE engine (Sec. 3.3) rather than
@@ -445,6 +451,30 @@ pty_status pty_group_reconstruct_step(pty_group* grp, void* stream, const pty_gr
                                       int32_t n_items);
 const char* pty_group_last_error(const pty_group* grp);
 void pty_group_destroy(pty_group* grp);
+
+/* ---- recorded steps -----------------------------------------------------
+ * One pty_reconstruct_step recorded as a HIP graph (stream capture) and
+ * replayed: for launch-bound problems (small probes, few slices) a replay
+ * issues the step's dozen or more kernels without their per-launch host cost.
+ * pty_step_graph_create records pty_reconstruct_step(ctx, stream, st,
+ * patterns, batch_idx, B, optim, loss) on `stream` (nothing runs while
+ * recording) and instantiates it; pty_step_graph_launch replays it on
+ * `stream`. Every pointer, size, learning rate and the group size B are fixed
+ * at recording; a replay reads the current contents of the same buffers, so
+ * a caller changes the minibatch by writing new indices into batch_idx
+ * between replays (and the state evolves in place, as with direct calls).
+ * The context must outlive the graph and must not be used by another call
+ * while a replay runs. Refused (PTY_EUNSUPPORTED, nothing recorded): Adam
+ * without st->step_dev (a host-side count would be frozen into the graph),
+ * the object-spectrum L1 regularizer (its transforms are library calls that
+ * are not recorded), and while launch timing is enabled. PTY_EHIP if the
+ * runtime refuses the capture or the instantiation. */
+typedef struct pty_step_graph pty_step_graph;
+pty_status pty_step_graph_create(pty_ctx* ctx, void* stream, pty_state* st, const float* patterns,
+                                 const int32_t* batch_idx, int32_t batch, const pty_optim* optim, double* loss,
+                                 pty_step_graph** out);
+pty_status pty_step_graph_launch(pty_step_graph* graph, void* stream);
+void pty_step_graph_destroy(pty_step_graph* graph);
 
 /* ---- launch timing ------------------------------------------------------
  * When enabled (process-wide), every kernel launch of the library is

@@ -30,7 +30,8 @@ EXPORTS = (
     "pty_destroy", "pty_group_create", "pty_group_workspace_bytes", "pty_group_reconstruct_step",
     "pty_group_last_error", "pty_group_destroy", "pty_profile_enable", "pty_profile_select", "pty_profile_collect",
     "pty_set_regularizers", "pty_set_strategy", "pty_set_reduction", "pty_lsqml_step", "pty_set_streams",
-    "pty_backward_dev", "pty_forward_static",
+    "pty_backward_dev", "pty_forward_static", "pty_step_graph_create", "pty_step_graph_launch",
+    "pty_step_graph_destroy",
 )
 # bytes of the static device array behind pty_forward_static (PTY_STATIC_SCRATCH_BYTES)
 STATIC_SCRATCH_BYTES = 32 << 20
@@ -78,7 +79,7 @@ class State(C.Structure):
         ("m_probe", C.c_void_p), ("v_probe", C.c_void_p),
         ("m_object", C.c_void_p), ("v_object", C.c_void_p),
         ("m_pos", C.c_void_p), ("v_pos", C.c_void_p),
-        ("step", C.c_int64),
+        ("step", C.c_int64), ("step_dev", C.c_void_p),
     ]
 
 
@@ -139,6 +140,9 @@ def load():
         "pty_set_reduction": ([vp, i32], i32),
         "pty_lsqml_step": ([vp, vp, C.POINTER(State), C.POINTER(Illum), vp, vp, i32, C.POINTER(Lsqml), vp], i32),
         "pty_profile_collect": ([C.c_char_p, sz, C.POINTER(f64), C.POINTER(i64), i32], i32),
+        "pty_step_graph_create": ([vp, vp, C.POINTER(State), vp, vp, i32, C.POINTER(Optim), vp, C.POINTER(vp)], i32),
+        "pty_step_graph_launch": ([vp, vp], i32),
+        "pty_step_graph_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

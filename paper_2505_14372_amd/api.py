@@ -7,6 +7,7 @@ C entry points, and raises PtyError on a non-OK status.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -60,9 +61,12 @@ class Optimizer:
 
 
 class ReconState:
-    """Resident reconstruction state (probe, object, positions, Adam moments)."""
+    """Resident reconstruction state (probe, object, positions, Adam moments).
+    With device_step the Adam step count lives in a device int64 (read and
+    advanced by the kernels), which a recorded step (Problem.record_step) needs."""
 
-    def __init__(self, probe: torch.Tensor, obj: torch.Tensor, positions: torch.Tensor, adam: bool = True):
+    def __init__(self, probe: torch.Tensor, obj: torch.Tensor, positions: torch.Tensor, adam: bool = True,
+                 device_step: bool = False):
         self.probe = probe.contiguous()
         self.object = obj.contiguous()
         self.positions = positions.contiguous()
@@ -75,11 +79,16 @@ class ReconState:
         self.m_pos = z(self.positions) if adam else None
         self.v_pos = z(self.positions) if adam else None
         self.step = 0
+        self.step_dev = torch.zeros(1, dtype=torch.int64, device=probe.device) if device_step else None
 
     def c(self):
         return _lib.State(_ptr(self.probe), _ptr(self.object), _ptr(self.positions), _ptr(self.m_probe),
                           _ptr(self.v_probe), _ptr(self.m_object), _ptr(self.v_object), _ptr(self.m_pos),
-                          _ptr(self.v_pos), self.step)
+                          _ptr(self.v_pos), self.step, _ptr(self.step_dev))
+
+    def steps_done(self) -> int:
+        """Completed Adam steps (reads the device count when there is one)."""
+        return int(self.step_dev.item()) if self.step_dev is not None else self.step
 
     def nbytes(self):
         return sum(t.numel() * t.element_size() for t in (self.probe, self.object, self.positions, self.m_probe,
@@ -128,6 +137,7 @@ class Problem:
                  checkpoint_every: int = 1, hbm_budget: int = 0, checkpoint_half: bool = False,
                  tilt=(0.0, 0.0), bandlimit_mask=None, lsqml: bool = False):
         self.lib = _lib.load()
+        self._graphs = []
         self.N, self.M, self.S, self.H, self.W, self.J = N, M, S, H, W, J
         self.loss_kind = loss
         self.max_batch = max_batch
@@ -145,6 +155,12 @@ class Problem:
         self.tape_id = 0          # incremented by every forward_save (identifies the tape)
 
     def close(self):
+        # recorded steps replay into this context's buffers: release them first
+        for ref in getattr(self, "_graphs", []):
+            g = ref()
+            if g is not None:
+                g.close()
+        self._graphs = []
         if getattr(self, "ctx", None):
             self.lib.pty_destroy(self.ctx)
             self.ctx = None
@@ -296,6 +312,29 @@ class Problem:
         state.step = cs.step
         return loss
 
+    def record_step(self, state: ReconState, patterns, batch_idx, opt: Optimizer, loss=None) -> "StepGraph":
+        """Record one reconstruct_step as a HIP graph (pty_step_graph_create)
+        for replays: StepGraph.replay() runs the whole step again on the same
+        buffers, reading their current contents (write the next minibatch's
+        indices into batch_idx in place between replays). Adam needs a state
+        made with device_step=True. Recording runs nothing; it uses a side
+        stream, since the default stream cannot record."""
+        B = self._check_inputs(state.probe, state.object, state.positions, batch_idx, patterns)
+        if loss is None:
+            loss = torch.zeros(1, dtype=torch.float64, device=state.probe.device)
+        cs = state.c()
+        co = opt.c()
+        out = C.c_void_p()
+        side = torch.cuda.Stream(device=state.probe.device)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            st = self.lib.pty_step_graph_create(self.ctx, _stream(), C.byref(cs), _ptr(patterns), _ptr(batch_idx),
+                                                B, C.byref(co), _ptr(loss), C.byref(out))
+        torch.cuda.current_stream().wait_stream(side)
+        if st:
+            self._err(st, "pty_step_graph_create")
+        return StepGraph(self, out, (state, patterns, batch_idx, loss))
+
     def lsqml_step(self, state: ReconState, illum: "IllumSums", patterns, batch_idx, beta_object=0.1,
                    beta_probe=0.1, delta_object=1e-2, delta_probe=1e-2, gamma=0.0, loss=None):
         """One LSQML group step (pty_lsqml_step); needs Problem(..., lsqml=True).
@@ -327,6 +366,36 @@ class Problem:
         st = self.lib.pty_check(self.ctx, _stream())
         if st:
             self._err(st, "pty_check")
+
+
+class StepGraph:
+    """A recorded reconstruct_step (Problem.record_step). replay() enqueues
+    the whole step on the current stream; close() (or closing the Problem)
+    releases it."""
+
+    def __init__(self, prob: Problem, handle: C.c_void_p, keep):
+        self.prob = prob
+        self.handle = handle
+        self._keep = keep          # the recorded buffers stay alive with the graph
+        prob._graphs.append(weakref.ref(self))
+
+    def replay(self):
+        if not self.handle or not self.prob.ctx:
+            raise RuntimeError("the recorded step or its problem is closed")
+        st = self.prob.lib.pty_step_graph_launch(self.handle, _stream())
+        if st:
+            self.prob._err(st, "pty_step_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.prob.lib.pty_step_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class IllumSums:

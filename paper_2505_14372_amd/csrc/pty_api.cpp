@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -930,16 +931,18 @@ pty_status pty_loss_and_grad(pty_ctx* c, void* stream, const pty_c64* probe, con
 namespace {
 
 // Optimiser step of one variable with n real components.
-void opt_update(hipStream_t s, const pty_optim* o, int64_t t, float* th, const float* g, float* m, float* v,
-                double lr, size_t n) {
+// One variable's update. Adam takes step t from the host, or, with t_dev,
+// reads it on the device (t = *t_dev + 1).
+void opt_update(hipStream_t s, const pty_optim* o, int64_t t, const int64_t* t_dev, float* th, const float* g,
+                float* m, float* v, double lr, size_t n) {
   if (lr == 0.0 || n == 0) return;
   if (o->kind == PTY_OPT_SGD) {
     launch_sgd(s, th, g, n, (float)lr);
+  } else if (t_dev) {
+    launch_adam_dev(s, th, g, m, v, n, lr, t_dev, o->beta1, o->beta2, (float)o->eps);
   } else {
-    const double bc1 = 1.0 - std::pow(o->beta1, (double)t);
-    const double bc2 = 1.0 - std::pow(o->beta2, (double)t);
-    launch_adam(s, th, g, m, v, n, (float)(lr / bc1), (float)(1.0 / std::sqrt(bc2)), o->beta1, o->beta2,
-                (float)o->eps);
+    const AdamFactors f = adam_factors(lr, o->beta1, o->beta2, t);
+    launch_adam(s, th, g, m, v, n, f.step_size, f.inv_sqrt_bc2, o->beta1, o->beta2, (float)o->eps);
   }
 }
 
@@ -966,10 +969,17 @@ void apply_optimizer(pty_ctx* c, hipStream_t s, pty_state* st, const pty_optim* 
   const size_t nP = (size_t)g.n_modes * g.N * g.N * 2;
   const size_t nX = (size_t)g.n_positions * 2;
   const int64_t t = st->step + 1;
-  opt_update(s, o, t, (float*)st->object, (const float*)c->gobj, st->m_object, st->v_object, o->lr_object, nO);
-  opt_update(s, o, t, (float*)st->probe, (const float*)c->gprobe, st->m_probe, st->v_probe, o->lr_probe, nP);
-  opt_update(s, o, t, st->positions, c->gpos, st->m_pos, st->v_pos, o->lr_pos, nX);
-  if (o->kind == PTY_OPT_ADAM) st->step = t;
+  const int64_t* t_dev = o->kind == PTY_OPT_ADAM ? st->step_dev : nullptr;
+  opt_update(s, o, t, t_dev, (float*)st->object, (const float*)c->gobj, st->m_object, st->v_object, o->lr_object,
+             nO);
+  opt_update(s, o, t, t_dev, (float*)st->probe, (const float*)c->gprobe, st->m_probe, st->v_probe, o->lr_probe,
+             nP);
+  opt_update(s, o, t, t_dev, st->positions, c->gpos, st->m_pos, st->v_pos, o->lr_pos, nX);
+  if (o->kind == PTY_OPT_ADAM) {
+    // the device count advances after the last update that read it
+    if (st->step_dev) launch_step_advance(s, st->step_dev);
+    else st->step = t;
+  }
 }
 
 }  // namespace
@@ -1451,6 +1461,81 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- recorded steps
+
+struct pty_step_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  pty_ctx* ctx = nullptr;
+};
+
+extern "C" pty_status pty_step_graph_create(pty_ctx* c, void* stream, pty_state* st, const float* patterns,
+                                            const int32_t* batch_idx, int32_t B, const pty_optim* o,
+                                            double* loss, pty_step_graph** out) {
+  if (!c) return PTY_EINVAL;
+  if (!out) { c->err = "NULL graph output"; return PTY_EINVAL; }
+  *out = nullptr;
+  pty_status v = check_state(c, st, o);
+  if (v != PTY_OK) return v;
+  if (o->kind == PTY_OPT_ADAM && !st->step_dev) {
+    c->err = "a recorded Adam step needs the device-side step count (pty_state.step_dev)";
+    return PTY_EUNSUPPORTED;
+  }
+  if (c->reg_on && c->obj_spec_l1 != 0.f) {
+    c->err = "the object-spectrum L1 regularizer cannot be recorded";
+    return PTY_EUNSUPPORTED;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (g_prof.on) { c->err = "launch timing is enabled"; return PTY_EUNSUPPORTED; }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  // nothing runs while the stream records; an argument error returns before
+  // the first launch and the recording is discarded
+  const pty_status rs = pty_reconstruct_step(c, stream, st, patterns, batch_idx, B, o, loss);
+  hipGraph_t g = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(s, &g);
+  if (rs != PTY_OK || e_end != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    if (rs != PTY_OK) return rs;
+    c->err = std::string("recording the step failed: ") + hipGetErrorString(e_end);
+    return PTY_EHIP;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t e_inst = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e_inst != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    c->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e_inst);
+    return PTY_EHIP;
+  }
+  pty_step_graph* G = new (std::nothrow) pty_step_graph;
+  if (!G) {
+    (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
+    c->err = "out of host memory";
+    return PTY_ENOMEM;
+  }
+  G->graph = g;
+  G->exec = x;
+  G->ctx = c;
+  *out = G;
+  return PTY_OK;
+}
+
+extern "C" pty_status pty_step_graph_launch(pty_step_graph* G, void* stream) {
+  if (!G) return PTY_EINVAL;
+  HIPCHECK(G->ctx, hipGraphLaunch(G->exec, (hipStream_t)stream));
+  return PTY_OK;
+}
+
+extern "C" void pty_step_graph_destroy(pty_step_graph* G) {
+  if (!G) return;
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  delete G;
+}
 
 extern "C" void pty_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -15,6 +16,27 @@ constexpr int kFlagBounds = 1;
 constexpr int kFlagNonFinite = 2;
 constexpr int kMaxReqs = 16;   // reconstructions per shared launch
 constexpr int kMaxItems = 65535;   // positions per launch (one grid dimension holds them)
+
+// Adam's per-step factors for step t >= 1: lr / (1 - b1^t) and
+// 1 / sqrt(1 - b2^t), in double with b^t formed by repeated squaring, so that
+// the host (host-side step count) and the device (device-side count) form
+// the same values.
+struct AdamFactors {
+  float step_size, inv_sqrt_bc2;
+};
+__host__ __device__ inline double pow_int(double b, long long t) {
+  double r = 1.0;
+  while (t > 0) {
+    if (t & 1) r *= b;
+    b *= b;
+    t >>= 1;
+  }
+  return r;
+}
+__host__ __device__ inline AdamFactors adam_factors(double lr, double b1, double b2, long long t) {
+  const double bc1 = 1.0 - pow_int(b1, t), bc2 = 1.0 - pow_int(b2, t);
+  return AdamFactors{(float)(lr / bc1), (float)(1.0 / sqrt(bc2))};
+}
 
 // One batch entry (probe position) of a launch; filled on the device.
 struct Item {
@@ -155,6 +177,10 @@ void launch_fill(hipStream_t s, float* p, size_t n, float v);
 void launch_sgd(hipStream_t s, float* th, const float* g, size_t n, float lr);
 void launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, size_t n, float step_size,
                  float inv_sqrt_bc2, double b1, double b2, float eps);
+// Adam with the step count read on the device: t = *step_dev + 1
+void launch_adam_dev(hipStream_t s, float* th, const float* g, float* m, float* v, size_t n, double lr,
+                     const int64_t* step_dev, double b1, double b2, float eps);
+void launch_step_advance(hipStream_t s, int64_t* step_dev);
 int col_blocks(int N);
 
 enum ColOp { COL_SHIFT = 0, COL_PROP = 1, COL_PROP_ADJ = 2, COL_FINAL = 3 };

@@ -9,9 +9,10 @@
 //   probe spectrum (unitary):         phat[m*N*N + u_y*N + u_x]
 //   entry-wave checkpoints:           ck[(ck0(b) + m + slot * n_items * M) * N*N + ...]
 //                                     (slot-major: one slice's waves of the group are contiguous);
-//                                     stored in float they hold the row spectrum F_x(psi_i),
-//                                     written by the column passes, as do the segment buffers
-//                                     of recomputed slices
+//                                     stored in float they hold the row spectrum F_x(psi_i):
+//                                     the forward row pass of slice i - 1 leaves its output in
+//                                     slot i and the column pass completes it there in place;
+//                                     the segment buffers of recomputed slices hold the same
 //
 // One slice step is two passes over a tile, each a batched launch:
 //   row pass    : inverse row DFT -> entry wave psi_i (real space, optionally
@@ -1128,6 +1129,37 @@ __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, floa
   }
 }
 
+// Adam with the step count on the device: one thread per workgroup forms the
+// step's factors from t = *step_dev + 1 (the value the whole step reads; the
+// step advances it after its last update).
+__global__ void k_adam_dev(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ mo,
+                           float* __restrict__ ve, size_t n, double lr, const int64_t* __restrict__ step_dev,
+                           double b1d, double b2d, float eps) {
+  __shared__ float fac[2];
+  if (threadIdx.x == 0) {
+    const AdamFactors f = adam_factors(lr, b1d, b2d, *step_dev + 1);
+    fac[0] = f.step_size;
+    fac[1] = f.inv_sqrt_bc2;
+  }
+  __syncthreads();
+  const float step_size = fac[0], inv_sqrt_bc2 = fac[1];
+  const float b1 = (float)b1d, c1 = (float)(1.0 - b1d), b2 = (float)b2d, c2 = (float)(1.0 - b2d);
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    float gi = g[i];
+    float m = b1 * mo[i] + c1 * gi;
+    float v = b2 * ve[i] + c2 * gi * gi;
+    mo[i] = m;
+    ve[i] = v;
+    th[i] -= step_size * m / (sqrtf(v) * inv_sqrt_bc2 + eps);
+  }
+}
+
+__global__ void k_step_advance(int64_t* step_dev) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step_dev += 1;
+}
+
 // ============================================================ launchers
 
 static inline dim3 grid1(size_t n) {
@@ -1290,6 +1322,14 @@ void launch_adam(hipStream_t s, float* th, const float* g, float* m, float* v, s
   if (n == 0) return;
   hipLaunchKernelGGL(k_adam, grid1(n), dim3(kThreads), 0, s, th, g, m, v, n, step_size, inv_sqrt_bc2, (float)b1,
                      (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), eps);
+}
+void launch_adam_dev(hipStream_t s, float* th, const float* g, float* m, float* v, size_t n, double lr,
+                     const int64_t* step_dev, double b1, double b2, float eps) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_adam_dev, grid1(n), dim3(kThreads), 0, s, th, g, m, v, n, lr, step_dev, b1, b2, eps);
+}
+void launch_step_advance(hipStream_t s, int64_t* step_dev) {
+  hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step_dev);
 }
 int col_blocks(int N) {
   return N == 256 ? ColPass<256>::NBLK : N == 192 ? ColPass<192>::NBLK : N == 128 ? ColPass<128>::NBLK : ColPass<64>::NBLK;
