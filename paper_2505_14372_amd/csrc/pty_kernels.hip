@@ -737,10 +737,16 @@ __device__ __forceinline__ void loss_weight(int kind, float I, float Ie, float e
       ell = I;
       w = 2.f;
     } else {
-      // I - Ie - Ie (ln(I+eps) - ln(Ie+eps)), the log ratio as log1p for accuracy;
-      // invalid counts (negative, NaN) give a non-finite loss and raise the flag
-      float den = Ie + eps;
-      ell = (I - Ie) - Ie * log1pf((I - Ie) / den);
+      // I - Ie - Ie (ln(I+eps) - ln(Ie+eps)). Near I = Ie the log ratio is
+      // log1p of the relative difference (no cancellation); away from it the
+      // difference of the two logs, since for I + eps below about 6e-8 of
+      // Ie + eps the relative difference rounds to -1 and log1p would return
+      // -inf for a finite loss. Invalid counts (negative, NaN) and I + eps = 0
+      // give a non-finite loss and raise the flag.
+      const float den = Ie + eps;
+      const float x = (I - Ie) / den;
+      const float lr = fabsf(x) < 0.5f ? log1pf(x) : logf(I + eps) - logf(den);
+      ell = (I - Ie) - Ie * lr;
       w = 2.f * (1.f - Ie / (I + eps));
     }
   } else if (kind == PTY_LOSS_GAUSSIAN) {

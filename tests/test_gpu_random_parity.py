@@ -3,6 +3,8 @@ noise model, band limit, beam tilt, object shape and amplitude, scan, batch
 subset and order, strategy, reduction, checkpoint interval and storage, and
 chunk size are drawn per case, and the HIP path's loss and gradients are
 compared element by element with the FP64 oracle on the same inputs."""
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +16,32 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 TOL_I, TOL_G = 1e-4, 1e-3
+
+
+def _float_sensitivity(c, ref):
+    """Relative change of the FP64 gradients when the far-field amplitude
+    carries an error of float32 size (3e-7 of its RMS, complex, fixed seed):
+    the resolution any float32 evaluation of this input can reach. The noise
+    models without eps (Sec. 3.1) are singular at zero intensity, and where a
+    counted pixel's intensity is a tiny fraction of its count this sensitivity
+    exceeds the gradient bar (the oracle itself is unchanged; only its
+    intensities are perturbed, through its own loss function)."""
+    import oracle.pty_oracle as po
+    rng = np.random.default_rng(7)
+    exact = po.loss_and_weight
+
+    def perturbed(I, Ie, kind, eps=0.0, sigma=1.0):
+        s = 3e-7 * np.sqrt(I.mean())
+        a = np.sqrt(I) + s * rng.standard_normal(I.shape)
+        b = s * rng.standard_normal(I.shape)
+        return exact(a * a + b * b, Ie, kind, eps, sigma)
+
+    po.loss_and_weight = perturbed
+    try:
+        per = c.oracle_grad()
+    finally:
+        po.loss_and_weight = exact
+    return {k: rel_l2(per[k], ref[k]) for k in ("g_object", "g_probe", "g_pos")}
 
 
 def _draw(seed):
@@ -47,7 +75,8 @@ def _draw(seed):
     return Case(wl, batch=batch), strategy, reduction, sched
 
 
-@pytest.mark.parametrize("seed", range(20))
+# PTY_RANDOM_CASES widens the sweep (default 20 cases)
+@pytest.mark.parametrize("seed", range(int(os.environ.get("PTY_RANDOM_CASES", "20"))))
 def test_random_configuration_matches_oracle(seed):
     c, strategy, reduction, sched = _draw(seed)
     print(f"seed {seed}: N={c.N} M={c.M} S={c.S} H={c.H} W={c.W} B={len(c.batch)} loss={c.geom.loss} "
@@ -61,9 +90,15 @@ def test_random_configuration_matches_oracle(seed):
     loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
     prob.check()
     assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
-    for name, got, want in (("object", gO, ref["g_object"]), ("probe", gP, ref["g_probe"]),
-                            ("positions", gX, ref["g_pos"])):
+    # a singular noise model (no eps) may make the exact gradients sensitive
+    # beyond the bar to float32-sized intensity errors: the bar is then four
+    # times that sensitivity
+    singular = c.geom.eps == 0.0 and c.geom.loss in ("amplitude", "anscombe", "poisson")
+    sens = _float_sensitivity(c, ref) if singular else {}
+    for name, key, got in (("object", "g_object", gO), ("probe", "g_probe", gP), ("positions", "g_pos", gX)):
         g = got.detach().cpu().numpy()
+        want = ref[key]
         e2, einf = rel_l2(g, want), max_rel(g, want)
-        print(f"  {name}: rel L2 {e2:.2e}, max {einf:.2e}")
-        assert e2 < TOL_G and einf < TOL_G, (name, e2, einf)
+        bar = max(TOL_G, 4.0 * sens.get(key, 0.0))
+        print(f"  {name}: rel L2 {e2:.2e}, max {einf:.2e}" + (f" (bar {bar:.1e})" if bar > TOL_G else ""))
+        assert e2 < bar and einf < bar, (name, e2, einf, bar)
