@@ -330,7 +330,8 @@ typedef struct {
  *   probe_phase_tikhonov, probe_phase_tv  the phase plate of each mode, the phase of its unitary
  *                   spectrum P^ = F(P) taken centred (zero frequency at N/2): for every pair of
  *                   neighbours (a, b) along either axis, z = a conj(b) = |z| e^{it}, t in (-pi, pi],
- *                   costs |z| t^2 (Tikhonov) or |z| sqrt(t^2 + tv_delta^2) (TV)
+ *                   costs |z|^2 t^2 (Tikhonov) or |z|^2 sqrt(t^2 + tv_delta^2) (TV): phase steps
+ *                   weighted by the two frequencies' intensities (gradient continuous at z = 0)
  * Constraint regularizers are applied to the state after the optimiser:
  *   amp_clamp       object amplitude limited to [amp_min, amp_max] (phase kept)
  *   probe_support   host [N][N] reciprocal-space mask (FFT order) or NULL: P <- F^-1(mask F(P))

@@ -575,10 +575,15 @@ def reconstruct_step(state, patterns, batch_idx, geom: Geometry, opt):
 #                 neighbouring frequencies); for each pair of neighbours
 #                 (a, b) along either axis, z = a conj(b) = |z| e^{i t} with t
 #                 the phase step in (-pi, pi] (no unwrapping needed), and the
-#                 cost is |z| t^2 (Tikhonov) or |z| sqrt(t^2 + delta^2) (TV):
-#                 the squared or absolute phase step weighted by the
-#                 amplitudes, so that the phase where the aperture is dark
-#                 costs nothing and the gradient stays bounded
+#                 cost is |z|^2 t^2 (Tikhonov) or |z|^2 sqrt(t^2 + delta^2)
+#                 (TV): the squared or absolute phase step weighted by the
+#                 intensities of the two frequencies, so that the phase where
+#                 the aperture is dark costs nothing and the gradient, with
+#                 respect to z 2 z (t^2 + i t) or z (2 sqrt(t^2 + delta^2) +
+#                 i t / sqrt(t^2 + delta^2)), vanishes continuously as z -> 0
+#                 (with weights |z| it would keep a magnitude of order 1 and a
+#                 direction set by rounding at a dark frequency next to a lit
+#                 one: the aperture edge)
 # Constraint regularizers are applied to the state after each group step:
 #   amplitude range: O <- O * clip(|O|, a_min, a_max) / |O|
 #   probe support:   P <- F^-1(mask * F(P)) with a reciprocal-space mask,
@@ -681,14 +686,16 @@ def regularization(obj, probe, reg):
             lo[ax] = slice(0, n - 1)
             a, b = C[tuple(hi)], C[tuple(lo)]
             z = a * np.conj(b)
-            r, t = np.abs(z), np.angle(z)
+            r2, t = np.abs(z) ** 2, np.angle(z)
+            # cost f(|z|) h(t) with f = |z|^2: gradient with respect to z (dRe + i dIm)
+            # e^{it} (f'(|z|) h + i f(|z|) h' / |z|) = z (2 h + i h')
             if key == "probe_phase_tikhonov":
-                cost += w * np.sum(r * t * t)
-                G = np.exp(1j * t) * (t * t + 2j * t)          # d(r t^2): e^{it} (d/dr + i/r d/dt)
+                cost += w * np.sum(r2 * t * t)
+                G = z * (2 * t * t + 2j * t)
             else:
                 q = np.sqrt(t * t + d * d)
-                cost += w * np.sum(r * q)
-                G = np.exp(1j * t) * (q + 1j * t / q)
+                cost += w * np.sum(r2 * q)
+                G = z * (2 * q + 1j * t / q)
             gC[tuple(hi)] += w * G * b                         # z = a conj(b)
             gC[tuple(lo)] += w * np.conj(G) * a
         gP += ifft2u(np.fft.ifftshift(gC, axes=(-2, -1)))

@@ -1452,25 +1452,27 @@ __global__ void k_reg_probe(const float2* __restrict__ P, float2* __restrict__ g
 // mod N, so the centred neighbours of u are u - 1 and u + 1 (mod N) except
 // across the centred array's ends (u = N/2 has no lower neighbour, u = N/2 - 1
 // no upper one). A pair (a, b) of neighbours, a the upper one, has
-// z = a conj(b) = r e^{it} and cost r t^2 (Tikhonov) or r sqrt(t^2 + d^2)
-// (TV), whose gradient with respect to z is G = e^{it} (dC/dr + i/r dC/dt):
-// e^{it} (t^2 + 2it) and e^{it} (q + it/q), q = sqrt(t^2 + d^2); then
-// dC/da = G b and dC/db = conj(G) a. One thread per pixel gathers the terms
-// of its (up to four) pairs into gphat and counts the cost of the pairs where
-// it is the upper element, so each pair is counted once.
+// z = a conj(b) = r e^{it} and cost r^2 t^2 (Tikhonov) or r^2 sqrt(t^2 + d^2)
+// (TV): phase steps weighted by the two frequencies' intensities. For a cost
+// f(r) h(t) the gradient with respect to z is e^{it} (f' h + i f h' / r), with
+// f = r^2 that is G = z (2h + i h'): 2 z (t^2 + it) and z (2q + it/q),
+// q = sqrt(t^2 + d^2), which vanishes continuously as z -> 0 (so a dark
+// frequency next to a lit one, whose phase is rounding noise, contributes
+// nothing); then dC/da = G b and dC/db = conj(G) a. One thread per pixel
+// gathers the terms of its (up to four) pairs into gphat and counts the cost
+// of the pairs where it is the upper element, so each pair is counted once.
 __device__ __forceinline__ float2 phase_pair_grad(float2 z, float wt, float wv, float d2, float& cost) {
-  const float r = hypotf(z.x, z.y);
+  const float r2 = cabs2(z);
   const float t = atan2f(z.y, z.x);
-  const float2 e = r > 0.f ? make_float2(z.x / r, z.y / r) : make_float2(1.f, 0.f);
   float2 G = make_float2(0.f, 0.f);
   if (wt != 0.f) {
-    cost += wt * r * t * t;
-    G = cadd(G, cscale(cmul(e, make_float2(t * t, 2.f * t)), wt));
+    cost += wt * r2 * t * t;
+    G = cadd(G, cscale(cmul(z, make_float2(2.f * t * t, 2.f * t)), wt));
   }
   if (wv != 0.f) {
     const float q = sqrtf(t * t + d2);
-    cost += wv * r * q;
-    G = cadd(G, cscale(cmul(e, make_float2(q, t / q)), wv));
+    cost += wv * r2 * q;
+    G = cadd(G, cscale(cmul(z, make_float2(2.f * q, t / q)), wv));
   }
   return G;
 }

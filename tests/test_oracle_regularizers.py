@@ -95,24 +95,35 @@ def test_phase_and_spectrum_l1_closed_forms():
 
 def test_probe_phase_plate_closed_forms():
     """Phase-plate Tikhonov / TV of a probe whose centred spectrum is
-    A exp(i alpha k_y): every step along k_y has phase alpha and weight A^2,
-    every step along k_x phase 0; a global phase and the amplitude pattern's
-    sign conventions leave it unchanged; a uniform phase plate costs nothing
-    (Tikhonov) or delta per step (TV)."""
+    A exp(i alpha k_y): every step along k_y has phase alpha and weight
+    |z|^2 = A^4, every step along k_x phase 0; a global phase leaves it
+    unchanged; a uniform phase plate costs nothing (Tikhonov) or A^4 delta per
+    step (TV); at a dark frequency next to a lit one the gradient vanishes."""
     N, A, al, d = 7, 1.3, 0.4, 0.05
     k = np.arange(N)[:, None] * np.ones((1, N))
     C = A * np.exp(1j * al * k)
     P = orc.ifft2u(np.fft.ifftshift(C))[None]
     vac = np.ones((1, 8, 8), complex)
+    A4 = A ** 4
     c, _, _ = orc.regularization(vac, P, {"probe_phase_tikhonov": 1.0})
-    assert abs(c - N * (N - 1) * A * A * al * al) < 1e-10
+    assert abs(c - N * (N - 1) * A4 * al * al) < 1e-10
     c, _, _ = orc.regularization(vac, P, {"probe_phase_tv": 1.0, "tv_delta": d})
-    assert abs(c - N * (N - 1) * A * A * (np.sqrt(al * al + d * d) + d)) < 1e-10
+    assert abs(c - N * (N - 1) * A4 * (np.sqrt(al * al + d * d) + d)) < 1e-10
     c2, _, _ = orc.regularization(vac, P * np.exp(0.9j), {"probe_phase_tikhonov": 1.0})
-    assert abs(c2 - N * (N - 1) * A * A * al * al) < 1e-10
+    assert abs(c2 - N * (N - 1) * A4 * al * al) < 1e-10
     flat = orc.ifft2u(np.fft.ifftshift(A * np.exp(0.7j) * np.ones((N, N))))[None]
     c, g, gP = orc.regularization(vac, flat, {"probe_phase_tikhonov": 1.0})
     assert abs(c) < 1e-20 and np.max(np.abs(gP)) < 1e-12
+    # an aperture: lit frequencies next to exactly dark ones; the gradient is
+    # the same whichever tiny values the dark frequencies hold (continuity at z = 0)
+    lit = (k - 3) ** 2 + (k.T - 3) ** 2 <= 4
+    rng = np.random.default_rng(3)
+    spec = np.where(lit, A * np.exp(1j * rng.uniform(-1, 1, (N, N))), 0)
+    noise = 1e-13 * (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    g0 = orc.regularization(vac, orc.ifft2u(np.fft.ifftshift(spec))[None], {"probe_phase_tikhonov": 1.0})[2]
+    g1 = orc.regularization(vac, orc.ifft2u(np.fft.ifftshift(spec + noise * ~lit))[None],
+                            {"probe_phase_tikhonov": 1.0})[2]
+    assert np.max(np.abs(g1 - g0)) < 1e-9 * np.max(np.abs(g0))
 
 
 def test_constraints():
