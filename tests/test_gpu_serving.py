@@ -1,6 +1,8 @@
 """The continuous-batching server: results of every reconstruction served in
 a mix of sizes equal its results served alone, admission respects the HBM
 budget, and a request that can never fit is refused."""
+import os
+
 import numpy as np
 import pytest
 
@@ -96,3 +98,27 @@ def test_served_large_windows_give_the_alone_bits():
         assert np.allclose(a.losses, b.losses, rtol=1e-12, atol=0)
         for x, y in ((a.obj, b.obj), (a.probe, b.probe), (a.positions, b.positions)):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("seed", range(int(os.environ.get("PTY_RANDOM_SERVED", "2"))))
+def test_random_served_streams_give_the_alone_bits(seed):
+    """Seeded random streams over every window size (mixed modes, slices and
+    scan sizes, several iterations): under the ordered reduction every served
+    reconstruction has the bits of its run alone."""
+    from paper_2505_14372_amd import serving
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.integers(3, 8))
+    reqs = serving.make_request_stream(n, seed=9100 + seed, rate_per_s=float(rng.uniform(5.0, 100.0)),
+                                       n_iters=int(rng.integers(1, 4)), sizes=(64, 128, 192, 256), max_modes=3,
+                                       max_slices=5, scans=(2, 6), steps=(4, 8), batch=int(rng.choice([8, 16, 32])))
+    print(seed, [(r.rid, r.N, r.M, r.S, r.J, r.batch) for r in reqs], flush=True)
+    srv = serving.Server(hbm_budget=64 << 30, reduction="ordered", fill_first=bool(rng.random() < 0.5))
+    for r in reqs:
+        srv.submit(r)
+    mixed = srv.run()
+    alone = serving.run_fifo(reqs, reduction="ordered")
+    for r in reqs:
+        a, b = mixed[r.rid], alone[r.rid]
+        assert np.allclose(a.losses, b.losses, rtol=1e-12, atol=0), r.rid
+        for x, y in ((a.obj, b.obj), (a.probe, b.probe), (a.positions, b.positions)):
+            assert np.array_equal(x, y), r.rid
