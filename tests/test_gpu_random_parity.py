@@ -72,6 +72,23 @@ def _draw(seed):
     reduction = str(rng.choice(["atomic", "ordered"]))
     sched = dict(checkpoint_every=int(rng.choice([1, 1, 2, 3])), checkpoint_half=bool(rng.random() < 0.25),
                  chunk=int(rng.choice([0, 0, 2, 3])))
+    # chunks on concurrent streams (atomic reduction only), and custom band-limit
+    # masks: an ellipse (centred intervals per row, rebuilt from 1D factors), an
+    # off-centre rectangle or a random scatter (both read from the table, with
+    # arbitrary live columns)
+    sched["streams"] = int(rng.choice([1, 1, 2, 3])) if reduction == "atomic" else 1
+    shape = str(rng.choice(["none", "none", "none", "ellipse", "rectangle", "scatter"]))
+    k = np.fft.fftfreq(N) * N
+    ky, kx = k[:, None], k[None, :]
+    if shape == "ellipse":
+        a, b = rng.uniform(0.15, 0.5, 2) * N
+        wl.bandlimit_mask = (ky / a) ** 2 + (kx / b) ** 2 <= 1.0
+    elif shape == "rectangle":
+        x0, x1 = sorted(rng.uniform(-0.45, 0.45, 2) * N)
+        y0, y1 = sorted(rng.uniform(-0.45, 0.45, 2) * N)
+        wl.bandlimit_mask = (kx >= min(x0, -1)) & (kx <= max(x1, 1)) & (ky >= min(y0, -1)) & (ky <= max(y1, 1))
+    elif shape == "scatter":
+        wl.bandlimit_mask = rng.random((N, N)) < 0.7
     return Case(wl, batch=batch), strategy, reduction, sched
 
 
@@ -80,13 +97,15 @@ def _draw(seed):
 def test_random_configuration_matches_oracle(seed):
     c, strategy, reduction, sched = _draw(seed)
     print(f"seed {seed}: N={c.N} M={c.M} S={c.S} H={c.H} W={c.W} B={len(c.batch)} loss={c.geom.loss} "
-          f"bandlimit={c.geom.bandlimit} tilt={c.tilt} {strategy} {reduction} {sched}", flush=True)
+          f"bandlimit={c.geom.bandlimit} mask={'custom' if c.mask is not None else 'none'} tilt={c.tilt} "
+          f"{strategy} {reduction} {sched}", flush=True)
     ref = c.oracle_grad()
     d = c.device()
     prob = c.problem(checkpoint_every=sched["checkpoint_every"], checkpoint_half=sched["checkpoint_half"])
     prob.set_strategy(strategy)
     prob.set_reduction(reduction)
     prob.set_chunk(sched["chunk"])
+    prob.set_streams(sched["streams"])
     loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
     prob.check()
     assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
