@@ -182,7 +182,8 @@ DOM_STEPS = 64   # timed steps whose dominant-kernel launches are bracketed by e
 def main():
     args = parse()
     if args.reduction == "auto":
-        args.reduction = FASTER_REDUCTION.get(args.workload, "atomic")
+        # the resident chains accumulate the object gradient with atomics only
+        args.reduction = "atomic" if args.strategy == "resident" else FASTER_REDUCTION.get(args.workload, "atomic")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (how the path would shard "
                                    "over GPUs is described in the design notes)"}))

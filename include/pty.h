@@ -160,9 +160,11 @@ int32_t pty_checkpoint_every(const pty_ctx* ctx);
 /* Kernel strategy. TWO_PASS: every slice step is a row pass and a column pass
  * over tiles in the workspace (all N). RESIDENT: for N = 64 and 128 a tile fits
  * in LDS and one workgroup per (position, mode) runs every slice with its
- * tile resident (used when every slice is checkpointed, else two-pass; the
- * ePIE engine always runs two-pass). AUTO (default): TWO_PASS, which measured
- * faster than RESIDENT at N = 128 (8 slices, 4 modes) and equal at N = 64. */
+ * tile resident (used when every slice is checkpointed and the object
+ * gradient is accumulated with atomics, else two-pass; the ePIE engine and
+ * the ordered reduction always run two-pass). AUTO (default): TWO_PASS, which
+ * measured faster than RESIDENT at N = 128 (8 slices, 4 modes) and equal at
+ * N = 64. */
 #define PTY_STRATEGY_AUTO 0
 #define PTY_STRATEGY_TWO_PASS 1
 #define PTY_STRATEGY_RESIDENT 2
