@@ -144,27 +144,30 @@ def kernel_flops_per_launch(name, N, M, B, S, spectral=False):
     return n_fft * lines * per_line
 
 
-def method_flops_per_launch(name, N, M, B):
+def method_flops_per_launch(name, N, M, B, S=1):
     """The method's own FFT flops in one launch (5 n log2 n per 1D line
     transform): each slice step is a 2D DFT and an inverse 2D DFT per mode,
     whose row halves run in the row passes and column halves in the column
-    passes. Work a kernel does beyond that (the adjoint row pass recovering
-    the entry wave from its spectral checkpoint, the far-field pass
-    recomputing the far field) is design overhead and not counted."""
+    passes; an LDS-resident chain runs every slice in one launch (row halves of
+    all S slices, column halves of the S - 1 propagations). Work a kernel does
+    beyond that (the adjoint row pass recovering the entry wave from its
+    spectral checkpoint, the far-field pass recomputing the far field) is
+    design overhead and not counted."""
     per_line = 5 * N * np.log2(N)
     lines = B * M * N
     n_fft = {"row_fwd": 2, "row_adj": 2, "col_prop": 2, "col_prop_adj": 2, "far_loss": 2,
-             "col_shift": 1, "col_final": 1}.get(name, 0)
+             "col_shift": 1, "col_final": 1, "res_fwd": 4 * S - 2, "res_adj": 4 * S - 2}.get(name, 0)
     return n_fft * lines * per_line
 
 
-def method_bytes_per_launch(name, N, B):
+def method_bytes_per_launch(name, N, B, S=1):
     """The method's own HBM bytes in one launch: the object patch of the slice
     (read in the forward and again in the adjoint), the object-gradient
     read-modify-write in the adjoint and the pattern read by the loss; tiles
-    are taken to stay on chip."""
+    are taken to stay on chip (an LDS-resident chain covers all S slices)."""
     T = 8 * N * N
-    return {"row_fwd": B * T, "row_adj": 3 * B * T, "far_loss": B * 4 * N * N}.get(name, 0)
+    return {"row_fwd": B * T, "row_adj": 3 * B * T, "far_loss": B * 4 * N * N,
+            "res_fwd": S * B * T, "res_adj": 3 * S * B * T}.get(name, 0)
 
 
 # Object-gradient reduction measured faster per workload on one MI355X: the
@@ -401,8 +404,8 @@ def main():
         spectral = not prob.checkpoint_half and args.strategy != "resident"
         live = live_fraction(N, wl.bandlimit, S)
         n_launch = B if args.chunk <= 0 else min(args.chunk, B)   # positions one launch processes
-        alg_flops = method_flops_per_launch(dom, N, M, n_launch)
-        alg_bytes = method_bytes_per_launch(dom, N, n_launch)
+        alg_flops = method_flops_per_launch(dom, N, M, n_launch, S)
+        alg_bytes = method_bytes_per_launch(dom, N, n_launch, S)
         design_bytes = kernel_bytes_per_launch(dom, N, M, n_launch, S, prob.checkpoint_half, args.engine, spectral,
                                                live, args.reduction == "ordered")
         tfl = alg_flops / avg_s / 1e12
