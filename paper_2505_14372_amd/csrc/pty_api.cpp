@@ -506,10 +506,12 @@ pty_status check_call(pty_ctx* c, const void* probe, const void* object, const v
 
 // Forward and adjoint of every chunk in turn (so that one chunk's tiles stay
 // cached between its passes), then the group reductions.
-void run_fused(pty_ctx* c, const LaunchCtx& L, float scale) {
+void run_fused(pty_ctx* c, const LaunchCtx& L0, float scale) {
   const int N = c->g.N, S = c->g.n_slices;
-  run_prepare(L, N);
-  const auto chunks = split_chunks(L.n_items, c->chunk);
+  run_prepare(L0, N);
+  const auto chunks = split_chunks(L0.n_items, c->chunk);
+  LaunchCtx L = L0;
+  set_chain_final(L, N, chunks.size() == 1);
   // Chunks touch disjoint work tiles, checkpoints and partial sums, so they
   // may run concurrently, chunk q on stream q mod n, except where two chunks
   // write the same words without atomics: the ordered object-gradient gather
@@ -875,7 +877,9 @@ pty_status backward_impl(pty_ctx* c, void* stream, double grad_scale, const doub
     ProfScope p(P_FILL, s);
     launch_fill(s, (float*)g_object, (size_t)S * c->g.obj_h * c->g.obj_w * 2, 0.f);
   }
-  for (auto& ch : split_chunks(L.n_items, c->chunk))
+  const auto chunks = split_chunks(L.n_items, c->chunk);
+  set_chain_final(L, N, chunks.size() == 1);
+  for (auto& ch : chunks)
     run_backward_chunk(sub(L, ch.first, ch.second), N, S, {S - 1}, (float)grad_scale, c->ck_every, c->ws2, c->seg);
   run_finish_backward(L, N, (float)grad_scale);
   if (g_probe)
@@ -1441,6 +1445,7 @@ pty_status pty_group_reconstruct_step(pty_group* G, void* stream, const pty_grou
   last_steps.erase(std::unique(last_steps.begin(), last_steps.end()), last_steps.end());
   // adjoint step t handles slice S_q - 1 - t of request q; slice 0 at t = S_q - 1
   run_prepare(L, N);
+  set_chain_final(L, N, true);
   run_forward_chunk(L, N, S_max, last_steps, true);
   run_backward_chunk(L, N, S_max, last_steps, 1.f, 1, nullptr, nullptr);
   run_finish_forward(L, N);

@@ -83,6 +83,10 @@ struct ReqDev {
   const float2* prop_x;     // [S-1][N] Hx
   const double* scale_dev;  // device double multiplying the adjoint's outputs (gradient of the
                             // caller's objective with respect to the loss), or null (1)
+  int chain_final;          // the final column pass walks this request's items in kProbeSplit
+                            // chains and keeps the probe-gradient sums in registers
+                            // (k_col_final_chain + k_probe_sum) instead of storing h_hat for
+                            // k_probe_grad (set per launch by set_chain_final)
 };
 
 // Scale of the adjoint outputs: the launch's host factor times the request's
@@ -169,6 +173,9 @@ void launch_col(const LaunchCtx& L, int N, int op, int step);
 void launch_far_loss(const LaunchCtx& L, int N, int step, bool grad);
 void launch_obj_gather(const LaunchCtx& L, int N, int step, int max_h, int max_w);
 void launch_probe_grad(const LaunchCtx& L, int N, float scale);
+// Marks the requests of L whose final column pass runs as chains (unchunked
+// launches with enough (column block, mode, chain) workgroups to fill the GPU).
+void set_chain_final(LaunchCtx& L, int N, bool unchunked);
 void launch_loss_reduce(const LaunchCtx& L, int N);
 void launch_pos_reduce(const LaunchCtx& L, int N, float scale);
 void launch_plain2d(int N, hipStream_t s, const float2* tw, const float2* src, float2* dst, int n_tiles,

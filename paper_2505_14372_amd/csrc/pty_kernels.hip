@@ -571,7 +571,7 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
   int i = 0;
   if constexpr (OP == COL_PROP) { i = step; if (i >= r.S - 1) return; }
   if constexpr (OP == COL_PROP_ADJ) { i = r.S - 1 - step; if (i < 1) return; }
-  if constexpr (OP == COL_FINAL) { if (r.S - 1 - step != 0) return; }
+  if constexpr (OP == COL_FINAL) { if (r.S - 1 - step != 0 || r.chain_final) return; }
   if constexpr (PROP) {
     // outside the propagator's support the output columns are zero: a
     // workgroup with no live column has nothing to do (its consumers read zeros)
@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restri
                                                             const float2* __restrict__ ramps, float scale) {
   const ReqDev& r = reqs.r[blockIdx.z];
   const int m = blockIdx.y;
-  if (m >= r.M || !r.gphat) return;
+  if (m >= r.M || !r.gphat || r.chain_final) return;
   constexpr int split = SPLIT, pix = PIX;
   const int px = threadIdx.x % pix, s = threadIdx.x / pix;
   const int p = blockIdx.x * pix + px;
@@ -1069,6 +1069,113 @@ __global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restri
       r.gphat[(size_t)m * N * N + p] = cscale(t, adj_scale(r, scale));
     }
   }
+}
+
+// Final column pass and probe-gradient sums in one, for the requests marked
+// chain_final. Workgroup (column block, mode, chain), chain = request r and
+// residue q < kProbeSplit, walks the request's items q, q + kProbeSplit, ...
+// in order: for each it forms h_hat = DFT_y(tile) / N and the block's
+// position-gradient partials exactly as COL_FINAL does, and adds
+// h_hat conj(R_b) into a sum held in registers. These are k_probe_grad's
+// kProbeSplit interleaved sums, added in the same order, so no h_hat tile is
+// stored and read back: the chain's sum is stored once, into the column block
+// of its first item's tile (that item's work tile is free by then, and no
+// other workgroup touches that block), where k_probe_sum adds the chains.
+template <int N>
+__global__ __launch_bounds__(ColPass<N>::THREADS) void k_col_final_chain(const Item* __restrict__ items,
+                                                                 const ReqTable reqs, float2* __restrict__ ws,
+                                                                 const float2* __restrict__ ramps,
+                                                                 const float2* __restrict__ twg, int step,
+                                                                 float* __restrict__ pos_part,
+                                                                 unsigned long long colmap) {
+  constexpr int L = ColPass<N>::L, E = ColPass<N>::E, CB = ColPass<N>::CB, T = ColPass<N>::THREADS;
+  static_assert(T >= N, "the twiddle table takes one entry per thread");
+  const int cb = (int)((colmap >> (8 * blockIdx.x)) & 0xffu);
+  __shared__ float2 tw[N];
+  __shared__ float2 xch[CB * ColMap<N>::STRIDE];
+  __shared__ float red[2][T / 64];
+  const int rq = blockIdx.z / kProbeSplit, q = blockIdx.z % kProbeSplit, m = blockIdx.y;
+  const ReqDev& r = reqs.r[rq];
+  if (!r.chain_final || m >= r.M || q >= r.n_items || r.S - 1 - step != 0) return;
+  const int t = threadIdx.x;
+  if (t < N) tw[t] = twg[t];
+  __syncthreads();
+  const int c = ColMap<N>::col(), l = ColMap<N>::lane();
+  const int ux = cb * CB + c;
+  float2* sx = xch + c * ColMap<N>::STRIDE;
+  const float2* ph = r.phat + (size_t)m * N * N;
+  const float inv = 1.f / (float)N;
+  const float fx = (float)((ux < (N + 1) / 2) ? ux : ux - N) / (float)N;
+  float2 acc[E];
+#pragma unroll
+  for (int a = 0; a < E; ++a) acc[a] = make_float2(0.f, 0.f);
+  for (int b = r.item0 + q; b < r.item0 + r.n_items; b += kProbeSplit) {
+    const Item it = items[b];
+    if (!it.valid) {
+      // k_probe_grad adds a zero term for a window outside the object
+#pragma unroll
+      for (int a = 0; a < E; ++a) acc[a] = cadd(acc[a], make_float2(0.f, 0.f));
+      continue;
+    }
+    const float2* tile = ws + (size_t)(it.tile0 + m) * N * N;
+    float2 v[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) v[a] = tile[(size_t)(l + L * a) * N + ux];
+    // (the transform's first barrier also orders the previous item's reads of red)
+    line_fft<N, false>(v, l, tw, sx, typename ColMap<N>::Sync{});
+    const float2* ry = ramps + (size_t)b * 2 * N;
+    const float2 rx = ramps[(size_t)b * 2 * N + N + ux];
+    float sy = 0.f, sxx = 0.f;
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      const int uy = l + L * a;
+      v[a] = cscale(v[a], inv);
+      const float2 A = cmul(cmul(ph[(size_t)uy * N + ux], ry[uy]), rx);
+      const float2 z = cjmul(v[a], A);          // conj(h_hat) * A
+      const float fy = (float)((uy < (N + 1) / 2) ? uy : uy - N) / (float)N;
+      sy += fy * z.y;
+      sxx += fx * z.y;
+      const float2 R = cmul(ry[uy], rx);
+      acc[a] = cadd(acc[a], cmul(v[a], cconj(R)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      sy += __shfl_xor(sy, off);
+      sxx += __shfl_xor(sxx, off);
+    }
+    if ((t & 63) == 0) { red[0][t >> 6] = sy; red[1][t >> 6] = sxx; }
+    __syncthreads();
+    if (t == 0) {
+      float t0 = 0.f, t1 = 0.f;
+      for (int w = 0; w < T / 64; ++w) { t0 += red[0][w]; t1 += red[1][w]; }
+      float* dst = pos_part + ((size_t)(it.tile0 + m) * ColPass<N>::NBLK + cb) * 2;
+      dst[0] = t0;
+      dst[1] = t1;
+    }
+  }
+  float2* dst = ws + (size_t)(items[r.item0 + q].tile0 + m) * N * N;
+#pragma unroll
+  for (int a = 0; a < E; ++a) dst[(size_t)(l + L * a) * N + ux] = acc[a];
+}
+
+// Probe-spectrum gradient of the chain_final requests: the kProbeSplit chain
+// sums (zero for a residue with no item) added in residue order, as k_probe_grad
+// adds its interleaved sums, times the adjoint scale.
+template <int N>
+__global__ __launch_bounds__(256) void k_probe_sum(const Item* __restrict__ items, const ReqTable reqs,
+                                                   const float2* __restrict__ ws, float scale) {
+  const ReqDev& r = reqs.r[blockIdx.z];
+  const int m = blockIdx.y;
+  if (!r.chain_final || m >= r.M || !r.gphat) return;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  float2 t = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < kProbeSplit; ++q) {
+    const float2 part = q < r.n_items ? ws[(size_t)(items[r.item0 + q].tile0 + m) * N * N + p]
+                                      : make_float2(0.f, 0.f);
+    t = q == 0 ? part : cadd(t, part);
+  }
+  r.gphat[(size_t)m * N * N + p] = cscale(t, adj_scale(r, scale));
 }
 
 // Per item: dL/dX = 2 pi * scale * sum over modes and blocks of the partials;
@@ -1231,7 +1338,15 @@ struct Launch {
       case COL_SHIFT: hipLaunchKernelGGL((k_col<N, COL_SHIFT>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map, L.seg_out); break;
       case COL_PROP: hipLaunchKernelGGL((k_col<N, COL_PROP>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, ck_out, map, L.seg_out); break;
       case COL_PROP_ADJ: hipLaunchKernelGGL((k_col<N, COL_PROP_ADJ>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map, L.seg_out); break;
-      default: hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map, L.seg_out); break;
+      default: {
+        bool any_chain = false, any_plain = false;
+        for (int q = 0; q < L.n_reqs; ++q) (L.reqs.r[q].chain_final ? any_chain : any_plain) = true;
+        if (any_plain)
+          hipLaunchKernelGGL((k_col<N, COL_FINAL>), g, dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, L.item_off, nullptr, map, L.seg_out);
+        if (any_chain)
+          hipLaunchKernelGGL((k_col_final_chain<N>), dim3(nb, L.max_modes, L.n_reqs * kProbeSplit), dim3(ColPass<N>::THREADS), 0, L.stream, L.items, L.reqs, L.ws, L.ramps, L.tw, step, L.pos_part, map);
+        break;
+      }
     }
   }
   static void obj_gather(const LaunchCtx& L, int step, int max_h, int max_w) {
@@ -1254,6 +1369,12 @@ struct Launch {
     // many (pixel block, mode) pairs: 256 pixels per workgroup, every thread
     // walks all items; few: 64 pixels per workgroup and the items split 16 ways
     static_assert((N * N) % 256 == 0, "pixel blocks must tile the probe");
+    bool any_chain = false, any_plain = false;
+    for (int q = 0; q < L.n_reqs; ++q) (L.reqs.r[q].chain_final ? any_chain : any_plain) = true;
+    if (any_chain)
+      hipLaunchKernelGGL((k_probe_sum<N>), dim3(N * N / 256, L.max_modes, L.n_reqs), dim3(256), 0, L.stream,
+                         L.items, L.reqs, L.ws, scale);
+    if (!any_plain) return;
     const bool small = (N * N / 256) * L.max_modes * L.n_reqs < 1024;
     if (small)
       hipLaunchKernelGGL((k_probe_grad<N, 64, kProbeSplit>), dim3(N * N / 64, L.max_modes, L.n_reqs), dim3(1024), 0, L.stream,
@@ -1303,6 +1424,16 @@ void launch_obj_gather(const LaunchCtx& L, int N, int step, int max_h, int max_w
 }
 void launch_far_loss(const LaunchCtx& L, int N, int step, bool grad) { PTY_DISPATCH(N, far_loss(L, step, grad)); }
 void launch_probe_grad(const LaunchCtx& L, int N, float scale) { PTY_DISPATCH(N, probe_grad(L, scale)); }
+void set_chain_final(LaunchCtx& L, int N, bool unchunked) {
+  // Chains where they measured faster: N = 256 (16 values per lane; at 24 per
+  // lane, N = 192, the chain kernel runs one wave per SIMD and loses) with
+  // enough (column block, mode, chain) workgroups to cover the CUs (one
+  // 512-thread workgroup per CU at its register count). Decided per request,
+  // so a request takes the same path alone or in a shared launch.
+  for (int q = 0; q < L.n_reqs; ++q)
+    L.reqs.r[q].chain_final =
+        (unchunked && N == 256 && col_blocks(N) * L.reqs.r[q].M * kProbeSplit >= 512) ? 1 : 0;
+}
 void launch_plain2d(int N, hipStream_t s, const float2* tw, const float2* src, float2* dst, int n_tiles,
                     bool inverse, float scale, bool accumulate) {
   PTY_DISPATCH(N, plain2d(s, tw, src, dst, n_tiles, inverse, scale, accumulate));

@@ -1127,3 +1127,54 @@ def test_conventional_engines_under_resident_strategy_and_chunks(engine):
     dP = _np(st.probe).astype(np.complex128) - P0
     assert rel_l2(dO, ref["object"] - O0) < TOL_G
     assert rel_l2(dP, ref["probe"] - P0) < TOL_G
+
+
+def test_final_pass_chains_match_the_oracle_and_the_stored_path():
+    """N = 256 with 4 modes: the final column pass runs as chains that keep the
+    probe-gradient sums in registers. Loss and gradients against the oracle;
+    against a chunked call, which stores h_hat and sums it in k_probe_grad in
+    the same order, the position gradient is bit for bit equal and the probe
+    gradient equal to float rounding (the two kernels may fuse the products of
+    a term into multiply-adds differently); a window outside the object inside
+    a chain adds a zero term on both paths."""
+    wl = synth.make_small(N=256, M=4, S=2, scan=6, step=4, seed=90, loss="poisson", eps=0.8, amp_noise=0.2)
+    c = Case(wl)
+    assert len(c.batch) >= 2 * 16
+    ref = c.oracle_grad()
+    d = c.device()
+    outs = {}
+    for chunk in (0, 7):
+        prob = c.problem()
+        prob.set_reduction("ordered")
+        prob.set_chunk(chunk)
+        outs[chunk] = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+        prob.check()
+        prob.close()
+    loss, gO, gP, gX = outs[0]
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    for name, got, want in (("object", gO, ref["g_object"]), ("probe", gP, ref["g_probe"]),
+                            ("positions", gX, ref["g_pos"])):
+        e2, einf = rel_l2(_np(got), want), max_rel(_np(got), want)
+        print(f"{name}: rel L2 {e2:.2e}, max {einf:.2e}")
+        assert e2 < TOL_G and einf < TOL_G, (name, e2, einf)
+    assert max_rel(_np(outs[0][2]), _np(outs[7][2])) < 1e-6 and torch.equal(outs[0][3], outs[7][3])
+    # one window far outside the object, in the middle of a chain
+    pos = d["pos"].clone()
+    pos[20] = torch.tensor([-50.0, -50.0], device="cuda")
+    got = {}
+    for chunk in (0, 7):
+        prob = c.problem()
+        prob.set_reduction("ordered")
+        prob.set_chunk(chunk)
+        got[chunk] = prob.loss_and_grad(d["probe"], d["obj"], pos, d["pats"], d["batch"])
+        with pytest.raises(Exception, match="window left the object"):
+            prob.check()
+        prob.close()
+    assert max_rel(_np(got[0][2]), _np(got[7][2])) < 1e-6 and torch.equal(got[0][3], got[7][3])
+    # the excluded window contributes nothing: the same gradients as without it
+    keep = torch.tensor([j for j in c.batch if j != 20], dtype=torch.int32, device="cuda")
+    prob = c.problem()
+    prob.set_reduction("ordered")
+    _, _, gP_keep, _ = prob.loss_and_grad(d["probe"], d["obj"], pos, d["pats"], keep)
+    prob.check()
+    assert max_rel(_np(got[0][2]), _np(gP_keep)) < 1e-6
