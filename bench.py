@@ -101,7 +101,7 @@ def live_fraction(N, bandlimit, S):
 
 
 def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spectral=False, live=1.0,
-                            ordered=False):
+                            ordered=False, chain=False):
     """Algorithmic HBM bytes one launch of a kernel class must move at an
     interior slice (complex64 tile T = 8 N^2 bytes, per launch over B
     positions and M modes; a checkpoint is T, or T/2 when stored as half
@@ -111,7 +111,10 @@ def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spec
     moves; LSQML adds the read-modify-write of a float illumination sum, T per
     position; with the ordered reduction the adjoint row pass stores each
     position's object-gradient contribution, T, instead of adding it into the
-    gradient, 2T)."""
+    gradient, 2T); with chain (the final pass as kProbeSplit = 16 chains that
+    keep the probe-gradient sums, N = 256 with 4 or more modes, unchunked) the
+    final pass reads every tile and writes 16 partial tiles per mode, which the
+    probe-gradient sum reads back."""
     T = 8 * N * N
     C = T // 2 if ck_half else T
     Tl = T * live
@@ -126,10 +129,10 @@ def kernel_bytes_per_launch(name, N, M, B, S, ck_half=False, engine="adam", spec
         return B * (3 * M * T + T // 2)
     if name == "col_shift":    # write every tile (the probe spectrum stays in cache)
         return B * M * T
-    if name == "col_final":    # read + write every tile
-        return B * 2 * M * T
-    if name == "probe_grad":   # read every tile
-        return B * M * T
+    if name == "col_final":    # read + write every tile, or read every tile and write the chain sums
+        return B * M * T + 16 * M * T if chain else B * 2 * M * T
+    if name == "probe_grad":   # read every tile, or the chain sums
+        return 16 * M * T if chain else B * M * T
     return 0
 
 
@@ -406,8 +409,9 @@ def main():
         n_launch = B if args.chunk <= 0 else min(args.chunk, B)   # positions one launch processes
         alg_flops = method_flops_per_launch(dom, N, M, n_launch, S)
         alg_bytes = method_bytes_per_launch(dom, N, n_launch, S)
+        chain = N == 256 and M >= 4 and args.chunk <= 0
         design_bytes = kernel_bytes_per_launch(dom, N, M, n_launch, S, prob.checkpoint_half, args.engine, spectral,
-                                               live, args.reduction == "ordered")
+                                               live, args.reduction == "ordered", chain)
         tfl = alg_flops / avg_s / 1e12
         gbs = alg_bytes / avg_s / 1e9
         if alg_flops / (FP32_PEAK_TFLOPS * 1e12) >= alg_bytes / (HBM_PEAK_GBS * 1e9):
