@@ -100,13 +100,20 @@ __device__ __forceinline__ bool col_live(const ReqDev& r, int x) {
 // the others. A masked slot loads the lane's slot-0 element of the same row
 // instead (a line the wave reads anyway), so the loads are unconditional: no
 // per-slot branch, and the compiler may issue them together.
-template <int N>
+// (NT: non-temporal loads, for rows read once.)
+template <int N, bool NT = false>
 __device__ __forceinline__ void load_row_masked(float2 (&v)[Cfg<N>::E], const float2* row, int l, unsigned mask) {
   constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
 #pragma unroll
   for (int a = 0; a < E; ++a) {
     const bool on = (mask >> a) & 1u;
-    const float2 t = row[on ? l + L * a : l];
+    float2 t;
+    if constexpr (NT) {
+      const float2* p = row + (on ? l + L * a : l);
+      t = make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+    } else {
+      t = row[on ? l + L * a : l];
+    }
     v[a] = on ? t : make_float2(0.f, 0.f);
   }
 }
@@ -128,7 +135,8 @@ __device__ __forceinline__ unsigned wave_slots(unsigned mask) {
 // (no per-slot address registers), and the lanes whose slot is dead take zero.
 // Dead columns of the tiles are never written, so what a dead lane reads is
 // discarded, never used.
-template <int N>
+// (NT: non-temporal loads, for rows read once.)
+template <int N, bool NT = false>
 __device__ __forceinline__ void load_row_slots(float2 (&v)[Cfg<N>::E], const float2* row, int l, unsigned mask,
                                                unsigned any) {
   constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
@@ -136,7 +144,10 @@ __device__ __forceinline__ void load_row_slots(float2 (&v)[Cfg<N>::E], const flo
 #pragma unroll
   for (int a = 0; a < E; ++a) {
     v[a] = make_float2(0.f, 0.f);
-    if ((any >> a) & 1u) v[a] = p[L * a];
+    if ((any >> a) & 1u) {
+      if constexpr (NT) v[a] = make_float2(__builtin_nontemporal_load(&p[L * a].x), __builtin_nontemporal_load(&p[L * a].y));
+      else v[a] = p[L * a];
+    }
   }
   const unsigned part = any & ~mask;
 #pragma unroll
@@ -289,7 +300,11 @@ __global__ __launch_bounds__(kThreads) void k_row_fwd(const Item* __restrict__ i
           in = static_cast<const float2*>(store.seg) +
                (((size_t)(it.tile0 + m) * store.seg_len + store.seg_slot) * N + y) * N;
       }
-      load_row_slots<N>(v, in, l, lmask, any_l);
+      // a checkpoint or segment row spectrum is not read again before the
+      // adjoint: loaded non-temporally, so that it does not displace the
+      // tiles the next column pass reads from the caches
+      if (in != trow) load_row_slots<N, true>(v, in, l, lmask, any_l);
+      else load_row_slots<N>(v, in, l, lmask, any_l);
       line_fft<N, true>(v, l, tw, sx, WaveSync{});
     }
     if (store.mode == 1 && (i % r.ck_every) == 0) {
@@ -431,7 +446,9 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     float2 v[E];
     float2 ps[SPEC ? E : 1];
     load_row_masked<N>(v, trow, l, gmask);
-    if constexpr (SPEC) load_row_masked<N>(ps, reinterpret_cast<const float2*>(prow), l, cmask);
+    // the checkpoint row is read once: non-temporal, so that the gradient
+    // tiles the adjoint column pass reads next stay in the caches
+    if constexpr (SPEC) load_row_masked<N, true>(ps, reinterpret_cast<const float2*>(prow), l, cmask);
     flush();
     line_fft<N, true>(v, l, tw, sx, WaveSync{});
     if constexpr (SPEC) line_fft<N, true>(ps, l, tw, sx, WaveSync{});
