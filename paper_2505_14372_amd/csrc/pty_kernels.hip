@@ -96,11 +96,21 @@ __device__ __forceinline__ bool col_live(const ReqDev& r, int x) {
   return r.live[x] != 0;
 }
 
+// Non-temporal row loads, for a row that is read once and not rewritten in
+// place, are used only where one load instruction covers whole 128-byte lines
+// of the row (L lanes x 8 bytes, L = 16): with L = 8 an instruction reads half
+// of each line and the next slot the other half, which a non-temporal load
+// does not keep, so every line would be fetched twice.
+template <int N, bool NT>
+struct RowNT {
+  static constexpr bool on = NT && Cfg<N>::L * sizeof(float2) >= 128;
+};
+
 // Row-pass load of x[l + L a] for the register slots a set in `mask`, zero in
 // the others. A masked slot loads the lane's slot-0 element of the same row
 // instead (a line the wave reads anyway), so the loads are unconditional: no
 // per-slot branch, and the compiler may issue them together.
-// (NT: non-temporal loads, for rows read once.)
+// (NT: non-temporal loads, for rows read once; see RowNT.)
 template <int N, bool NT = false>
 __device__ __forceinline__ void load_row_masked(float2 (&v)[Cfg<N>::E], const float2* row, int l, unsigned mask) {
   constexpr int L = Cfg<N>::L, E = Cfg<N>::E;
@@ -108,7 +118,7 @@ __device__ __forceinline__ void load_row_masked(float2 (&v)[Cfg<N>::E], const fl
   for (int a = 0; a < E; ++a) {
     const bool on = (mask >> a) & 1u;
     float2 t;
-    if constexpr (NT) {
+    if constexpr (RowNT<N, NT>::on) {
       const float2* p = row + (on ? l + L * a : l);
       t = make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
     } else {
@@ -135,7 +145,7 @@ __device__ __forceinline__ unsigned wave_slots(unsigned mask) {
 // (no per-slot address registers), and the lanes whose slot is dead take zero.
 // Dead columns of the tiles are never written, so what a dead lane reads is
 // discarded, never used.
-// (NT: non-temporal loads, for rows read once.)
+// (NT: non-temporal loads, for rows read once; see RowNT.)
 template <int N, bool NT = false>
 __device__ __forceinline__ void load_row_slots(float2 (&v)[Cfg<N>::E], const float2* row, int l, unsigned mask,
                                                unsigned any) {
@@ -145,7 +155,8 @@ __device__ __forceinline__ void load_row_slots(float2 (&v)[Cfg<N>::E], const flo
   for (int a = 0; a < E; ++a) {
     v[a] = make_float2(0.f, 0.f);
     if ((any >> a) & 1u) {
-      if constexpr (NT) v[a] = make_float2(__builtin_nontemporal_load(&p[L * a].x), __builtin_nontemporal_load(&p[L * a].y));
+      if constexpr (RowNT<N, NT>::on)
+        v[a] = make_float2(__builtin_nontemporal_load(&p[L * a].x), __builtin_nontemporal_load(&p[L * a].y));
       else v[a] = p[L * a];
     }
   }
