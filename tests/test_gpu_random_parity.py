@@ -121,3 +121,54 @@ def test_random_configuration_matches_oracle(seed):
         bar = max(TOL_G, 4.0 * sens.get(key, 0.0))
         print(f"  {name}: rel L2 {e2:.2e}, max {einf:.2e}" + (f" (bar {bar:.1e})" if bar > TOL_G else ""))
         assert e2 < bar and einf < bar, (name, e2, einf, bar)
+
+
+def _draw_chain(seed):
+    """A 256 x 256 window with 4-6 modes, launched unchunked: the probe
+    gradient then runs as interleaved chains over the group's items with
+    register-held sums (the final column pass's chained form); the rest of the
+    configuration is drawn as in the sweep above."""
+    rng = np.random.default_rng(3000 + seed)
+    N, M, S = 256, int(rng.integers(4, 7)), int(rng.integers(1, 4))
+    loss = str(rng.choice(["amplitude", "anscombe", "poisson", "gaussian"]))
+    eps = float(rng.choice([0.0, 0.3, 0.8])) if loss != "gaussian" else 0.0
+    bandlimit = float(rng.choice([2.0 / 3.0, 0.5, 0.0]))
+    # more than 16 items, so that every chain sums several of them
+    scan, step = int(rng.integers(5, 7)), int(rng.integers(3, 6))
+    wl = synth.make_small(N=N, M=M, S=S, scan=scan, step=step, seed=4000 + seed, loss=loss, eps=eps,
+                          phi_max=float(rng.uniform(0.05, 0.3)), amp_noise=float(rng.choice([0.0, 0.2])),
+                          dose=1e5, bandlimit=bandlimit)
+    if S > 1:
+        wl.dz = [float(x) for x in rng.uniform(0.5, 4.0, S - 1)]
+    if rng.random() < 0.5:
+        wl.tilt = (float(rng.uniform(-4e-3, 4e-3)), float(rng.uniform(-4e-3, 4e-3)))
+    J = wl.positions.shape[0]
+    batch = rng.permutation(J)[: int(rng.integers(17, J + 1))].astype(np.int32)
+    reduction = str(rng.choice(["atomic", "ordered"]))
+    sched = dict(checkpoint_every=int(rng.choice([1, 1, 2])), checkpoint_half=bool(rng.random() < 0.25))
+    return Case(wl, batch=batch), reduction, sched
+
+
+# PTY_RANDOM_CHAIN widens the sweep (default 3 cases)
+@pytest.mark.parametrize("seed", range(int(os.environ.get("PTY_RANDOM_CHAIN", "3"))))
+def test_random_chained_final_pass_matches_oracle(seed):
+    c, reduction, sched = _draw_chain(seed)
+    print(f"seed {seed}: N={c.N} M={c.M} S={c.S} H={c.H} W={c.W} B={len(c.batch)} loss={c.geom.loss} "
+          f"eps={c.geom.eps} bandlimit={c.geom.bandlimit} tilt={c.tilt} {reduction} {sched}", flush=True)
+    ref = c.oracle_grad()
+    d = c.device()
+    prob = c.problem(checkpoint_every=sched["checkpoint_every"], checkpoint_half=sched["checkpoint_half"])
+    prob.set_reduction(reduction)
+    prob.set_chunk(0)
+    loss, gO, gP, gX = prob.loss_and_grad(d["probe"], d["obj"], d["pos"], d["pats"], d["batch"])
+    prob.check()
+    assert abs(loss.item() - ref["loss"]) < TOL_I * abs(ref["loss"])
+    singular = c.geom.eps == 0.0 and c.geom.loss in ("amplitude", "anscombe", "poisson")
+    sens = _float_sensitivity(c, ref) if singular else {}
+    for name, key, got in (("object", "g_object", gO), ("probe", "g_probe", gP), ("positions", "g_pos", gX)):
+        g = got.detach().cpu().numpy()
+        want = ref[key]
+        e2, einf = rel_l2(g, want), max_rel(g, want)
+        bar = max(TOL_G, 4.0 * sens.get(key, 0.0))
+        print(f"  {name}: rel L2 {e2:.2e}, max {einf:.2e}" + (f" (bar {bar:.1e})" if bar > TOL_G else ""))
+        assert e2 < bar and einf < bar, (name, e2, einf, bar)
