@@ -96,14 +96,21 @@ __device__ __forceinline__ bool col_live(const ReqDev& r, int x) {
   return r.live[x] != 0;
 }
 
-// Non-temporal row loads, for a row that is read once and not rewritten in
-// place, are used only where one load instruction covers whole 128-byte lines
-// of the row (L lanes x 8 bytes, L = 16): with L = 8 an instruction reads half
-// of each line and the next slot the other half, which a non-temporal load
-// does not keep, so every line would be fetched twice.
+
+// Does one row-pass slot (L lanes x 8 bytes of a row) cover whole 128-byte
+// lines (L = 16, N = 256)? Only then are read-once rows loaded non-temporally:
+// with L = 8 an instruction reads half of each line and the next slot the
+// other half, which a non-temporal load does not keep, so every line would be
+// fetched twice. The store forms that write whole lines at the band edges
+// (whole slots in the adjoint row pass, whole column blocks in the
+// propagation passes) are used at that size too.
+template <int N>
+struct WholeLines {
+  static constexpr bool on = Cfg<N>::L * sizeof(float2) >= 128;
+};
 template <int N, bool NT>
 struct RowNT {
-  static constexpr bool on = NT && Cfg<N>::L * sizeof(float2) >= 128;
+  static constexpr bool on = NT && WholeLines<N>::on;
 };
 
 // Row-pass load of x[l + L a] for the register slots a set in `mask`, zero in
@@ -410,8 +417,13 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   const unsigned gmask = (r.live && i < r.S - 1) ? live : ~0u;
   const unsigned cmask = (r.live && i >= 1) ? live : ~0u;
   // the output of slices i >= 1 feeds only the adjoint propagation column
-  // pass, which reads the live columns alone (slice 0 feeds the final one)
+  // pass, which reads the live columns alone (slice 0 feeds the final one).
+  // Where a slot is a whole line (N = 256) every lane of a slot with a live
+  // column stores, as in the forward row pass: whole-line writes beat partial
+  // ones at the band edges (1.070 -> 1.046 ms per launch at 8 modes, 512
+  // positions); at 8 lanes per line only the live lanes store.
   const unsigned omask = cmask;
+  const unsigned any_o = WholeLines<N>::on ? wave_slots<N>(omask) : omask;
   float2 acc[E];
   const size_t orow = ((size_t)i * r.H + it.ny + y) * r.W + it.nx;
   // ePIE: object step divided by max sum_m |psi_i|^2, wave step by max |O_i|^2
@@ -444,7 +456,7 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
     if (!out_row) return;
 #pragma unroll
     for (int a = 0; a < E; ++a)
-      if ((omask >> a) & 1u) out_row[l + L * a] = hout[a];
+      if ((any_o >> a) & 1u) out_row[l + L * a] = hout[a];
     out_row = nullptr;
   };
   for (int m = 0; m < r.M; ++m) {
@@ -732,8 +744,15 @@ __global__ __launch_bounds__(ColPass<N>::THREADS) void k_col(const Item* __restr
     }
   }
   const TileBuf out(dst, N * N * 8);
+  // A dead column of a live block holds zero (it was read as zero and stays
+  // zero through the transforms). At N = 256 the whole block is stored, so
+  // that the lines at the band edges are written whole (forward and adjoint
+  // propagation passes 0.61 -> 0.57 ms per launch at 8 modes and 512
+  // positions); at N = 128 and 192 that measured slower (more of each live
+  // block is dead there), and only the live columns are stored.
+  const bool st_col = (PROP && WholeLines<N>::on) ? true : live_col;
 #pragma unroll
-  for (int a = 0; a < E; ++a) out.st(tile_off<N>(live_col, l + L * a, ux), v[a]);
+  for (int a = 0; a < E; ++a) out.st(tile_off<N>(st_col, l + L * a, ux), v[a]);
 }
 
 // Plain column DFT of M probe-sized tiles (in place): tile = scale * DFT_y(tile).
