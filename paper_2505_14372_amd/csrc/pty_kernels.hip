@@ -150,8 +150,9 @@ __device__ __forceinline__ unsigned wave_slots(unsigned mask) {
 // wave needs is skipped by a scalar branch and costs no request; the other
 // slots are read by every lane from one base address with immediate offsets
 // (no per-slot address registers), and the lanes whose slot is dead take zero.
-// Dead columns of the tiles are never written, so what a dead lane reads is
-// discarded, never used.
+// A dead column of a tile holds whatever was last written there (stale data,
+// or a value a pass stored only to write its line whole), so what a dead lane
+// reads is discarded, never used.
 // (NT: non-temporal loads, for rows read once; see RowNT.)
 template <int N, bool NT = false>
 __device__ __forceinline__ void load_row_slots(float2 (&v)[Cfg<N>::E], const float2* row, int l, unsigned mask,
@@ -407,7 +408,9 @@ __global__ __launch_bounds__(kThreads) void k_row_adj(const Item* __restrict__ i
   const CT* ck = static_cast<const CT*>(ck_);
   // columns outside the propagator's support: zero in g for i < S - 1 (it came
   // through an adjoint propagation column pass) and in a spectral checkpoint
-  // for i >= 1 (written by a forward one); those columns were never written
+  // for i >= 1 (written by a forward one); in memory they hold zeros or stale
+  // data (a dead column is written only when its line holds live ones), so
+  // they are masked rather than read
   unsigned live = ~0u;
   if (r.live) {
     live = 0u;

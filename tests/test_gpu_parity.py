@@ -181,10 +181,12 @@ def test_edge_positions_match_oracle(N):
 
 @pytest.mark.parametrize("N", [64, 256])
 def test_stale_workspace_is_never_read(N):
-    """Columns outside the propagator's support are neither written nor read:
-    after a call whose detector weights are NaN everywhere (every work tile
-    and checkpoint full of NaN), the next call on the same context still
-    matches the oracle, so no consumer picked up a column it was not given."""
+    """Columns outside the propagator's support are never read (at N = 256 the
+    passes write the dead columns of the 128-byte lines that also hold live
+    ones, and no consumer uses them): after a call whose detector weights are
+    NaN everywhere (every work tile and checkpoint full of NaN), the next call
+    on the same context still matches the oracle, so no consumer picked up a
+    column it was not given."""
     from paper_2505_14372_amd._lib import PTY_ENONFINITE, PtyError
     c = Case(synth.make_small(N=N, M=2, S=3, scan=2, step=6, seed=70 + N, loss="gaussian", amp_noise=0.2))
     ref = c.oracle_grad()
