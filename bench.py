@@ -93,7 +93,8 @@ def parse():
 def live_fraction(N, bandlimit, S):
     """Fraction of row-spectrum columns u_x that the circular band limit
     (fraction of Nyquist) keeps; the others are zero after a propagation and
-    are neither written nor read."""
+    are never read (at N = 256 the passes write those that share a 128-byte
+    line with live ones)."""
     if S < 2 or bandlimit <= 0:
         return 1.0
     k = np.fft.fftfreq(N) * N
@@ -161,6 +162,26 @@ def method_flops_per_launch(name, N, M, B, S=1):
     n_fft = {"row_fwd": 2, "row_adj": 2, "col_prop": 2, "col_prop_adj": 2, "far_loss": 2,
              "col_shift": 1, "col_final": 1, "res_fwd": 4 * S - 2, "res_adj": 4 * S - 2}.get(name, 0)
     return n_fft * lines * per_line
+
+
+def step_roofline(N, M, S, t_meas_pos):
+    """Roofline of the method's own work per position (the measurement plan's
+    counts): flops = 4 S M 2D FFTs of 5 N^2 log2 N^2 each; bytes = the pattern
+    plus the object patch read in the forward and again in the adjoint plus the
+    object-gradient read-modify-write. T_roof = max(bytes / HBM peak, flops /
+    FP32 peak); the step's fraction is T_roof / T_measured (seconds per
+    position)."""
+    flop_pos = 4 * S * M * 5 * N * N * np.log2(N * N)
+    bytes_pos = N * N * 4 + 4 * S * N * N * 8
+    t_alu, t_hbm = flop_pos / (FP32_PEAK_TFLOPS * 1e12), bytes_pos / (HBM_PEAK_GBS * 1e9)
+    t_roof_pos = max(t_alu, t_hbm)
+    return {"bound": "alu" if t_alu >= t_hbm else "hbm",
+            "flops_per_position": flop_pos, "bytes_per_position": bytes_pos,
+            "t_roof_us_per_position": round(t_roof_pos * 1e6, 3),
+            "t_measured_us_per_position": round(t_meas_pos * 1e6, 3),
+            "frac": round(t_roof_pos / t_meas_pos, 4),
+            "achieved_tflops": round(flop_pos / t_meas_pos / 1e12, 2),
+            "achieved_alg_GBps": round(bytes_pos / t_meas_pos / 1e9, 1)}
 
 
 def method_bytes_per_launch(name, N, B, S=1):
@@ -376,22 +397,7 @@ def main():
         prob.check()
         print(f"[bench] profiled pass: {n_prof} steps, {prof_ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # Roofline of the method's own work (the per-position counts of the
-    # measurement plan): flops = 4 S M 2D FFTs of 5 N^2 log2 N^2 each, bytes =
-    # the pattern plus the object patch read in the forward and again in the
-    # adjoint plus the object-gradient read-modify-write. T_roof = max(bytes /
-    # HBM peak, flops / FP32 peak); the step's fraction is T_roof / T_measured.
-    flop_pos = 4 * S * M * 5 * N * N * np.log2(N * N)
-    bytes_pos = N * N * 4 + 4 * S * N * N * 8
-    t_roof_pos = max(bytes_pos / (HBM_PEAK_GBS * 1e9), flop_pos / (FP32_PEAK_TFLOPS * 1e12))
-    t_meas_pos = ms_per_step / 1000.0 / B
-    step_roof = {"bound": "alu" if flop_pos / (FP32_PEAK_TFLOPS * 1e12) >= bytes_pos / (HBM_PEAK_GBS * 1e9) else "hbm",
-                 "flops_per_position": flop_pos, "bytes_per_position": bytes_pos,
-                 "t_roof_us_per_position": round(t_roof_pos * 1e6, 3),
-                 "t_measured_us_per_position": round(t_meas_pos * 1e6, 3),
-                 "frac": round(t_roof_pos / t_meas_pos, 4),
-                 "achieved_tflops": round(flop_pos * value / 1e12, 2),
-                 "achieved_alg_GBps": round(bytes_pos * value / 1e9, 1)}
+    step_roof = step_roofline(N, M, S, ms_per_step / 1000.0 / B)
     roof = None
     kernels = {}
     if prof:
@@ -451,7 +457,7 @@ def main():
         "epoch_s_p50": round(float(np.percentile(ep_ms, 50)) / 1000.0, 4) if n_ep else None,
         "positions_per_s_epoch_p50": round(n_groups * B / (float(np.percentile(ep_ms, 50)) / 1000.0), 1) if n_ep else None,
         "positions_per_s_epoch_p99": round(n_groups * B / (float(np.percentile(ep_ms, 99)) / 1000.0), 1) if n_ep else None,
-        "fft_tflops_per_s": round(flop_pos * value / 1e12, 2),
+        "fft_tflops_per_s": round(step_roof["flops_per_position"] * value / 1e12, 2),
         "roofline": roof, "step_roofline": step_roof, "kernels": kernels,
         "profiled_pass_ms_per_step": round(prof_ms_per_step, 3) if prof_ms_per_step else None,
     }
