@@ -96,7 +96,6 @@ __device__ __forceinline__ bool col_live(const ReqDev& r, int x) {
   return r.live[x] != 0;
 }
 
-
 // Does one row-pass slot (L lanes x 8 bytes of a row) cover whole 128-byte
 // lines (L = 16, N = 256)? Only then are read-once rows loaded non-temporally:
 // with L = 8 an instruction reads half of each line and the next slot the
