@@ -937,26 +937,32 @@ __global__ void k_loss_reduce(const ReqTable reqs, const float* __restrict__ los
   if (threadIdx.x == 0 && r.loss_out) *r.loss_out = red[0];
 }
 
-// Probe-spectrum gradient per request: gphat_m(u) = scale * sum_b h_hat_{b,m}(u) conj(R_b(u)).
-// A workgroup of PIX x SPLIT threads covers PIX consecutive pixels; thread
-// row s sums the items b = item0 + s, s + SPLIT, ... and the rows are added
-// in a fixed order (deterministic for a given launch shape).
 // Ordered object-gradient reduction for slice i = S - 1 - step of every
-// request: one workgroup per kGatherTY x 64 tile of the object gradient sums
-// the stored contributions of the positions whose windows cover the tile and
-// adds the sum to the gradient. Each tile has one owner (no atomics) and the
-// summation order is fixed by the batch order alone: the covering positions
-// are listed in batch order (a block-wide ordered compaction over the
-// request's items, 256 at a time), wave w sums the w-th contiguous quarter of
-// each list in list order (loads for four positions issued ahead of their
-// additions), and the four wave sums are added in wave order at the end.
-// With WS the stored illumination sums of LSQML (wscr) are added the same way into r.wsum.
-constexpr int kGatherTY = 8, kGatherW = 4;
+// request: one workgroup per TY x 64 tile of the object gradient sums the
+// stored contributions of the positions whose windows cover the tile and adds
+// the sum to the gradient. Each tile has one owner (no atomics) and the
+// summation order is fixed by the batch order and the tile shape alone: the
+// covering positions are listed in batch order (a block-wide ordered
+// compaction over the request's items, 64 W at a time), wave w sums the w-th
+// contiguous part of each list in list order (loads for four positions issued
+// ahead of their additions), and the W wave sums are added in wave order at
+// the end. With WS the stored illumination sums of LSQML (wscr) are added the
+// same way into r.wsum.
+// Tile shape per window size (the same for a request alone or in a group, so
+// both give the same bits): 8 rows and 4 waves; at N = 128, where a scan's
+// object is small for its many positions (a 384 x 384 slice under 1024 windows
+// gives 288 tiles of 8 rows for 256 CUs, each summing about 120 positions),
+// 2 rows and 8 waves: four times the workgroups and twice the waves per list
+// (0.071 -> 0.044 ms per slice, 138.8k -> 142.9k positions/s). Other shapes
+// measured no better at 192 and slower at 256.
+template <int N> struct Gather { static constexpr int TY = 8, W = 4; };
+template <> struct Gather<128> { static constexpr int TY = 2, W = 8; };
 template <int N, bool WS>
-__global__ __launch_bounds__(64 * kGatherW) void k_obj_gather(const Item* __restrict__ items, const ReqTable reqs,
+__global__ __launch_bounds__(64 * Gather<N>::W) void k_obj_gather(const Item* __restrict__ items, const ReqTable reqs,
                                                               const float2* __restrict__ cscr,
                                                               const float* __restrict__ wscr, int step,
                                                               int item_off, int n_items) {
+  constexpr int kGatherTY = Gather<N>::TY, kGatherW = Gather<N>::W;
   const ReqDev& r = reqs.r[blockIdx.z];
   const int i = r.S - 1 - step;
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kGatherTY;
@@ -1071,6 +1077,10 @@ __global__ __launch_bounds__(64 * kGatherW) void k_obj_gather(const Item* __rest
 }
 
 constexpr int kProbeSplit = 16;
+// Probe-spectrum gradient per request: gphat_m(u) = scale * sum_b h_hat_{b,m}(u) conj(R_b(u)).
+// A workgroup of PIX x SPLIT threads covers PIX consecutive pixels; thread
+// row s sums the items b = item0 + s, s + SPLIT, ... and the rows are added
+// in a fixed order (deterministic for a given launch shape).
 template <int N, int PIX, int SPLIT>
 __global__ __launch_bounds__(PIX * SPLIT) void k_probe_grad(const Item* __restrict__ items, const ReqTable reqs,
                                                             const float2* __restrict__ ws,
@@ -1399,12 +1409,13 @@ struct Launch {
     }
   }
   static void obj_gather(const LaunchCtx& L, int step, int max_h, int max_w) {
-    dim3 g((max_w + 63) / 64, (max_h + kGatherTY - 1) / kGatherTY, L.n_reqs);
+    constexpr int TY = Gather<N>::TY, W = Gather<N>::W;
+    dim3 g((max_w + 63) / 64, (max_h + TY - 1) / TY, L.n_reqs);
     if (L.wsum && L.wscr)
-      hipLaunchKernelGGL((k_obj_gather<N, true>), g, dim3(64 * kGatherW), 0, L.stream, L.items, L.reqs, L.cscr,
+      hipLaunchKernelGGL((k_obj_gather<N, true>), g, dim3(64 * W), 0, L.stream, L.items, L.reqs, L.cscr,
                          L.wscr, step, L.item_off, L.n_items);
     else
-      hipLaunchKernelGGL((k_obj_gather<N, false>), g, dim3(64 * kGatherW), 0, L.stream, L.items, L.reqs, L.cscr,
+      hipLaunchKernelGGL((k_obj_gather<N, false>), g, dim3(64 * W), 0, L.stream, L.items, L.reqs, L.cscr,
                          nullptr, step, L.item_off, L.n_items);
   }
   static void far_loss(const LaunchCtx& L, int step, bool grad) {
